@@ -1,0 +1,206 @@
+/*
+ * hough_tf.h -- C ABI of the MI355X (gfx950) Hough track finder.
+ *
+ * The library finds straight lines in the phi-z projection of silicon-strip
+ * hits (paper: Sec. 4, Eq. (4), rho = phi cos(theta) + z sin(theta)) and
+ * returns them as track candidates with their hit lists. Per event it runs
+ * the find-and-remove loop: fill the theta x rho vote histogram from the hits
+ * still in the pool (Sec. 5: every hit votes in every theta bin), search
+ * peaks (Sec. 4 and 5: the most populated bin is the most probable line; with
+ * pileup, every local maximum of a (2w+1)^2 window, or the single maximum),
+ * associate the hits that lie on each peak's line (Sec. 5, seed finding),
+ * remove them, and repeat until no bin reaches the vote threshold (the
+ * iterative procedure of Sec. 4).
+ *
+ * Every interface here is plain C: integers, floats and pointers. Pointers
+ * marked "device" must point to memory of the device the context was created
+ * on (hipMalloc or equivalent); pointers marked "host" to host memory.
+ *
+ * Threading and ordering: a context is used by one host thread at a time.
+ * Work is enqueued on the caller's HIP stream (passed as void*, the value of
+ * a hipStream_t; NULL is the default stream) and is asynchronous: outputs are
+ * valid once the stream has been synchronised.
+ *
+ * Ownership: the caller owns every input and output buffer. The library owns
+ * its workspace (device memory grown on demand inside hough_find, freed by
+ * hough_destroy) and its lookup tables. Nothing returned must be freed by the
+ * caller.
+ */
+#ifndef HOUGH_TF_H
+#define HOUGH_TF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HOUGH_OK = 0,
+    HOUGH_ERR_INVALID_ARG = -1,   /* bad config, null pointer, bad offsets  */
+    HOUGH_ERR_CAPACITY = -2,      /* an output or limit is too small        */
+    HOUGH_ERR_OOM = -3,           /* device allocation failed               */
+    HOUGH_ERR_DEVICE = -4,        /* a HIP runtime call failed              */
+    HOUGH_ERR_INTERNAL = -5,
+    HOUGH_ERR_DATA = -6           /* an input hit is invalid (device check) */
+} hough_status;
+
+/*
+ * Finder configuration.
+ *
+ * Histogram (Sec. 5 uses 180 theta bins over 0..180 degrees and 1000 rho
+ * bins over -500..500): theta bins cover [0, pi) and are sampled at their
+ * centres (j + 1/2) pi / n_theta; rho bins cover [rho_min, rho_max).
+ *
+ * A hit i is (z_i, vane_i); its azimuth is phi_i = 360 * vane / n_vanes in
+ * degrees (phi_unit 0) or 2 pi * vane / n_vanes in radians (phi_unit 1),
+ * i.e. the azimuth of the radial vane it was recorded on (Sec. 2: 40 vanes).
+ * The rho bin of hit i at theta bin j is
+ *     k = floor(((phi_i * c_j) + (z_i * s_j) - rho_min) * inv_w)
+ * with every operation rounded to float in this order (no fused
+ * multiply-add), c_j = float(cos theta_j), s_j = float(sin theta_j) computed
+ * in double, inv_w = float(n_rho / (rho_max - rho_min)). Votes with k outside
+ * [0, n_rho) are dropped.
+ *
+ * Bins are ordered by the 64-bit key (count << 32) | (2^32 - 1 - flat),
+ * flat = j * n_rho + k: higher count first, then lower flat index.
+ */
+typedef struct {
+    int32_t  n_theta;        /* theta bins, 1..65536                         */
+    int32_t  n_rho;          /* rho bins, 1..65536; n_theta*n_rho < 2^31     */
+    float    rho_min;        /* lower rho edge (-500)                        */
+    float    rho_max;        /* upper rho edge (+500), > rho_min             */
+    int32_t  n_vanes;        /* vanes of the detector (40)                   */
+    int32_t  phi_unit;       /* 0 = degrees, 1 = radians                     */
+    uint32_t min_votes;      /* T: smallest peak count and candidate size    */
+    int32_t  peak_mode;      /* 0 = argmax (one global maximum per pass),
+                                1 = nms (every local maximum)                */
+    int32_t  nms_radius;     /* w: window half-width for nms, 0..16          */
+    int32_t  assoc_window;   /* a: a hit joins peak (j,k) if |k_i(j)-k| <= a */
+    int32_t  max_iters;      /* iteration cap per event, 0 = none            */
+    /* launch shape; 0 picks the tuned default                               */
+    int32_t  tile_rows;      /* theta rows per LDS tile                      */
+    int32_t  wg_threads;     /* threads per workgroup: 256, 512 or 1024      */
+    int32_t  reserved[4];    /* must be 0                                    */
+} hough_config;
+
+/*
+ * One track candidate (40 bytes), in emission order: events ascending, then
+ * iteration, then descending peak key within the iteration.
+ */
+typedef struct {
+    int32_t  event;          /* event index within the call                  */
+    int32_t  iter;           /* find-and-remove iteration that emitted it    */
+    int32_t  theta_bin;      /* j of the peak                                */
+    int32_t  rho_bin;        /* k of the peak                                */
+    uint32_t peak_votes;     /* histogram count of the peak bin              */
+    uint32_t n_hits;         /* hits claimed by this candidate (>= T)        */
+    int64_t  hit_offset;     /* first entry of its hits in hit_index         */
+    float    theta;          /* bin centre, radians: float((j+1/2) pi/n_theta) */
+    float    rho;            /* bin centre: float(rho_min + (k+1/2) width/n_rho) */
+} hough_candidate;
+
+/* counts[] written by hough_find (device, int64, HOUGH_COUNTS entries) */
+#define HOUGH_COUNTS 8
+#define HOUGH_COUNT_CANDIDATES 0   /* candidates written                    */
+#define HOUGH_COUNT_HITS 1         /* hit indices written                   */
+#define HOUGH_COUNT_STATUS 2       /* 0, or a negative hough_status         */
+#define HOUGH_COUNT_DETAIL 3       /* first invalid global hit index, or -1 */
+#define HOUGH_COUNT_VOTES 4        /* votes cast: sum of alive hits x n_theta
+                                      over all iterations and events        */
+#define HOUGH_COUNT_ITERS 5        /* iterations summed over events         */
+#define HOUGH_COUNT_MAX_ITERS 6    /* largest iteration count of an event   */
+#define HOUGH_COUNT_PASSES 7       /* histogram sweeps (>= iterations; more
+                                      when a pass overflowed the peak list) */
+
+/* Largest hit count of one event. */
+#define HOUGH_MAX_EVENT_HITS 131072
+/* Largest |z| accepted (keeps every bin value inside int range). */
+#define HOUGH_Z_LIMIT 1.0e6f
+
+/* Fills *cfg with the defaults: 1024 x 1024 bins over [-500, 500), 40 vanes,
+ * degrees, T = 6, nms with w = 1, a = 0, no iteration cap, tuned launch. */
+hough_status hough_config_default(hough_config *cfg);
+
+/* Validates cfg, builds the lookup tables on the host, uploads them to
+ * `device` and returns a new context in *out (host pointer). On error *out is
+ * NULL. */
+hough_status hough_create(const hough_config *cfg, int device, void **out);
+
+/* Frees the context and its device memory. NULL is accepted. The caller
+ * must have synchronised every stream that still uses the context. */
+hough_status hough_destroy(void *ctx);
+
+/* Upper bounds of the outputs for n_events events holding n_hits_total hits
+ * in total: at most floor(n_e / T) candidates per event, so
+ * floor(n_hits_total / T) overall, and at most n_hits_total hit indices. */
+hough_status hough_output_bounds(const void *ctx, int32_t n_events, int64_t n_hits_total,
+                                 int64_t *max_candidates, int64_t *max_hit_index);
+
+/*
+ * Runs the finder on n_events events.
+ *   event_offsets  device int64[n_events + 1]; event e holds hits
+ *                  [offsets[e], offsets[e+1]); offsets[0] must be 0 and
+ *                  offsets[n_events] must equal n_hits_total (the host
+ *                  cannot read device memory without a copy, so the caller
+ *                  states n_hits_total; a mismatch is reported as
+ *                  HOUGH_ERR_INVALID_ARG through counts[2]).
+ *   z, vane        device float[n_hits_total], int16[n_hits_total]:
+ *                  structure-of-arrays hits (z in mm, vane in [0, n_vanes)).
+ *   cand           device hough_candidate[cand_capacity]
+ *   hit_index      device int32[hit_capacity]: per candidate, its hits as
+ *                  event-local indices, ascending
+ *   counts         device int64[HOUGH_COUNTS], see HOUGH_COUNT_*
+ * cand_capacity and hit_capacity must be at least the bounds of
+ * hough_output_bounds, else HOUGH_ERR_CAPACITY is returned before anything
+ * is enqueued. Invalid hits (vane out of range, non-finite z or
+ * |z| > HOUGH_Z_LIMIT) and events with more than HOUGH_MAX_EVENT_HITS hits
+ * are found on the device: counts[2] then holds HOUGH_ERR_DATA or
+ * HOUGH_ERR_CAPACITY, counts[3] the first offending global hit index, and
+ * counts[0] = counts[1] = 0 (nothing partial is reported).
+ * Returns HOUGH_ERR_INVALID_ARG for null pointers, negative sizes or a bad
+ * context, HOUGH_ERR_OOM if the workspace cannot grow, HOUGH_ERR_DEVICE if a
+ * launch fails.
+ */
+hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
+                        const int64_t *event_offsets, const float *z, const int16_t *vane,
+                        hough_candidate *cand, int64_t cand_capacity,
+                        int32_t *hit_index, int64_t hit_capacity, int64_t *counts);
+
+/*
+ * Debug view of the vote histogram of one event: acc_out (device
+ * uint32[n_theta * n_rho], row-major theta x rho) receives the histogram of
+ * the hits still in the pool after `iters` iterations of the finder
+ * (iters = 0: all n_hits hits). z and vane are device arrays of n_hits hits.
+ * counts as in hough_find (device int64[HOUGH_COUNTS]).
+ */
+hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, const float *z,
+                                     const int16_t *vane, int32_t iters, uint32_t *acc_out,
+                                     int64_t *counts);
+
+/* Host copies of the lookup tables the context uploaded: c_j, s_j
+ * (float[n_theta]), phi per vane (float[n_vanes]), inv_w (float[1]), theta
+ * and rho bin centres (float[n_theta], float[n_rho]). Any pointer may be
+ * NULL. */
+hough_status hough_tables(const void *ctx, float *cos_t, float *sin_t, float *phi_v,
+                          float *inv_w, float *theta_c, float *rho_c);
+
+/* Launch shape chosen for this context (after defaults/tuning). */
+hough_status hough_launch_shape(const void *ctx, int32_t *tile_rows, int32_t *wg_threads,
+                                int32_t *lds_bytes);
+
+/* Kernel timing: when enabled, hough_find records HIP events around its
+ * finder kernel; hough_timing returns the summed milliseconds and the number
+ * of launches measured since the last reset (it synchronises those events). */
+hough_status hough_set_timing(void *ctx, int enable);
+hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, int reset);
+
+const char *hough_status_string(hough_status st);
+/* Detail of the last failing call on ctx (empty string if none). */
+const char *hough_last_error(const void *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOUGH_TF_H */

@@ -82,6 +82,10 @@ static int orc_check_config(const orc_config *c)
     if (c->n_theta < 1 || c->n_rho < 1 || c->n_theta > 65536 || c->n_rho > 65536) return ORC_ERR_ARG;
     if ((int64_t)c->n_theta * c->n_rho > 0x7fffffffLL) return ORC_ERR_ARG;
     if (!(c->rho_max > c->rho_min)) return ORC_ERR_ARG;
+    /* keeps |u| below 2^31 for every accepted hit, so the float-to-int
+     * conversion of the bin value is always defined */
+    if (fabsf(c->rho_min) > 1.0e6f || fabsf(c->rho_max) > 1.0e6f) return ORC_ERR_ARG;
+    if ((double)c->n_rho / ((double)c->rho_max - (double)c->rho_min) > 1000.0) return ORC_ERR_ARG;
     if (c->n_vanes < 1 || c->n_vanes > 32767) return ORC_ERR_ARG;
     if (c->phi_unit != 0 && c->phi_unit != 1) return ORC_ERR_ARG;
     if (c->min_votes < 1) return ORC_ERR_ARG;

@@ -1,0 +1,520 @@
+// C-ABI layer: context, lookup tables, workspace, argument checks, launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hough_internal.h"
+#include "hough_tf.h"
+
+namespace {
+
+constexpr int kHotCap = 512;
+constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
+constexpr int kAssocMinBytes = 2048 * 8 + 2048 * 12;  // one peak at the largest event
+constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
+
+struct Ctx {
+    uint32_t magic = 0x48544631u;
+    hough_config cfg{};
+    int device = 0;
+    // tables, host copies and device copies
+    std::vector<float> cos_t, sin_t, phi_v, theta_c, rho_c;
+    float inv_w = 0.f;
+    float *d_tables = nullptr;
+    float2 *d_cs = nullptr;
+    float *d_phi = nullptr, *d_thc = nullptr, *d_rhoc = nullptr;
+    // launch shape
+    int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
+    int dump_rows = 0, dump_lds = 0;
+    // workspace
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t ws_hits = -1, ws_events = -1;
+    int32_t *state = nullptr, *aidx = nullptr, *hits_ws = nullptr, *ev_ncand = nullptr, *ev_nhits = nullptr;
+    float *aphi = nullptr, *az = nullptr;
+    hough_candidate *cand_ws = nullptr;
+    long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
+    unsigned long long *stats = nullptr;
+    int64_t *tmp_offsets = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    std::string last_error;
+};
+
+thread_local std::string g_last_global_error;
+
+Ctx *as_ctx(void *p) {
+    Ctx *c = static_cast<Ctx *>(p);
+    return (c && c->magic == 0x48544631u) ? c : nullptr;
+}
+const Ctx *as_ctx(const void *p) {
+    const Ctx *c = static_cast<const Ctx *>(p);
+    return (c && c->magic == 0x48544631u) ? c : nullptr;
+}
+
+hough_status fail(Ctx *c, hough_status st, const std::string &msg) {
+    if (c) c->last_error = msg;
+    g_last_global_error = msg;
+    return st;
+}
+
+hough_status check_config(const hough_config *c, std::string &why) {
+    if (!c) { why = "null config"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->n_theta < 1 || c->n_theta > 65536 || c->n_rho < 1 || c->n_rho > 65536) {
+        why = "n_theta and n_rho must be in 1..65536";
+        return HOUGH_ERR_INVALID_ARG;
+    }
+    if ((int64_t)c->n_theta * c->n_rho > 0x7fffffffLL) { why = "n_theta * n_rho must be < 2^31"; return HOUGH_ERR_INVALID_ARG; }
+    if (!(c->rho_max > c->rho_min)) { why = "rho_max must exceed rho_min"; return HOUGH_ERR_INVALID_ARG; }
+    if (std::fabs(c->rho_min) > 1.0e6f || std::fabs(c->rho_max) > 1.0e6f) { why = "|rho_min|, |rho_max| must be <= 1e6"; return HOUGH_ERR_INVALID_ARG; }
+    if ((double)c->n_rho / ((double)c->rho_max - (double)c->rho_min) > 1000.0) { why = "n_rho / (rho_max - rho_min) must be <= 1000"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->n_vanes < 1 || c->n_vanes > 32767) { why = "n_vanes must be in 1..32767"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->phi_unit != 0 && c->phi_unit != 1) { why = "phi_unit must be 0 or 1"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->min_votes < 1) { why = "min_votes must be >= 1"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->peak_mode != 0 && c->peak_mode != 1) { why = "peak_mode must be 0 or 1"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->nms_radius < 0 || c->nms_radius > 16) { why = "nms_radius must be in 0..16"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->assoc_window < 0) { why = "assoc_window must be >= 0"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->max_iters < 0) { why = "max_iters must be >= 0"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->tile_rows < 0 || c->tile_rows > 4096) { why = "tile_rows must be in 0..4096"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->wg_threads != 0 && c->wg_threads != 256 && c->wg_threads != 512 && c->wg_threads != 1024) {
+        why = "wg_threads must be 0, 256, 512 or 1024";
+        return HOUGH_ERR_INVALID_ARG;
+    }
+    for (int r : c->reserved)
+        if (r != 0) { why = "reserved fields must be 0"; return HOUGH_ERR_INVALID_ARG; }
+    return HOUGH_OK;
+}
+
+void build_tables(Ctx &c) {
+    const hough_config &g = c.cfg;
+    const double pi = 3.14159265358979323846;
+    c.cos_t.resize(g.n_theta);
+    c.sin_t.resize(g.n_theta);
+    c.theta_c.resize(g.n_theta);
+    for (int j = 0; j < g.n_theta; ++j) {
+        const double th = (j + 0.5) * pi / (double)g.n_theta;
+        c.cos_t[j] = (float)std::cos(th);
+        c.sin_t[j] = (float)std::sin(th);
+        c.theta_c[j] = (float)th;
+    }
+    c.phi_v.resize(g.n_vanes);
+    const double full = g.phi_unit == 0 ? 360.0 : 2.0 * pi;
+    for (int v = 0; v < g.n_vanes; ++v) c.phi_v[v] = (float)(full * (double)v / (double)g.n_vanes);
+    const double width = (double)g.rho_max - (double)g.rho_min;
+    c.inv_w = (float)((double)g.n_rho / width);
+    c.rho_c.resize(g.n_rho);
+    for (int k = 0; k < g.n_rho; ++k) c.rho_c[k] = (float)((double)g.rho_min + (k + 0.5) * width / (double)g.n_rho);
+}
+
+// Picks the LDS tile: as many theta rows as fit the per-workgroup LDS next to
+// the hot list and the peak list (one workgroup per compute unit).
+hough_status choose_shape(Ctx &c, std::string &why) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c.device) != hipSuccess) { why = "hipGetDeviceProperties failed"; return HOUGH_ERR_DEVICE; }
+    const int lds_max = (int)prop.sharedMemPerBlock;
+    const hough_config &g = c.cfg;
+    c.pitch = (g.n_rho + 3) & ~3;
+    const int halo = g.peak_mode == 1 ? g.nms_radius : 0;
+    const int extra = 4 * kHotCap + 8 * (kHotCap + kPeakKeep) + kStaticLds;
+    const int row_bytes = 4 * c.pitch;
+    int rows_fit = (lds_max - extra) / row_bytes - 2 * halo;
+    if (rows_fit < 1) { why = "n_rho too large for the LDS tile"; return HOUGH_ERR_INVALID_ARG; }
+    int rows = g.tile_rows > 0 ? g.tile_rows : std::min(rows_fit, 32);
+    rows = std::min(rows, g.n_theta);
+    if (rows > rows_fit) { why = "tile_rows does not fit in LDS"; return HOUGH_ERR_INVALID_ARG; }
+    c.tile_rows = rows;
+    c.tile_bytes = std::max(row_bytes * (rows + 2 * halo), kAssocMinBytes);
+    c.tile_bytes = (c.tile_bytes + 15) & ~15;
+    c.lds_bytes = c.tile_bytes + 4 * kHotCap + 8 * (kHotCap + kPeakKeep);
+    if (c.lds_bytes + kStaticLds > lds_max) { why = "LDS budget exceeded"; return HOUGH_ERR_INVALID_ARG; }
+    c.wg_threads = g.wg_threads > 0 ? g.wg_threads : 1024;
+    if (hough::set_find_lds_limit(c.wg_threads, c.lds_bytes) != hipSuccess) {
+        why = "hipFuncSetAttribute failed for the finder kernel";
+        return HOUGH_ERR_DEVICE;
+    }
+    int drows = std::min(g.n_theta, std::max(1, (lds_max - kStaticLds) / row_bytes));
+    c.dump_rows = std::min(drows, 64);
+    c.dump_lds = c.dump_rows * row_bytes;
+    if (hough::set_dump_lds_limit(c.dump_lds) != hipSuccess) {
+        why = "hipFuncSetAttribute failed for the dump kernel";
+        return HOUGH_ERR_DEVICE;
+    }
+    return HOUGH_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Grows the workspace for n_hits hits and n_events events.
+hough_status ensure_workspace(Ctx &c, int64_t n_hits, int64_t n_events, hipStream_t s) {
+    if (c.ws && n_hits <= c.ws_hits && n_events <= c.ws_events) return HOUGH_OK;
+    int64_t nh = std::max<int64_t>(n_hits, std::max<int64_t>(c.ws_hits, 1024));
+    int64_t ne = std::max<int64_t>(n_events, std::max<int64_t>(c.ws_events, 64));
+    if (c.ws) {
+        nh = std::max<int64_t>(nh, c.ws_hits + c.ws_hits / 2);
+        ne = std::max<int64_t>(ne, c.ws_events + c.ws_events / 2);
+    }
+    const int64_t ncand = nh / (int64_t)c.cfg.min_votes + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_state = take(4 * nh), o_aidx = take(4 * nh), o_aphi = take(4 * nh), o_az = take(4 * nh);
+    const size_t o_hits = take(4 * nh), o_cand = take(sizeof(hough_candidate) * ncand);
+    const size_t o_enc = take(4 * ne), o_enh = take(4 * ne), o_eco = take(8 * ne), o_eho = take(8 * ne);
+    const size_t o_stats = take(8 * 8), o_err = take(8 * 4), o_offs = take(8 * 4);
+    void *p = nullptr;
+    if (c.ws) {
+        // the old workspace may still be read by work queued earlier
+        if (hipStreamSynchronize(s) != hipSuccess) return HOUGH_ERR_DEVICE;
+        (void)hipFree(c.ws);
+        c.ws = nullptr;
+    }
+    if (hipMalloc(&p, off) != hipSuccess) {
+        c.ws_hits = c.ws_events = -1;
+        return HOUGH_ERR_OOM;
+    }
+    char *base = static_cast<char *>(p);
+    c.ws = p;
+    c.ws_bytes = off;
+    c.ws_hits = nh;
+    c.ws_events = ne;
+    c.state = reinterpret_cast<int32_t *>(base + o_state);
+    c.aidx = reinterpret_cast<int32_t *>(base + o_aidx);
+    c.aphi = reinterpret_cast<float *>(base + o_aphi);
+    c.az = reinterpret_cast<float *>(base + o_az);
+    c.hits_ws = reinterpret_cast<int32_t *>(base + o_hits);
+    c.cand_ws = reinterpret_cast<hough_candidate *>(base + o_cand);
+    c.ev_ncand = reinterpret_cast<int32_t *>(base + o_enc);
+    c.ev_nhits = reinterpret_cast<int32_t *>(base + o_enh);
+    c.ev_cout = reinterpret_cast<long long *>(base + o_eco);
+    c.ev_hout = reinterpret_cast<long long *>(base + o_eho);
+    c.stats = reinterpret_cast<unsigned long long *>(base + o_stats);
+    c.err = reinterpret_cast<long long *>(base + o_err);
+    c.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
+    return HOUGH_OK;
+}
+
+hough::FindArgs find_args(const Ctx &c) {
+    hough::FindArgs a{};
+    const hough_config &g = c.cfg;
+    a.n_theta = g.n_theta;
+    a.n_rho = g.n_rho;
+    a.n_vanes = g.n_vanes;
+    a.rho_min = g.rho_min;
+    a.inv_w = c.inv_w;
+    a.min_votes = g.min_votes;
+    a.peak_mode = g.peak_mode;
+    a.nms_radius = g.nms_radius;
+    a.assoc_window = g.assoc_window;
+    a.max_iters = g.max_iters;
+    a.cs = c.d_cs;
+    a.phi_v = c.d_phi;
+    a.theta_c = c.d_thc;
+    a.rho_c = c.d_rhoc;
+    a.state = c.state;
+    a.aidx = c.aidx;
+    a.aphi = c.aphi;
+    a.az = c.az;
+    a.cand_ws = c.cand_ws;
+    a.hits_ws = c.hits_ws;
+    a.ev_ncand = c.ev_ncand;
+    a.ev_nhits = c.ev_nhits;
+    a.stats = c.stats;
+    a.err = c.err;
+    a.tile_rows = c.tile_rows;
+    a.pitch = c.pitch;
+    a.tile_bytes = c.tile_bytes;
+    a.hcap = kHotCap;
+    a.pkeep = kPeakKeep;
+    return a;
+}
+
+hough_status run_find(Ctx &c, hipStream_t s, int32_t n_events, int64_t n_total, const int64_t *offsets,
+                      const float *z, const int16_t *vane, int32_t max_iters) {
+    hough::FindArgs a = find_args(c);
+    a.n_events = n_events;
+    a.n_total = n_total;
+    a.offsets = offsets;
+    a.z = z;
+    a.vane = vane;
+    a.max_iters = max_iters;
+    if (hough::launch_reset(c.stats, c.err, s) != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, "reset launch failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c.timing && n_events > 0) {
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return fail(&c, HOUGH_ERR_DEVICE, "hipEventCreate failed");
+        (void)hipEventRecord(e0, s);
+    }
+    hipError_t st = hough::launch_find(a, c.wg_threads, c.lds_bytes, s);
+    if (st != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("finder launch failed: ") + hipGetErrorString(st));
+    if (e0) {
+        (void)hipEventRecord(e1, s);
+        c.ev_pairs.emplace_back(e0, e1);
+    }
+    return HOUGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hough_status hough_config_default(hough_config *cfg) {
+    if (!cfg) return HOUGH_ERR_INVALID_ARG;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_theta = 1024;
+    cfg->n_rho = 1024;
+    cfg->rho_min = -500.0f;
+    cfg->rho_max = 500.0f;
+    cfg->n_vanes = 40;
+    cfg->phi_unit = 0;
+    cfg->min_votes = 6;
+    cfg->peak_mode = 1;
+    cfg->nms_radius = 1;
+    cfg->assoc_window = 0;
+    cfg->max_iters = 0;
+    return HOUGH_OK;
+}
+
+hough_status hough_create(const hough_config *cfg, int device, void **out) {
+    if (!out) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    std::string why;
+    hough_status st = check_config(cfg, why);
+    if (st) return fail(nullptr, st, why);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, HOUGH_ERR_INVALID_ARG, "no such device");
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return fail(nullptr, HOUGH_ERR_OOM, "host allocation failed");
+    c->cfg = *cfg;
+    c->device = device;
+    build_tables(*c);
+    st = choose_shape(*c, why);
+    if (st) {
+        delete c;
+        return fail(nullptr, st, why);
+    }
+    const size_t nf = 2 * (size_t)cfg->n_theta + cfg->n_vanes + cfg->n_theta + cfg->n_rho;
+    if (hipMalloc(&c->d_tables, nf * sizeof(float)) != hipSuccess) {
+        delete c;
+        return fail(nullptr, HOUGH_ERR_OOM, "table allocation failed");
+    }
+    c->d_cs = reinterpret_cast<float2 *>(c->d_tables);
+    c->d_phi = c->d_tables + 2 * cfg->n_theta;
+    c->d_thc = c->d_phi + cfg->n_vanes;
+    c->d_rhoc = c->d_thc + cfg->n_theta;
+    std::vector<float> host(nf);
+    float *h = host.data();
+    for (int j = 0; j < cfg->n_theta; ++j) {
+        h[2 * j] = c->cos_t[j];
+        h[2 * j + 1] = c->sin_t[j];
+    }
+    std::copy(c->phi_v.begin(), c->phi_v.end(), h + 2 * cfg->n_theta);
+    std::copy(c->theta_c.begin(), c->theta_c.end(), h + 2 * cfg->n_theta + cfg->n_vanes);
+    std::copy(c->rho_c.begin(), c->rho_c.end(), h + 3 * cfg->n_theta + cfg->n_vanes);
+    if (hipMemcpy(c->d_tables, h, nf * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(c->d_tables);
+        delete c;
+        return fail(nullptr, HOUGH_ERR_DEVICE, "table upload failed");
+    }
+    *out = c;
+    return HOUGH_OK;
+}
+
+hough_status hough_destroy(void *ctx) {
+    if (!ctx) return HOUGH_OK;
+    Ctx *c = as_ctx(ctx);
+    if (!c) return HOUGH_ERR_INVALID_ARG;
+    (void)hipSetDevice(c->device);
+    for (auto &pr : c->ev_pairs) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->d_tables) (void)hipFree(c->d_tables);
+    c->magic = 0;
+    delete c;
+    return HOUGH_OK;
+}
+
+hough_status hough_output_bounds(const void *ctx, int32_t n_events, int64_t n_hits_total,
+                                 int64_t *max_candidates, int64_t *max_hit_index) {
+    const Ctx *c = as_ctx(ctx);
+    if (!c || n_events < 0 || n_hits_total < 0 || !max_candidates || !max_hit_index) return HOUGH_ERR_INVALID_ARG;
+    *max_candidates = n_hits_total / (int64_t)c->cfg.min_votes;
+    *max_hit_index = n_hits_total;
+    return HOUGH_OK;
+}
+
+hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
+                        const int64_t *event_offsets, const float *z, const int16_t *vane,
+                        hough_candidate *cand, int64_t cand_capacity, int32_t *hit_index,
+                        int64_t hit_capacity, int64_t *counts) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
+    if (n_events < 0 || n_hits_total < 0) return fail(c, HOUGH_ERR_INVALID_ARG, "negative size");
+    if (!event_offsets || !counts) return fail(c, HOUGH_ERR_INVALID_ARG, "null offsets or counts");
+    if (n_hits_total > 0 && (!z || !vane)) return fail(c, HOUGH_ERR_INVALID_ARG, "null hit arrays");
+    if (n_events == 0 && n_hits_total != 0) return fail(c, HOUGH_ERR_INVALID_ARG, "hits without events");
+    if (n_hits_total > 0x7fffffffLL) return fail(c, HOUGH_ERR_INVALID_ARG, "more than 2^31-1 hits per call");
+    const int64_t need_c = n_hits_total / (int64_t)c->cfg.min_votes;
+    if (cand_capacity < need_c || hit_capacity < n_hits_total) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "output capacity too small: need %lld candidates and %lld hit indices",
+                      (long long)need_c, (long long)n_hits_total);
+        return fail(c, HOUGH_ERR_CAPACITY, buf);
+    }
+    if ((need_c > 0 && !cand) || (n_hits_total > 0 && !hit_index)) return fail(c, HOUGH_ERR_INVALID_ARG, "null outputs");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hough_status st = ensure_workspace(*c, n_hits_total, n_events, s);
+    if (st) return fail(c, st, "workspace allocation failed");
+    st = run_find(*c, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters);
+    if (st) return st;
+    hough::CompactArgs ca{};
+    ca.n_events = n_events;
+    ca.n_total = n_hits_total;
+    ca.min_votes = c->cfg.min_votes;
+    ca.offsets = event_offsets;
+    ca.cand_ws = c->cand_ws;
+    ca.hits_ws = c->hits_ws;
+    ca.ev_ncand = c->ev_ncand;
+    ca.ev_nhits = c->ev_nhits;
+    ca.ev_cout = c->ev_cout;
+    ca.ev_hout = c->ev_hout;
+    ca.stats = c->stats;
+    ca.err = c->err;
+    ca.cand = cand;
+    ca.hit_index = hit_index;
+    ca.counts = counts;
+    if (hough::launch_compact(ca, s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "compaction launch failed");
+    c->last_error.clear();
+    return HOUGH_OK;
+}
+
+hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, const float *z,
+                                     const int16_t *vane, int32_t iters, uint32_t *acc_out, int64_t *counts) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
+    if (n_hits < 0 || n_hits > HOUGH_MAX_EVENT_HITS || iters < 0 || !acc_out || !counts ||
+        (n_hits > 0 && (!z || !vane)))
+        return fail(c, HOUGH_ERR_INVALID_ARG, "bad debug_accumulator arguments");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hough_status st = ensure_workspace(*c, n_hits, 1, s);
+    if (st) return fail(c, st, "workspace allocation failed");
+    if (hough::launch_set_offsets(c->tmp_offsets, n_hits, s) != hipSuccess)
+        return fail(c, HOUGH_ERR_DEVICE, "offset launch failed");
+    // iters == 0 still runs the finder for its input validation, with a cap of
+    // zero iterations expressed by skipping the state below
+    st = run_find(*c, s, 1, n_hits, c->tmp_offsets, z, vane, iters > 0 ? iters : 0);
+    if (st) return st;
+    hough::CompactArgs ca{};
+    ca.n_events = 0;
+    ca.stats = c->stats;
+    ca.err = c->err;
+    ca.counts = counts;
+    ca.ev_ncand = c->ev_ncand;
+    ca.ev_nhits = c->ev_nhits;
+    if (hough::launch_compact(ca, s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "status launch failed");
+    hough::DumpArgs da{};
+    da.n_theta = c->cfg.n_theta;
+    da.n_rho = c->cfg.n_rho;
+    da.n_vanes = c->cfg.n_vanes;
+    da.rho_min = c->cfg.rho_min;
+    da.inv_w = c->inv_w;
+    da.cs = c->d_cs;
+    da.phi_v = c->d_phi;
+    da.n = n_hits;
+    da.z = z;
+    da.vane = vane;
+    da.state = iters > 0 ? c->state : nullptr;
+    da.acc = acc_out;
+    da.tile_rows = c->dump_rows;
+    da.pitch = c->pitch;
+    if (hough::launch_dump(da, c->dump_lds, s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "dump launch failed");
+    c->last_error.clear();
+    return HOUGH_OK;
+}
+
+hough_status hough_tables(const void *ctx, float *cos_t, float *sin_t, float *phi_v, float *inv_w,
+                          float *theta_c, float *rho_c) {
+    const Ctx *c = as_ctx(ctx);
+    if (!c) return HOUGH_ERR_INVALID_ARG;
+    if (cos_t) std::copy(c->cos_t.begin(), c->cos_t.end(), cos_t);
+    if (sin_t) std::copy(c->sin_t.begin(), c->sin_t.end(), sin_t);
+    if (phi_v) std::copy(c->phi_v.begin(), c->phi_v.end(), phi_v);
+    if (inv_w) *inv_w = c->inv_w;
+    if (theta_c) std::copy(c->theta_c.begin(), c->theta_c.end(), theta_c);
+    if (rho_c) std::copy(c->rho_c.begin(), c->rho_c.end(), rho_c);
+    return HOUGH_OK;
+}
+
+hough_status hough_launch_shape(const void *ctx, int32_t *tile_rows, int32_t *wg_threads, int32_t *lds_bytes) {
+    const Ctx *c = as_ctx(ctx);
+    if (!c) return HOUGH_ERR_INVALID_ARG;
+    if (tile_rows) *tile_rows = c->tile_rows;
+    if (wg_threads) *wg_threads = c->wg_threads;
+    if (lds_bytes) *lds_bytes = c->lds_bytes;
+    return HOUGH_OK;
+}
+
+hough_status hough_set_timing(void *ctx, int enable) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return HOUGH_ERR_INVALID_ARG;
+    c->timing = enable != 0;
+    return HOUGH_OK;
+}
+
+hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, int reset) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return HOUGH_ERR_INVALID_ARG;
+    for (auto &pr : c->ev_pairs) {
+        if (hipEventSynchronize(pr.second) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipEventSynchronize failed");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, pr.first, pr.second);
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    c->ev_pairs.clear();
+    if (find_kernel_ms) *find_kernel_ms = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    if (reset) {
+        c->timed_ms = 0.0;
+        c->timed_launches = 0;
+    }
+    return HOUGH_OK;
+}
+
+const char *hough_status_string(hough_status st) {
+    switch (st) {
+    case HOUGH_OK: return "ok";
+    case HOUGH_ERR_INVALID_ARG: return "invalid argument";
+    case HOUGH_ERR_CAPACITY: return "capacity exceeded";
+    case HOUGH_ERR_OOM: return "out of device memory";
+    case HOUGH_ERR_DEVICE: return "device error";
+    case HOUGH_ERR_INTERNAL: return "internal error";
+    case HOUGH_ERR_DATA: return "invalid hit data";
+    default: return "unknown status";
+    }
+}
+
+const char *hough_last_error(const void *ctx) {
+    const Ctx *c = as_ctx(ctx);
+    if (!c) return g_last_global_error.c_str();
+    return c->last_error.c_str();
+}
+
+}  // extern "C"

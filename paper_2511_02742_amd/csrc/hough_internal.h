@@ -1,0 +1,82 @@
+// Internal interface between the C-ABI layer and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hough_tf.h"
+
+namespace hough {
+
+// Everything the finder kernel needs, passed by value.
+struct FindArgs {
+    // configuration
+    int32_t n_theta, n_rho, n_vanes;
+    float rho_min, inv_w;
+    uint32_t min_votes;
+    int32_t peak_mode, nms_radius, assoc_window, max_iters;
+    // lookup tables (device); cs[j] = (c_j, s_j)
+    const float2 *cs;
+    const float *phi_v, *theta_c, *rho_c;
+    // inputs (device)
+    int32_t n_events;
+    int64_t n_total;
+    const int64_t *offsets;
+    const float *z;
+    const int16_t *vane;
+    // workspace (device), indexed by global hit / event
+    int32_t *state;      // per hit: owning candidate id (event-local) or -1
+    int32_t *aidx;       // alive list: event-local hit index
+    float *aphi, *az;    // alive list: phi and z
+    hough_candidate *cand_ws;  // candidate slots, event e starts at floor(off_e / T)
+    int32_t *hits_ws;    // hit-list slots, event e starts at off_e
+    int32_t *ev_ncand, *ev_nhits;
+    unsigned long long *stats;  // [votes, iters, max_iters, passes]
+    long long *err;             // [status (min), first bad global hit index (min)]
+    // launch shape
+    int32_t tile_rows;   // own theta rows per LDS tile
+    int32_t pitch;       // LDS words per tile row (n_rho rounded up to 4)
+    int32_t tile_bytes;  // LDS bytes of the tile / association union
+    int32_t hcap;        // hot-list capacity per tile
+    int32_t pkeep;       // peak entries kept after a compaction; pkeep + hcap is a power of 2
+};
+
+struct DumpArgs {
+    int32_t n_theta, n_rho, n_vanes;
+    float rho_min, inv_w;
+    const float2 *cs;
+    const float *phi_v;
+    int64_t n;
+    const float *z;
+    const int16_t *vane;
+    const int32_t *state;  // NULL: every hit votes
+    uint32_t *acc;
+    int32_t tile_rows, pitch;
+};
+
+struct CompactArgs {
+    int32_t n_events;
+    int64_t n_total;
+    uint32_t min_votes;
+    const int64_t *offsets;
+    const hough_candidate *cand_ws;
+    const int32_t *hits_ws;
+    const int32_t *ev_ncand, *ev_nhits;
+    long long *ev_cout, *ev_hout;  // exclusive prefix sums
+    const unsigned long long *stats;
+    const long long *err;
+    hough_candidate *cand;
+    int32_t *hit_index;
+    int64_t *counts;
+};
+
+// Kernel launchers (hough_kernels.hip). Each returns the launch status.
+hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s);
+hipError_t launch_find(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
+hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
+hipError_t launch_dump(const DumpArgs &a, int lds_bytes, hipStream_t s);
+hipError_t launch_set_offsets(int64_t *offsets, int64_t n, hipStream_t s);
+hipError_t set_find_lds_limit(int wg_threads, int lds_bytes);
+hipError_t set_dump_lds_limit(int lds_bytes);
+
+}  // namespace hough

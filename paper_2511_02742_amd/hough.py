@@ -1,0 +1,268 @@
+"""Python binding of ``libhough_tf.so`` (the C ABI in include/hough_tf.h).
+
+Argument marshalling only: torch provides device memory and the stream, and
+every step of the finder runs in the library's HIP kernels. There is no CPU
+fallback -- if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhough_tf.so")
+
+HOUGH_OK = 0
+HOUGH_ERR_INVALID_ARG = -1
+HOUGH_ERR_CAPACITY = -2
+HOUGH_ERR_OOM = -3
+HOUGH_ERR_DEVICE = -4
+HOUGH_ERR_INTERNAL = -5
+HOUGH_ERR_DATA = -6
+
+HOUGH_COUNTS = 8
+COUNT_NAMES = ("candidates", "hits", "status", "detail", "votes", "iters", "max_iters", "passes")
+
+EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
+           "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
+           "hough_timing", "hough_status_string", "hough_last_error")
+
+cand_dtype = np.dtype([("event", "<i4"), ("iter", "<i4"), ("theta_bin", "<i4"), ("rho_bin", "<i4"),
+                       ("peak_votes", "<u4"), ("n_hits", "<u4"), ("hit_offset", "<i8"),
+                       ("theta", "<f4"), ("rho", "<f4")])
+assert cand_dtype.itemsize == 40
+
+
+class HoughConfig(ctypes.Structure):
+    _fields_ = [("n_theta", ctypes.c_int32), ("n_rho", ctypes.c_int32),
+                ("rho_min", ctypes.c_float), ("rho_max", ctypes.c_float),
+                ("n_vanes", ctypes.c_int32), ("phi_unit", ctypes.c_int32),
+                ("min_votes", ctypes.c_uint32), ("peak_mode", ctypes.c_int32),
+                ("nms_radius", ctypes.c_int32), ("assoc_window", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("wg_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class HoughError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        super().__init__("hough status %d (%s)%s" % (status, _status_string(status),
+                                                     (": " + detail) if detail else ""))
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhough_tf.so not found at %s; run __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I32 = ctypes.c_int32
+    I64 = ctypes.c_int64
+    cfgp = ctypes.POINTER(HoughConfig)
+    st = ctypes.c_int
+    lib.hough_config_default.argtypes = [cfgp]
+    lib.hough_config_default.restype = st
+    lib.hough_create.argtypes = [cfgp, ctypes.c_int, ctypes.POINTER(P)]
+    lib.hough_create.restype = st
+    lib.hough_destroy.argtypes = [P]
+    lib.hough_destroy.restype = st
+    lib.hough_output_bounds.argtypes = [P, I32, I64, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    lib.hough_output_bounds.restype = st
+    lib.hough_find.argtypes = [P, P, I32, I64, P, P, P, P, I64, P, I64, P]
+    lib.hough_find.restype = st
+    lib.hough_debug_accumulator.argtypes = [P, P, I64, P, P, I32, P, P]
+    lib.hough_debug_accumulator.restype = st
+    lib.hough_tables.argtypes = [P, P, P, P, P, P, P]
+    lib.hough_tables.restype = st
+    lib.hough_launch_shape.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.hough_launch_shape.restype = st
+    lib.hough_set_timing.argtypes = [P, ctypes.c_int]
+    lib.hough_set_timing.restype = st
+    lib.hough_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), ctypes.c_int]
+    lib.hough_timing.restype = st
+    lib.hough_status_string.argtypes = [ctypes.c_int]
+    lib.hough_status_string.restype = ctypes.c_char_p
+    lib.hough_last_error.argtypes = [P]
+    lib.hough_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _status_string(status: int) -> str:
+    try:
+        return load_library().hough_status_string(status).decode()
+    except Exception:  # library not loadable: plain number
+        return str(status)
+
+
+def default_config(**overrides) -> HoughConfig:
+    cfg = HoughConfig()
+    load_library().hough_config_default(ctypes.byref(cfg))
+    for k, v in overrides.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+@dataclasses.dataclass
+class FindOutput:
+    cand: "object"        # torch uint8 [cap, 40] on the device
+    hit_index: "object"   # torch int32 [cap] on the device
+    counts: "object"      # torch int64 [8] on the device
+
+    def to_host(self):
+        """(candidates as a structured array, hit indices, counts dict)."""
+        cnt = self.counts.cpu().numpy()
+        info = dict(zip(COUNT_NAMES, (int(x) for x in cnt)))
+        nc, nh = info["candidates"], info["hits"]
+        cand = self.cand[:nc].cpu().numpy().reshape(-1).view(cand_dtype).copy() if nc else \
+            np.zeros(0, cand_dtype)
+        hits = self.hit_index[:nh].cpu().numpy().copy()
+        return cand, hits, info
+
+
+class HoughFinder:
+    """One library context bound to one device."""
+
+    def __init__(self, device: int = 0, config: Optional[HoughConfig] = None, **overrides):
+        import torch  # device memory and streams
+        self._torch = torch
+        self.lib = load_library()
+        self.device = device
+        self.config = config if config is not None else default_config(**overrides)
+        if config is not None:
+            for k, v in overrides.items():
+                setattr(self.config, k, v)
+        h = ctypes.c_void_p()
+        st = self.lib.hough_create(ctypes.byref(self.config), device, ctypes.byref(h))
+        if st != HOUGH_OK:
+            raise HoughError(st, self.lib.hough_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.hough_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st: int):
+        return HoughError(st, self.lib.hough_last_error(self._h).decode())
+
+    def _stream(self, stream):
+        torch = self._torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def output_bounds(self, n_events: int, n_hits: int):
+        mc = ctypes.c_int64()
+        mh = ctypes.c_int64()
+        st = self.lib.hough_output_bounds(self._h, n_events, n_hits, ctypes.byref(mc), ctypes.byref(mh))
+        if st != HOUGH_OK:
+            raise self._err(st)
+        return mc.value, mh.value
+
+    def alloc_outputs(self, n_events: int, n_hits: int) -> FindOutput:
+        torch = self._torch
+        mc, mh = self.output_bounds(n_events, n_hits)
+        dev = torch.device("cuda", self.device)
+        return FindOutput(torch.empty((max(mc, 1), 40), dtype=torch.uint8, device=dev),
+                          torch.empty(max(mh, 1), dtype=torch.int32, device=dev),
+                          torch.empty(HOUGH_COUNTS, dtype=torch.int64, device=dev))
+
+    def find(self, z, vane, offsets, out: Optional[FindOutput] = None, stream=None,
+             capacities=None) -> FindOutput:
+        """Runs the finder on device tensors z (float32), vane (int16), offsets (int64)."""
+        torch = self._torch
+        assert z.dtype == torch.float32 and vane.dtype == torch.int16 and offsets.dtype == torch.int64
+        assert z.is_contiguous() and vane.is_contiguous() and offsets.is_contiguous()
+        n_events = offsets.numel() - 1
+        n_hits = z.numel()
+        if out is None:
+            out = self.alloc_outputs(n_events, n_hits)
+        cc, hc = capacities if capacities is not None else (out.cand.shape[0], out.hit_index.numel())
+        st = self.lib.hough_find(self._h, self._stream(stream), n_events, n_hits,
+                                 ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                 ctypes.c_void_p(vane.data_ptr()), ctypes.c_void_p(out.cand.data_ptr()), cc,
+                                 ctypes.c_void_p(out.hit_index.data_ptr()), hc,
+                                 ctypes.c_void_p(out.counts.data_ptr()))
+        if st != HOUGH_OK:
+            raise self._err(st)
+        return out
+
+    def find_host(self, z, vane, offsets):
+        """Copies numpy hits to the device, runs, and returns host results."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        zt = torch.from_numpy(np.ascontiguousarray(z, np.float32)).to(dev)
+        vt = torch.from_numpy(np.ascontiguousarray(vane, np.int16)).to(dev)
+        ot = torch.from_numpy(np.ascontiguousarray(offsets, np.int64)).to(dev)
+        out = self.find(zt, vt, ot)
+        torch.cuda.synchronize(dev)
+        return out.to_host()
+
+    def debug_accumulator(self, z, vane, iters: int = 0, stream=None):
+        """(uint32 numpy [n_theta, n_rho], counts dict) for one event."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        zt = torch.as_tensor(np.ascontiguousarray(z, np.float32)).to(dev)
+        vt = torch.as_tensor(np.ascontiguousarray(vane, np.int16)).to(dev)
+        acc = torch.empty(self.config.n_theta * self.config.n_rho, dtype=torch.int32, device=dev)
+        counts = torch.empty(HOUGH_COUNTS, dtype=torch.int64, device=dev)
+        st = self.lib.hough_debug_accumulator(self._h, self._stream(stream), zt.numel(),
+                                              ctypes.c_void_p(zt.data_ptr()), ctypes.c_void_p(vt.data_ptr()),
+                                              iters, ctypes.c_void_p(acc.data_ptr()),
+                                              ctypes.c_void_p(counts.data_ptr()))
+        if st != HOUGH_OK:
+            raise self._err(st)
+        torch.cuda.synchronize(dev)
+        a = acc.cpu().numpy().view(np.uint32).reshape(self.config.n_theta, self.config.n_rho)
+        return a, dict(zip(COUNT_NAMES, (int(x) for x in counts.cpu().numpy())))
+
+    def tables(self):
+        c = self.config
+        cos_t = np.empty(c.n_theta, np.float32)
+        sin_t = np.empty(c.n_theta, np.float32)
+        phi_v = np.empty(c.n_vanes, np.float32)
+        theta_c = np.empty(c.n_theta, np.float32)
+        rho_c = np.empty(c.n_rho, np.float32)
+        inv_w = np.empty(1, np.float32)
+        P = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        st = self.lib.hough_tables(self._h, P(cos_t), P(sin_t), P(phi_v), P(inv_w), P(theta_c), P(rho_c))
+        if st != HOUGH_OK:
+            raise self._err(st)
+        return cos_t, sin_t, phi_v, inv_w[0], theta_c, rho_c
+
+    def launch_shape(self):
+        t = ctypes.c_int32()
+        w = ctypes.c_int32()
+        l = ctypes.c_int32()  # noqa: E741
+        self.lib.hough_launch_shape(self._h, ctypes.byref(t), ctypes.byref(w), ctypes.byref(l))
+        return {"tile_rows": t.value, "wg_threads": w.value, "lds_bytes": l.value}
+
+    def set_timing(self, enable: bool):
+        self.lib.hough_set_timing(self._h, 1 if enable else 0)
+
+    def timing(self, reset: bool = True):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        st = self.lib.hough_timing(self._h, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0)
+        if st != HOUGH_OK:
+            raise self._err(st)
+        return ms.value, n.value

@@ -1,0 +1,79 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, and rejects bad input before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hough_tf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hough_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2511_02742_amd import hough
+    lib = hough.load_library()
+    names = _declared()
+    assert "hough_find" in names and "hough_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(hough.EXPORTS) == set(names)
+
+
+def test_config_default_and_status_strings():
+    from paper_2511_02742_amd import hough
+    cfg = hough.default_config()
+    assert (cfg.n_theta, cfg.n_rho, cfg.min_votes, cfg.peak_mode, cfg.nms_radius) == (1024, 1024, 6, 1, 1)
+    assert cfg.rho_min == -500.0 and cfg.rho_max == 500.0 and cfg.n_vanes == 40
+    lib = hough.load_library()
+    assert lib.hough_status_string(0) == b"ok"
+    assert lib.hough_status_string(-6) == b"invalid hit data"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Compiles the public header with the host C compiler and compares the
+    struct layouts with the Python binding's."""
+    import subprocess
+    from paper_2511_02742_amd import hough
+    src = tmp_path / "layout.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"hough_tf.h\"\n"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(hough_config),"
+        " offsetof(hough_config, min_votes), offsetof(hough_config, reserved), sizeof(hough_candidate),"
+        " offsetof(hough_candidate, hit_offset), offsetof(hough_candidate, rho)); return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(hough.HoughConfig), hough.HoughConfig.min_votes.offset,
+            hough.HoughConfig.reserved.offset, hough.cand_dtype.itemsize,
+            hough.cand_dtype.fields["hit_offset"][1], hough.cand_dtype.fields["rho"][1]]
+    assert got == want
+
+
+@pytest.mark.parametrize("field,value", [("n_theta", 0), ("min_votes", 0), ("peak_mode", 2),
+                                         ("rho_max", -600.0), ("wg_threads", 128), ("nms_radius", 17)])
+def test_create_rejects_bad_config(field, value):
+    from paper_2511_02742_amd import hough
+    cfg = hough.default_config(**{field: value})
+    lib = hough.load_library()
+    h = ctypes.c_void_p()
+    st = lib.hough_create(ctypes.byref(cfg), 0, ctypes.byref(h))
+    assert st == hough.HOUGH_ERR_INVALID_ARG
+    assert not h.value
+    assert lib.hough_last_error(None)
+
+
+def test_null_and_bad_context_rejected():
+    from paper_2511_02742_amd import hough
+    lib = hough.load_library()
+    assert lib.hough_destroy(None) == 0
+    mc, mh = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.hough_output_bounds(None, 1, 10, ctypes.byref(mc), ctypes.byref(mh)) == hough.HOUGH_ERR_INVALID_ARG
+    assert lib.hough_find(None, None, 1, 0, None, None, None, None, 0, None, 0, None) == \
+        hough.HOUGH_ERR_INVALID_ARG
