@@ -70,9 +70,6 @@ def main():
     for _ in range(args.warmup):
         f.find(z, vane, offs, out=out, stream=stream)
     torch.cuda.synchronize(dev)
-    info = dict(zip(("candidates", "hits", "status", "detail", "votes", "iters", "max_iters", "passes"),
-                    (int(x) for x in out.counts.cpu().numpy())))
-    assert info["status"] == 0, info
     f.set_timing(True)
     f.timing(reset=True)
     torch.cuda.synchronize(dev)
@@ -83,6 +80,9 @@ def main():
     t2 = time.perf_counter()
     f.set_timing(False)
     kern_ms, launches = f.timing(reset=True)
+    info = dict(zip(("candidates", "hits", "status", "detail", "votes", "iters", "max_iters", "passes"),
+                    (int(x) for x in out.counts.cpu().numpy())))
+    assert info["status"] == 0, info
     wall = t2 - t1
     ms_per_step = 1e3 * wall / args.steps
     value = N_EVENTS * args.steps / wall

@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
-constexpr int kAssocMinBytes = 2048 * 8 + 2048 * 12;  // one peak at the largest event
+constexpr int kAssocMinBytes = 2048 * 20 + 64;  // one peak at the largest event (2048 chunks)
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
 
 struct Ctx {
@@ -117,28 +117,37 @@ void build_tables(Ctx &c) {
     for (int k = 0; k < g.n_rho; ++k) c.rho_c[k] = (float)((double)g.rho_min + (k + 0.5) * width / (double)g.n_rho);
 }
 
-// Picks the LDS tile: as many theta rows as fit the per-workgroup LDS next to
-// the hot list and the peak list (one workgroup per compute unit).
+// Picks the LDS tile: the own theta rows plus the 2w halo rows make a
+// multiple of the waves per workgroup (each wave owns whole rows), as many as
+// fit the per-workgroup LDS next to the hot list and the peak lists.
 hough_status choose_shape(Ctx &c, std::string &why) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c.device) != hipSuccess) { why = "hipGetDeviceProperties failed"; return HOUGH_ERR_DEVICE; }
     const int lds_max = (int)prop.sharedMemPerBlock;
     const hough_config &g = c.cfg;
+    c.wg_threads = g.wg_threads > 0 ? g.wg_threads : 1024;
+    const int nw = c.wg_threads / 64;
     c.pitch = (g.n_rho + 3) & ~3;
     const int halo = g.peak_mode == 1 ? g.nms_radius : 0;
-    const int extra = 4 * kHotCap + 8 * (kHotCap + kPeakKeep) + kStaticLds;
+    const int extra = hough::find_lds_extra(c.wg_threads, kHotCap, kPeakKeep) + kStaticLds;
     const int row_bytes = 4 * c.pitch;
-    int rows_fit = (lds_max - extra) / row_bytes - 2 * halo;
-    if (rows_fit < 1) { why = "n_rho too large for the LDS tile"; return HOUGH_ERR_INVALID_ARG; }
-    int rows = g.tile_rows > 0 ? g.tile_rows : std::min(rows_fit, 32);
+    const int total_fit = (lds_max - extra) / row_bytes;
+    if (total_fit - 2 * halo < 1) { why = "n_rho too large for the LDS tile"; return HOUGH_ERR_INVALID_ARG; }
+    int rows;
+    if (g.tile_rows > 0) {
+        rows = g.tile_rows;
+    } else {
+        int total = (total_fit / nw) * nw;
+        if (total - 2 * halo < 1) total = total_fit;
+        rows = total - 2 * halo;
+    }
     rows = std::min(rows, g.n_theta);
-    if (rows > rows_fit) { why = "tile_rows does not fit in LDS"; return HOUGH_ERR_INVALID_ARG; }
+    if (rows + 2 * halo > total_fit) { why = "tile_rows does not fit in LDS"; return HOUGH_ERR_INVALID_ARG; }
     c.tile_rows = rows;
     c.tile_bytes = std::max(row_bytes * (rows + 2 * halo), kAssocMinBytes);
     c.tile_bytes = (c.tile_bytes + 15) & ~15;
-    c.lds_bytes = c.tile_bytes + 4 * kHotCap + 8 * (kHotCap + kPeakKeep);
+    c.lds_bytes = c.tile_bytes + hough::find_lds_extra(c.wg_threads, kHotCap, kPeakKeep);
     if (c.lds_bytes + kStaticLds > lds_max) { why = "LDS budget exceeded"; return HOUGH_ERR_INVALID_ARG; }
-    c.wg_threads = g.wg_threads > 0 ? g.wg_threads : 1024;
     if (hough::set_find_lds_limit(c.wg_threads, c.lds_bytes) != hipSuccess) {
         why = "hipFuncSetAttribute failed for the finder kernel";
         return HOUGH_ERR_DEVICE;
@@ -235,6 +244,8 @@ hough::FindArgs find_args(const Ctx &c) {
     a.tile_bytes = c.tile_bytes;
     a.hcap = kHotCap;
     a.pkeep = kPeakKeep;
+    a.stream_ok = (c.wg_threads / 64) * c.pitch * 4 <= c.tile_bytes &&
+                  2 * 4 * (2 * (kPeakKeep + kHotCap)) <= c.tile_bytes ? 1 : 0;
     return a;
 }
 

@@ -39,6 +39,7 @@ struct FindArgs {
     int32_t tile_bytes;  // LDS bytes of the tile / association union
     int32_t hcap;        // hot-list capacity per tile
     int32_t pkeep;       // peak entries kept after a compaction; pkeep + hcap is a power of 2
+    int32_t stream_ok;   // tile holds one row buffer per wave: row-stream sweep allowed
 };
 
 struct DumpArgs {
@@ -77,6 +78,8 @@ hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_dump(const DumpArgs &a, int lds_bytes, hipStream_t s);
 hipError_t launch_set_offsets(int64_t *offsets, int64_t n, hipStream_t s);
 hipError_t set_find_lds_limit(int wg_threads, int lds_bytes);
+// LDS bytes of k_find beyond the tile (hot list, peak lists, dummies).
+int find_lds_extra(int wg_threads, int hcap, int pkeep);
 hipError_t set_dump_lds_limit(int lds_bytes);
 
 }  // namespace hough

@@ -2,20 +2,24 @@
 //
 // One workgroup owns one event for the whole loop (paper Sec. 6: one block
 // per time window, one thread per hit). Per iteration it
-//   1. compacts the hits still in the pool into an alive list,
-//   2. sweeps the theta rows in LDS tiles of `tile_rows` rows (plus w halo
-//      rows on each side for the window test): zero the tile, let every
-//      alive hit vote once per row (Eq. (4)) with an LDS atomic add that
-//      returns the old count, and record in a hot list every bin whose count
-//      just reached T -- only those bins can be peaks, so the tile is never
-//      scanned;
+//   1. compacts the hits still in the pool into an alive list; every wave
+//      then holds the alive hits in registers, 64 per chunk;
+//   2. sweeps the theta rows in LDS tiles (plus w halo rows on each side
+//      for the window test). Each wave owns whole tile rows: it zeroes them
+//      and lets every alive hit vote once per row (Eq. (4)) with an LDS
+//      atomic add that returns the old count, so a row needs no workgroup
+//      barrier between its zeroing and its votes, and the chunks of a row
+//      keep several atomics in flight. A vote that lifts a bin to T records
+//      the bin in a hot list: only those bins can be peaks, so the tile is
+//      never scanned;
 //   3. tests each hot bin against its (2w+1)^2 window (nms) or keeps the
 //      largest key (argmax), collecting peak keys in an LDS list that is
 //      sorted and truncated when it fills (the dropped keys are handled by a
 //      further pass over the same histogram);
-//   4. associates hits with the peaks in descending key order using wave
-//      ballots: a 64-bit mask per (peak, 64 alive hits), then one wave
-//      resolves the claims peak by peak, then all waves write the hit lists.
+//   4. associates hits with the peaks in descending key order: a ballot
+//      mask per (peak, chunk) from the register-resident hits, then one wave
+//      resolves the claims peak by peak with DPP prefix sums, then all waves
+//      write the hit lists.
 // The histogram never leaves LDS; HBM sees the hits, the alive list and the
 // candidates only.
 //
@@ -33,6 +37,7 @@ namespace hough {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
 
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -45,19 +50,16 @@ __device__ __forceinline__ int mbcnt64(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
+// Inclusive prefix sum over the 64 lanes with DPP moves: shifts by 1, 2, 4
+// and 8 inside each row of 16 lanes, then the row totals are carried with the
+// lane-15 and lane-31 broadcasts. Lanes whose source is out of range add 0.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-    const int l = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        int t = __shfl_up(v, o, kWave);
-        if (l >= o) v += t;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
@@ -106,25 +108,63 @@ __device__ __forceinline__ int next_pow2(int v) {
 }
 
 struct Shared {
-    int hot;
+    int hotc[2];
+    int hs_cnt;
     int pcnt;
     int nalive;
     int ncand;
     int nhit;
+    int nemit;
     int bad;
     unsigned long long maxdrop;
     unsigned long long best;
     int wtot[16];
-    int emit[64];
 };
+
+// LDS layout of k_find (dynamic part):
+//   [0, tile_bytes)        tile rows, reused by the association phase
+//   hot[hcap]              u32, (tile row << 16) | k
+//   pbuf[pkeep + hcap]     u64 peak keys
+//   dec[pkeep + hcap]      int2 (theta bin, rho bin) of the sorted peaks
+//   dummy[threads]         u32, one word per lane for masked-off votes
+//   hs[pkeep + hcap]       u64 keys of every bin that reached T (row-stream
+//                          sweep), later the sorted peak keys
+struct Lds {
+    uint32_t *tile;
+    uint32_t *hot;
+    unsigned long long *pbuf;
+    int2 *dec;
+    uint32_t *dummy;
+    unsigned long long *hs;
+};
+
+// The alive hits of one register batch: chunk ch holds alive-list entries
+// (batch * kChunks + ch) * 64 + lane.
+struct HitRegs {
+    float phi[kChunks];
+    float z[kChunks];
+    int nch;  // chunks present in this batch (uniform)
+};
+
+__device__ __forceinline__ void load_batch(const FindArgs &A, int64_t b, int n_alive, int batch, HitRegs &h) {
+    const int lane = lane_id();
+    const int ch0 = batch * kChunks;
+    const int nchunks = (n_alive + kWave - 1) / kWave;
+    h.nch = min(kChunks, nchunks - ch0);
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const int q = (ch0 + c) * kWave + lane;
+        const bool v = c < h.nch && q < n_alive;
+        h.phi[c] = v ? A.aphi[b + q] : 0.0f;
+        h.z[c] = v ? A.az[b + q] : 0.0f;
+    }
+}
 
 // Window test of bin (tr, k) of the tile (tile row tr = theta row lo + tr)
 // and insertion of its key into the peak list.
-template <int NT>
-__device__ __forceinline__ void test_bin(const FindArgs &A, const uint32_t *tile, int tr, int k, int lo,
-                                         unsigned long long ceil_key, unsigned long long *pbuf,
-                                         Shared &sh) {
-    const uint32_t c = tile[tr * A.pitch + k];
+__device__ __forceinline__ void test_bin(const FindArgs &A, const Lds &L, int tr, int k, int lo,
+                                         unsigned long long ceil_key, Shared &sh) {
+    const uint32_t c = L.tile[tr * A.pitch + k];
     const int j = lo + tr;
     const unsigned long long key = bin_key(c, (uint32_t)(j * A.n_rho + k));
     if (A.peak_mode == 0) {
@@ -133,104 +173,324 @@ __device__ __forceinline__ void test_bin(const FindArgs &A, const uint32_t *tile
     }
     const int w = A.nms_radius;
     bool peak = true;
-    for (int dr = -w; dr <= w && peak; ++dr) {
-        const int jj = j + dr;
-        if (jj < 0 || jj >= A.n_theta) continue;
-        const uint32_t *row = tile + (tr + dr) * A.pitch;
-        for (int dk = -w; dk <= w; ++dk) {
-            const int kk = k + dk;
-            if (kk < 0 || kk >= A.n_rho || (dr == 0 && dk == 0)) continue;
-            const uint32_t nc = row[kk];
-            const bool earlier = dr < 0 || (dr == 0 && dk < 0);
-            if (nc > c || (earlier && nc == c)) {
-                peak = false;
-                break;
+    if (w == 1) {
+        // the eight neighbours, read together; absent ones count as 0 < c
+        const bool up = j > 0, dn = j + 1 < A.n_theta, lf = k > 0, rt = k + 1 < A.n_rho;
+        const uint32_t *r0 = L.tile + (tr - 1) * A.pitch;
+        const uint32_t *r1 = L.tile + tr * A.pitch;
+        const uint32_t *r2 = L.tile + (tr + 1) * A.pitch;
+        const uint32_t a0 = up && lf ? r0[k - 1] : 0u, a1 = up ? r0[k] : 0u, a2 = up && rt ? r0[k + 1] : 0u;
+        const uint32_t b0 = lf ? r1[k - 1] : 0u, b2 = rt ? r1[k + 1] : 0u;
+        const uint32_t c0 = dn && lf ? r2[k - 1] : 0u, c1 = dn ? r2[k] : 0u, c2 = dn && rt ? r2[k + 1] : 0u;
+        // neighbours with a lower flat index (row above, left) win ties
+        peak = a0 < c && a1 < c && a2 < c && b0 < c && b2 <= c && c0 <= c && c1 <= c && c2 <= c;
+    } else {
+        for (int dr = -w; dr <= w; ++dr) {
+            const int jj = j + dr;
+            if (jj < 0 || jj >= A.n_theta) continue;
+            const uint32_t *row = L.tile + (tr + dr) * A.pitch;
+            for (int dk = -w; dk <= w; ++dk) {
+                const int kk = k + dk;
+                if (kk < 0 || kk >= A.n_rho || (dr == 0 && dk == 0)) continue;
+                const uint32_t nc = row[kk];
+                const bool earlier = dr < 0 || (dr == 0 && dk < 0);
+                peak = peak && !(nc > c || (earlier && nc == c));
             }
         }
     }
     if (peak && key <= ceil_key && key > sh.maxdrop) {
         int p = atomicAdd(&sh.pcnt, 1);
-        pbuf[p] = key;
+        L.pbuf[p] = key;
     }
 }
 
 // Keeps the pkeep largest keys when the peak list holds more; the largest
 // dropped key becomes the floor below which later keys are refused.
 template <int NT>
-__device__ void maybe_truncate(const FindArgs &A, unsigned long long *pbuf, Shared &sh) {
+__device__ void maybe_truncate(const FindArgs &A, const Lds &L, Shared &sh) {
     const int cnt = sh.pcnt;
     if (cnt <= A.pkeep) return;
     const int cap = A.pkeep + A.hcap;
-    for (int i = cnt + threadIdx.x; i < cap; i += NT) pbuf[i] = 0ull;
+    for (int i = cnt + threadIdx.x; i < cap; i += NT) L.pbuf[i] = 0ull;
     __syncthreads();
-    sort_desc<NT>(pbuf, cap);
+    sort_desc<NT>(L.pbuf, cap);
     if (threadIdx.x == 0) {
-        unsigned long long d = pbuf[A.pkeep];
+        unsigned long long d = L.pbuf[A.pkeep];
         if (d > sh.maxdrop) sh.maxdrop = d;
         sh.pcnt = A.pkeep;
     }
     __syncthreads();
 }
 
+// Votes of the NCH register chunks into the tile rows this wave owns
+// (tr = wave, wave + NW, ...). Straight-line code per row, so the NCH LDS
+// atomics of a row are in flight together. Lane i fetches the (c, s) pair of
+// the wave's i-th row with one vector load (its wait does not depend on the
+// LDS queue, unlike a scalar load) and each row reads it with v_readlane.
+template <int NT, int NCH>
+__device__ __forceinline__ void vote_rows(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L,
+                                          const HitRegs &h, int qbase, int n_alive, int lo, int rows,
+                                          int own_lo, int own_hi, int *hotc) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const uint32_t tm1 = A.min_votes - 1u;
+    uint32_t *const my_dummy = L.dummy + threadIdx.x;
+    bool valid[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) valid[c] = (qbase + c * kWave) < n_alive;
+    const int rpw = (rows - wave + NW - 1) / NW;  // rows owned by this wave (<= 64)
+    const int lane = lane_id();
+    const float2 mine = lane < rpw ? cs[lo + wave + NW * lane] : make_float2(0.0f, 0.0f);
+    for (int i = 0; i < rpw; ++i) {
+        const int tr = wave + NW * i;
+        float2 t;
+        t.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
+        t.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
+        uint32_t *const row = L.tile + tr * A.pitch;
+        uint32_t old[NCH];
+        int kk[NCH];
+        bool in[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            kk[c] = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+            in[c] = valid[c] && (unsigned)kk[c] < (unsigned)A.n_rho;
+            old[c] = atomicAdd(in[c] ? row + kk[c] : my_dummy, 1u);
+        }
+        if (tr >= own_lo && tr < own_hi) {
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) any = any || (in[c] && old[c] == tm1);
+            if (__ballot(any) != 0ull) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    if (in[c] && old[c] == tm1) {
+                        const int slot = atomicAdd(hotc, 1);
+                        if (slot < A.hcap) L.hot[slot] = ((uint32_t)tr << 16) | (uint32_t)kk[c];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Row-stream sweep: every wave owns the theta rows j = wave, wave + NW, ...
+// and a private one-row LDS buffer (kept all-zero between rows). Per row it
+// votes the NCH register chunks, reads back the final count of every bin its
+// votes lifted to T (only this wave writes the row, and the LDS operations of
+// a wave are performed in order, so no barrier is needed), appends those
+// bins to the workgroup hot set, and restores the buffer to zero by writing
+// 0 to the addresses it voted. The window test runs afterwards on the hot set:
+// a bin below T can never beat a bin that reached T.
+template <int NT, int NCH>
+__device__ __forceinline__ void stream_rows(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L,
+                                            const HitRegs &h, int n_alive, Shared &sh) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    const uint32_t tm1 = A.min_votes - 1u;
+    const int hs_cap = A.pkeep + A.hcap;
+    uint32_t *const rowbuf = L.tile + wave * A.pitch;
+    uint32_t *const my_dummy = L.dummy + threadIdx.x;
+    bool valid[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) valid[c] = c * kWave + lane < n_alive;
+    for (int jb = wave; jb < A.n_theta; jb += NW * kWave) {
+        const int nr = min(kWave, (A.n_theta - jb + NW - 1) / NW);
+        const float2 mine = lane < nr ? cs[jb + NW * lane] : make_float2(0.0f, 0.0f);
+        for (int i = 0; i < nr; ++i) {
+            const int j = jb + NW * i;
+            float2 t;
+            t.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
+            t.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
+            uint32_t *addr[NCH];
+            uint32_t old[NCH];
+            bool hot[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+                const bool in = valid[c] && (unsigned)k < (unsigned)A.n_rho;
+                addr[c] = in ? rowbuf + k : my_dummy;
+                old[c] = atomicAdd(addr[c], 1u);
+                hot[c] = in && old[c] == tm1;
+            }
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) any = any || hot[c];
+            if (__ballot(any) != 0ull) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    if (hot[c]) {
+                        const uint32_t cnt = *addr[c];
+                        const int k = (int)(addr[c] - rowbuf);
+                        const int slot = atomicAdd(&sh.hs_cnt, 1);
+                        if (slot < hs_cap) L.hs[slot] = bin_key(cnt, (uint32_t)(j * A.n_rho + k));
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) *addr[c] = 0u;
+        }
+    }
+}
+
+template <int NT>
+__device__ void stream_sweep(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
+                             int n_alive, Shared &sh) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    // the row buffers may hold the previous pass's association data
+    uint4 *r4 = reinterpret_cast<uint4 *>(L.tile + wave * A.pitch);
+    for (int x = lane; x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
+    if (lane < kWave) L.dummy[threadIdx.x] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    switch (h.nch) {
+    case 1: stream_rows<NT, 1>(A, cs, L, h, n_alive, sh); break;
+    case 2: stream_rows<NT, 2>(A, cs, L, h, n_alive, sh); break;
+    case 3: stream_rows<NT, 3>(A, cs, L, h, n_alive, sh); break;
+    case 4: stream_rows<NT, 4>(A, cs, L, h, n_alive, sh); break;
+    case 5: stream_rows<NT, 5>(A, cs, L, h, n_alive, sh); break;
+    case 6: stream_rows<NT, 6>(A, cs, L, h, n_alive, sh); break;
+    case 7: stream_rows<NT, 7>(A, cs, L, h, n_alive, sh); break;
+    default: stream_rows<NT, 8>(A, cs, L, h, n_alive, sh); break;
+    }
+    (void)NW;
+}
+
+__device__ __forceinline__ uint32_t hs_hash(uint32_t flat, int log2n) {
+    return (flat * 2654435761u) >> (32 - log2n);
+}
+
+// Peaks among the n_hs hot bins (keys in L.hs): the window test looks the
+// neighbours up in an LDS hash table keyed by flat index (bins below T are
+// absent and count as 0). Leaves the peak keys sorted in descending order in
+// L.hs and returns their number.
+template <int NT>
+__device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &sh) {
+    if (A.peak_mode == 0) {
+        for (int e = threadIdx.x; e < n_hs; e += NT) atomicMax(&sh.best, L.hs[e]);
+        __syncthreads();
+        const unsigned long long best = sh.best;
+        const int npk = n_hs > 0 ? 1 : 0;
+        __syncthreads();
+        if (threadIdx.x == 0) L.hs[0] = best;
+        __syncthreads();
+        return npk;
+    }
+    int log2n = 6;
+    while ((1 << log2n) < 2 * n_hs) ++log2n;
+    const int ht = 1 << log2n;
+    uint32_t *htk = L.tile;        // flat + 1, 0 = empty
+    uint32_t *htc = L.tile + ht;   // count
+    for (int i = threadIdx.x; i < ht; i += NT) htk[i] = 0u;
+    if (threadIdx.x == 0) sh.pcnt = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n_hs; e += NT) {
+        const unsigned long long key = L.hs[e];
+        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+        uint32_t slot = hs_hash(flat, log2n);
+        while (atomicCAS(&htk[slot], 0u, flat + 1u) != 0u) slot = (slot + 1u) & (uint32_t)(ht - 1);
+        htc[slot] = (uint32_t)(key >> 32);
+    }
+    __syncthreads();
+    const int w = A.nms_radius;
+    for (int e = threadIdx.x; e < n_hs; e += NT) {
+        const unsigned long long key = L.hs[e];
+        const uint32_t c = (uint32_t)(key >> 32);
+        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+        const int j = (int)(flat / (uint32_t)A.n_rho);
+        const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
+        bool peak = true;
+        for (int dr = -w; dr <= w; ++dr) {
+            const int jj = j + dr;
+            if (jj < 0 || jj >= A.n_theta) continue;
+            for (int dk = -w; dk <= w; ++dk) {
+                const int kk = k + dk;
+                if (kk < 0 || kk >= A.n_rho || (dr == 0 && dk == 0)) continue;
+                const uint32_t f2 = (uint32_t)(jj * A.n_rho + kk);
+                uint32_t slot = hs_hash(f2, log2n);
+                uint32_t c2 = 0u;
+                for (;;) {
+                    const uint32_t kf = htk[slot];
+                    if (kf == 0u) break;
+                    if (kf == f2 + 1u) {
+                        c2 = htc[slot];
+                        break;
+                    }
+                    slot = (slot + 1u) & (uint32_t)(ht - 1);
+                }
+                // a neighbour with a lower flat index wins ties
+                if (c2 > c || (c2 == c && f2 < flat)) peak = false;
+            }
+        }
+        if (peak) L.pbuf[atomicAdd(&sh.pcnt, 1)] = key;
+    }
+    __syncthreads();
+    const int npk = sh.pcnt;
+    // rank sort (keys are distinct): descending order into L.hs
+    for (int p = threadIdx.x; p < npk; p += NT) {
+        const unsigned long long key = L.pbuf[p];
+        int r = 0;
+        for (int q = 0; q < npk; ++q) r += L.pbuf[q] > key ? 1 : 0;
+        L.hs[r] = key;
+    }
+    __syncthreads();
+    return npk;
+}
+
 // One pass of the histogram over all theta rows for the current alive list.
 // Leaves the peak keys with key <= ceil_key (and > sh.maxdrop) in pbuf.
 template <int NT>
-__device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t b, uint32_t *tile, uint32_t *hot,
-                      unsigned long long *pbuf, unsigned long long ceil_key, Shared &sh) {
+__device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t b, const Lds &L,
+                      HitRegs &h, int nbatch, unsigned long long ceil_key, Shared &sh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
     const int n_alive = sh.nalive;
     const int w = A.peak_mode == 1 ? A.nms_radius : 0;
-    const int chunks = (n_alive + kWave - 1) / kWave;
-    const int groups = chunks >= NW ? 1 : NW / chunks;
-    const int tasks = chunks * groups;
-    const uint32_t tm1 = A.min_votes - 1u;
+    uint4 *t4 = reinterpret_cast<uint4 *>(L.tile);
+    const int pitch4 = A.pitch / 4;
 
-    for (int j0 = 0; j0 < A.n_theta; j0 += A.tile_rows) {
+    int slab = 0;
+    for (int j0 = 0; j0 < A.n_theta; j0 += A.tile_rows, ++slab) {
         const int own = min(A.tile_rows, A.n_theta - j0);
         const int lo = max(0, j0 - w);
         const int hi = min(A.n_theta, j0 + own + w);
         const int rows = hi - lo;
         const int own_lo = j0 - lo;          // first own tile row
         const int own_hi = own_lo + own;     // one past the last own tile row
+        int *hotc = &sh.hotc[slab & 1];
 
-        uint4 *t4 = reinterpret_cast<uint4 *>(tile);
-        const int n4 = rows * A.pitch / 4;
-        for (int q = threadIdx.x; q < n4; q += NT) t4[q] = make_uint4(0u, 0u, 0u, 0u);
-        if (threadIdx.x == 0) sh.hot = 0;
-        __syncthreads();
-
-        // votes: lanes over hits, waves over (hit chunk, row group)
-        for (int t = wave; t < tasks; t += NW) {
-            const int chunk = t % chunks;
-            const int grp = t / chunks;
-            const int q = chunk * kWave + lane;
-            const bool valid = q < n_alive;
-            const float phi = valid ? A.aphi[b + q] : 0.0f;
-            const float zz = valid ? A.az[b + q] : 0.0f;
-            for (int tr = grp; tr < rows; tr += groups) {
-                const float2 t = cs[lo + tr];
-                const int k = rho_bin(phi, zz, t.x, t.y, A.rho_min, A.inv_w);
-                if (valid && (unsigned)k < (unsigned)A.n_rho) {
-                    const uint32_t old = atomicAdd(&tile[tr * A.pitch + k], 1u);
-                    if (old == tm1 && tr >= own_lo && tr < own_hi) {
-                        int h = atomicAdd(&sh.hot, 1);
-                        if (h < A.hcap) hot[h] = ((uint32_t)tr << 16) | (uint32_t)k;
-                    }
-                }
+        // each wave zeroes the rows it owns, then votes into them; the LDS
+        // operations of one wave are performed in program order
+        for (int tr = wave; tr < rows; tr += NW)
+            for (int x = lane; x < pitch4; x += kWave) t4[tr * pitch4 + x] = make_uint4(0u, 0u, 0u, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        for (int bt = 0; bt < nbatch; ++bt) {
+            if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
+            const int qbase = bt * kChunks * kWave + lane;
+            switch (h.nch) {
+            case 1: vote_rows<NT, 1>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            case 2: vote_rows<NT, 2>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            case 3: vote_rows<NT, 3>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            case 4: vote_rows<NT, 4>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            case 5: vote_rows<NT, 5>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            case 6: vote_rows<NT, 6>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            case 7: vote_rows<NT, 7>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
+            default: vote_rows<NT, 8>(A, cs, L, h, qbase, n_alive, lo, rows, own_lo, own_hi, hotc); break;
             }
         }
         __syncthreads();
 
-        const int nhot = sh.hot;
+        const int nhot = *hotc;
+        if (threadIdx.x == 0) sh.hotc[(slab + 1) & 1] = 0;
         if (nhot <= A.hcap) {
-            for (int h = threadIdx.x; h < nhot; h += NT) {
-                const uint32_t e = hot[h];
-                test_bin<NT>(A, tile, (int)(e >> 16), (int)(e & 0xffffu), lo, ceil_key, pbuf, sh);
+            for (int e = threadIdx.x; e < nhot; e += NT) {
+                const uint32_t v = L.hot[e];
+                test_bin(A, L, (int)(v >> 16), (int)(v & 0xffffu), lo, ceil_key, sh);
             }
             __syncthreads();
-            if (A.peak_mode == 1) maybe_truncate<NT>(A, pbuf, sh);
+            if (A.peak_mode == 1) maybe_truncate<NT>(A, L, sh);
         } else {
             // hot list overflowed: scan the own rows in chunks of hcap bins
             const int nb = own * A.n_rho;
@@ -240,11 +500,10 @@ __device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t 
                     const int bin = base + q;
                     const int tr = own_lo + bin / A.n_rho;
                     const int k = bin % A.n_rho;
-                    if (tile[tr * A.pitch + k] >= A.min_votes)
-                        test_bin<NT>(A, tile, tr, k, lo, ceil_key, pbuf, sh);
+                    if (L.tile[tr * A.pitch + k] >= A.min_votes) test_bin(A, L, tr, k, lo, ceil_key, sh);
                 }
                 __syncthreads();
-                if (A.peak_mode == 1) maybe_truncate<NT>(A, pbuf, sh);
+                if (A.peak_mode == 1) maybe_truncate<NT>(A, L, sh);
             }
         }
     }
@@ -253,119 +512,172 @@ __device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t 
 // Claims hits for the sorted peaks pbuf[0, npk) of this pass.
 template <int NT>
 __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
-                          unsigned char *uni, int uni_bytes,
-                          const unsigned long long *pbuf, int npk, Shared &sh) {
+                          const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
+                          int npk, Shared &sh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
     const int n_alive = sh.nalive;
     const int W = (n_alive + kWave - 1) / kWave;
-    unsigned long long *iclaimed = reinterpret_cast<unsigned long long *>(uni);
-    unsigned long long *M = iclaimed + W;
-    int pb = (uni_bytes - W * 8) / (W * 12);
-    pb = pb > 64 ? 64 : pb;
-    uint32_t *pref = reinterpret_cast<uint32_t *>(M + (size_t)pb * W);
     const int64_t cbase = b / (int64_t)A.min_votes;
 
-    // hits of the alive list claimed by an earlier pass of this iteration
+    // union area: icl[W] u64 | M[pb * W] u64 | pref[pb * W] u32 | elist[pb] i32
+    unsigned char *uni = reinterpret_cast<unsigned char *>(L.tile);
+    unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni);
+    unsigned long long *M = icl + W;
+    int pb = (uni_bytes - 8 * W) / (12 * W + 4);
+    pb = min(pb, A.pkeep + A.hcap);
+    uint32_t *pref = reinterpret_cast<uint32_t *>(M + (size_t)pb * W);
+    int *elist = reinterpret_cast<int *>(pref + (size_t)pb * W);
+
+    // peak coordinates, and the hits claimed by an earlier pass of this
+    // iteration
+    for (int p = threadIdx.x; p < npk; p += NT) {
+        const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p] & 0xffffffffull);
+        L.dec[p] = make_int2((int)(flat / (uint32_t)A.n_rho), (int)(flat % (uint32_t)A.n_rho));
+    }
     for (int ch = wave; ch < W; ch += NW) {
         const int q = ch * kWave + lane;
         const bool taken = q < n_alive && A.state[b + A.aidx[b + q]] != -1;
         const unsigned long long m = __ballot(taken);
-        if (lane == 0) iclaimed[ch] = m;
+        if (lane == 0) icl[ch] = m;
     }
     __syncthreads();
 
     for (int p0 = 0; p0 < npk; p0 += pb) {
         const int nb = min(pb, npk - p0);
-        // A: match masks of nb peaks
-        for (int t = wave; t < nb * W; t += NW) {
-            const int p = t / W;
-            const int ch = t - p * W;
-            const unsigned long long key = pbuf[p0 + p];
-            const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
-            const int jp = (int)(flat / (uint32_t)A.n_rho);
-            const int kp = (int)(flat % (uint32_t)A.n_rho);
-            const float2 tcs = cs[jp];
-            const int q = ch * kWave + lane;
-            bool hit = false;
-            if (q < n_alive) {
-                const int k = rho_bin(A.aphi[b + q], A.az[b + q], tcs.x, tcs.y, A.rho_min, A.inv_w);
-                const int d = k - kp;
-                hit = (d < 0 ? -d : d) <= A.assoc_window;
+        // A: match masks, from the register-resident hits
+        for (int bt = 0; bt < nbatch; ++bt) {
+            if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
+            const int qbase = bt * kChunks * kWave + lane;
+            for (int p = wave; p < nb; p += NW) {
+                const int2 jk = L.dec[p0 + p];
+                const float2 t = cs[jk.x];
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    if (c < h.nch) {
+                        const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+                        const int d = k - jk.y;
+                        const bool hit = (qbase + c * kWave) < n_alive && (d < 0 ? -d : d) <= A.assoc_window;
+                        const unsigned long long m = __ballot(hit);
+                        if (lane == 0) M[(size_t)p * W + bt * kChunks + c] = m;
+                    }
+                }
             }
-            const unsigned long long m = __ballot(hit);
-            if (lane == 0) M[(size_t)p * W + ch] = m;
         }
         __syncthreads();
         // B: one wave resolves the claims in key order
-        if (wave == 0) {
+        if (wave == 0 && W <= kWave) {
+            // one mask word per lane; the claimed-so-far word stays in a
+            // register and the next peak's masks are fetched ahead
             int ncand = sh.ncand;
             int nhit = sh.nhit;
+            int nemit = 0;
+            unsigned long long mine = lane < W ? icl[lane] : ~0ull;
+            unsigned long long mnext = lane < W ? M[lane] : 0ull;
+            for (int p = 0; p < nb; ++p) {
+                const unsigned long long mp = mnext;
+                if (p + 1 < nb) mnext = lane < W ? M[(size_t)(p + 1) * W + lane] : 0ull;
+                const unsigned long long m = mp & ~mine;
+                const int cnt = __popcll(m);
+                const int incl = wave_incl_scan(cnt);
+                const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                if (total < (int)A.min_votes) continue;
+                mine |= m;
+                if (lane < W) {
+                    M[(size_t)p * W + lane] = m;
+                    pref[(size_t)p * W + lane] = (uint32_t)(nhit + incl - cnt);
+                }
+                if (lane == 0) {
+                    const int2 jk = L.dec[p0 + p];
+                    hough_candidate cd;
+                    cd.event = e;
+                    cd.iter = iter;
+                    cd.theta_bin = jk.x;
+                    cd.rho_bin = jk.y;
+                    cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
+                    cd.n_hits = (uint32_t)total;
+                    cd.hit_offset = nhit;
+                    cd.theta = A.theta_c[jk.x];
+                    cd.rho = A.rho_c[jk.y];
+                    A.cand_ws[cbase + ncand] = cd;
+                    elist[nemit] = p;
+                }
+                ++nemit;
+                ++ncand;
+                nhit += total;
+            }
+            if (lane < W) icl[lane] = mine;
+            if (lane == 0) {
+                sh.nemit = nemit;
+                sh.ncand = ncand;
+                sh.nhit = nhit;
+            }
+        } else if (wave == 0) {
+            int ncand = sh.ncand;
+            int nhit = sh.nhit;
+            int nemit = 0;
             for (int p = 0; p < nb; ++p) {
                 int total = 0;
                 for (int cb = 0; cb < W; cb += kWave) {
                     const int ch = cb + lane;
-                    const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~iclaimed[ch]) : 0ull;
-                    total += wave_sum(__popcll(m));
+                    const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
+                    total += __builtin_amdgcn_readlane(wave_incl_scan(__popcll(m)), kWave - 1);
                 }
-                if (total >= (int)A.min_votes) {
-                    int run = 0;
-                    for (int cb = 0; cb < W; cb += kWave) {
-                        const int ch = cb + lane;
-                        const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~iclaimed[ch]) : 0ull;
-                        const int cnt = __popcll(m);
-                        const int incl = wave_incl_scan(cnt);
-                        if (ch < W) {
-                            pref[(size_t)p * W + ch] = (uint32_t)(nhit + run + incl - cnt);
-                            iclaimed[ch] |= m;
-                            M[(size_t)p * W + ch] = m;
-                        }
-                        run += __shfl(incl, kWave - 1, kWave);
+                if (total < (int)A.min_votes) continue;
+                int run = nhit;
+                for (int cb = 0; cb < W; cb += kWave) {
+                    const int ch = cb + lane;
+                    const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
+                    const int cnt = __popcll(m);
+                    const int incl = wave_incl_scan(cnt);
+                    if (ch < W) {
+                        pref[(size_t)p * W + ch] = (uint32_t)(run + incl - cnt);
+                        icl[ch] |= m;
+                        M[(size_t)p * W + ch] = m;
                     }
-                    if (lane == 0) {
-                        const unsigned long long key = pbuf[p0 + p];
-                        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
-                        const int jp = (int)(flat / (uint32_t)A.n_rho);
-                        const int kp = (int)(flat % (uint32_t)A.n_rho);
-                        hough_candidate cd;
-                        cd.event = e;
-                        cd.iter = iter;
-                        cd.theta_bin = jp;
-                        cd.rho_bin = kp;
-                        cd.peak_votes = (uint32_t)(key >> 32);
-                        cd.n_hits = (uint32_t)total;
-                        cd.hit_offset = nhit;
-                        cd.theta = A.theta_c[jp];
-                        cd.rho = A.rho_c[kp];
-                        A.cand_ws[cbase + ncand] = cd;
-                        sh.emit[p] = ncand;
-                    }
-                    ++ncand;
-                    nhit += total;
-                } else if (lane == 0) {
-                    sh.emit[p] = -1;
+                    run += __builtin_amdgcn_readlane(incl, kWave - 1);
                 }
+                if (lane == 0) {
+                    const int2 jk = L.dec[p0 + p];
+                    hough_candidate cd;
+                    cd.event = e;
+                    cd.iter = iter;
+                    cd.theta_bin = jk.x;
+                    cd.rho_bin = jk.y;
+                    cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
+                    cd.n_hits = (uint32_t)total;
+                    cd.hit_offset = nhit;
+                    cd.theta = A.theta_c[jk.x];
+                    cd.rho = A.rho_c[jk.y];
+                    A.cand_ws[cbase + ncand] = cd;
+                    elist[nemit] = p;
+                }
+                ++nemit;
+                ++ncand;
+                nhit += total;
             }
             if (lane == 0) {
+                sh.nemit = nemit;
                 sh.ncand = ncand;
                 sh.nhit = nhit;
             }
         }
         __syncthreads();
         // C: hit lists (ascending alive-list position = ascending hit index)
-        for (int t = wave; t < nb * W; t += NW) {
-            const int p = t / W;
-            const int ch = t - p * W;
-            const int cid = sh.emit[p];
-            if (cid < 0) continue;
+        const int nemit = sh.nemit;
+        const int cid0 = sh.ncand - nemit;
+        for (int t = wave; t < nemit * W; t += NW) {
+            const int ei = t / W;
+            const int ch = t - ei * W;
+            const int p = elist[ei];
             const unsigned long long m = M[(size_t)p * W + ch];
             if ((m >> lane) & 1ull) {
                 const int q = ch * kWave + lane;
                 const int il = A.aidx[b + q];
                 const int pos = (int)pref[(size_t)p * W + ch] + mbcnt64(m);
                 A.hits_ws[b + pos] = il;
-                A.state[b + il] = cid;
+                A.state[b + il] = cid0 + ei;
             }
         }
         __syncthreads();
@@ -377,9 +689,13 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     constexpr int NW = NT / kWave;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ Shared sh;
-    uint32_t *tile = reinterpret_cast<uint32_t *>(lds);
-    uint32_t *hot = reinterpret_cast<uint32_t *>(lds + A.tile_bytes);
-    unsigned long long *pbuf = reinterpret_cast<unsigned long long *>(lds + A.tile_bytes + 4 * A.hcap);
+    Lds L;
+    L.tile = reinterpret_cast<uint32_t *>(lds);
+    L.hot = reinterpret_cast<uint32_t *>(lds + A.tile_bytes);
+    L.pbuf = reinterpret_cast<unsigned long long *>(lds + A.tile_bytes + 4 * A.hcap);
+    L.dec = reinterpret_cast<int2 *>(L.pbuf + (A.pkeep + A.hcap));
+    L.dummy = reinterpret_cast<uint32_t *>(L.dec + (A.pkeep + A.hcap));
+    L.hs = reinterpret_cast<unsigned long long *>(L.dummy + NT);
 
     const int e = blockIdx.x;
     const int wave = wave_id();
@@ -434,6 +750,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     unsigned long long votes = 0;
     int iter = 0;
     int passes = 0;
+    HitRegs h;
     for (;;) {
         if (A.max_iters > 0 && iter >= A.max_iters) break;
         // alive list, in ascending hit order
@@ -460,39 +777,65 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             __syncthreads();
         }
         if (carry < (int)A.min_votes) break;
-        if (threadIdx.x == 0) sh.nalive = carry;
-        votes += (unsigned long long)carry * (unsigned long long)A.n_theta;
+        const int n_alive = carry;
+        const int nbatch = (n_alive + kChunks * kWave - 1) / (kChunks * kWave);
+        if (threadIdx.x == 0) sh.nalive = n_alive;
+        votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
         const int ncand0 = sh.ncand;
+        if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
 
-        unsigned long long ceil_key = ~0ull;
         bool any = false;
-        for (;;) {
+        bool done = false;
+        if (nbatch == 1 && A.stream_ok) {
+            // row-stream sweep; falls back to the tiled sweep below when more
+            // bins reach T than the hot set holds
+            ++passes;
+            if (threadIdx.x == 0) {
+                sh.hs_cnt = 0;
+                sh.best = 0ull;
+            }
+            __syncthreads();
+            stream_sweep<NT>(A, cs, L, h, n_alive, sh);
+            __syncthreads();
+            const int n_hs = sh.hs_cnt;
+            if (n_hs <= A.pkeep + A.hcap) {
+                done = true;
+                const int npk = hotset_peaks<NT>(A, L, n_hs, sh);
+                if (npk > 0) {
+                    any = true;
+                    associate<NT>(A, cs, e, b, iter, L, L.hs, A.tile_bytes, h, nbatch, npk, sh);
+                }
+            }
+        }
+        unsigned long long ceil_key = ~0ull;
+        for (; !done;) {
             ++passes;
             if (threadIdx.x == 0) {
                 sh.pcnt = 0;
                 sh.maxdrop = 0ull;
                 sh.best = 0ull;
+                sh.hotc[0] = 0;
             }
             __syncthreads();
-            sweep<NT>(A, cs, b, tile, hot, pbuf, ceil_key, sh);
+            sweep<NT>(A, cs, b, L, h, nbatch, ceil_key, sh);
             int npk;
             if (A.peak_mode == 0) {
                 const unsigned long long best = sh.best;
                 npk = (uint32_t)(best >> 32) >= A.min_votes ? 1 : 0;
                 __syncthreads();
-                if (threadIdx.x == 0) pbuf[0] = best;
+                if (threadIdx.x == 0) L.pbuf[0] = best;
             } else {
                 npk = sh.pcnt;
                 const int cap = next_pow2(npk);
-                for (int i = npk + threadIdx.x; i < cap; i += NT) pbuf[i] = 0ull;
+                for (int i = npk + threadIdx.x; i < cap; i += NT) L.pbuf[i] = 0ull;
                 __syncthreads();
-                if (npk > 1) sort_desc<NT>(pbuf, cap);
+                if (npk > 1) sort_desc<NT>(L.pbuf, cap);
             }
             __syncthreads();
             if (npk == 0) break;
             any = true;
             const unsigned long long drop = sh.maxdrop;
-            associate<NT>(A, cs, e, b, iter, lds, A.tile_bytes, pbuf, npk, sh);
+            associate<NT>(A, cs, e, b, iter, L, L.pbuf, A.tile_bytes, h, nbatch, npk, sh);
             if (drop == 0ull) break;
             ceil_key = drop;
         }
@@ -638,6 +981,11 @@ __global__ __launch_bounds__(1024) void k_dump(DumpArgs A, const float2 *__restr
 }
 
 }  // namespace
+
+int find_lds_extra(int wg_threads, int hcap, int pkeep) {
+    // hot list, peak keys, decoded peaks, one dummy word per thread, hot set
+    return 4 * hcap + 8 * (pkeep + hcap) + 8 * (pkeep + hcap) + 4 * wg_threads + 8 * (pkeep + hcap);
+}
 
 hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, stats, err);
