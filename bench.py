@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--plain-events", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this size first, as the reference kernel for "
+                         "FETCH_SIZE / WRITE_SIZE counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -61,6 +64,15 @@ def main():
     vane = torch.from_numpy(batch.vane).to(dev)
     offs = torch.from_numpy(batch.offsets).to(dev)
 
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        log("copy calibration: %d bytes read, %d bytes written" % (nb, nb))
+        del src, dst
+
     f = HoughFinder(0)
     shape = f.launch_shape()
     out = f.alloc_outputs(N_EVENTS, batch.n_hits)
@@ -80,8 +92,8 @@ def main():
     t2 = time.perf_counter()
     f.set_timing(False)
     kern_ms, launches = f.timing(reset=True)
-    info = dict(zip(("candidates", "hits", "status", "detail", "votes", "iters", "max_iters", "passes"),
-                    (int(x) for x in out.counts.cpu().numpy())))
+    from paper_2511_02742_amd.hough import COUNT_NAMES
+    info = dict(zip(COUNT_NAMES, (int(x) for x in out.counts.cpu().numpy())))
     assert info["status"] == 0, info
     wall = t2 - t1
     ms_per_step = 1e3 * wall / args.steps
@@ -115,13 +127,13 @@ def main():
                                                               1e6 * np.percentile(lat, 99)))
 
     # ---- roofline of the finder kernel ------------------------------------
-    flops = FLOPS_PER_VOTE * info["votes"]
+    flops = FLOPS_PER_VOTE * info["evals"]
     achieved = flops / (kern_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TFLOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
                 "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
-                "votes_per_launch": info["votes"], "flops_per_vote": FLOPS_PER_VOTE,
-                "votes_per_s": round(info["votes"] / (kern_avg_ms * 1e-3), 1)}
+                "evals_per_launch": info["evals"], "flops_per_eval": FLOPS_PER_VOTE,
+                "evals_per_s": round(info["evals"] / (kern_avg_ms * 1e-3), 1)}
 
     # ---- CPU oracle on a bounded sample -----------------------------------
     cpu = None
@@ -154,8 +166,8 @@ def main():
                   "latency_us_p99": round(1e6 * float(np.percentile(lat, 99)), 2)},
         "batched_latency_ms_p99": round(ms_per_step, 4),
         "speedup_batched_vs_plain": round(value / plain_rate, 2),
-        "work": {"candidates": info["candidates"], "assigned_hits": info["hits"], "iters": info["iters"],
-                 "max_iters": info["max_iters"], "passes": info["passes"]},
+        "work": {k: info[k] for k in ("candidates", "hits", "evals", "iters", "max_iters", "passes", "tiled",
+                                      "truncations", "hot_scans", "hotset_full", "recounts")},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

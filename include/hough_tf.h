@@ -81,7 +81,11 @@ typedef struct {
     /* launch shape; 0 picks the tuned default                               */
     int32_t  tile_rows;      /* theta rows per LDS tile                      */
     int32_t  wg_threads;     /* threads per workgroup: 256, 512 or 1024      */
-    int32_t  reserved[4];    /* must be 0                                    */
+    int32_t  sweep_groups;   /* workgroups per event for the first histogram
+                                sweep, run as a separate kernel; 0 = the
+                                finder's own workgroup sweeps               */
+    int32_t  sweep_threads;  /* threads per sweep workgroup (256/512/1024)  */
+    int32_t  reserved[2];    /* must be 0                                    */
 } hough_config;
 
 /*
@@ -101,17 +105,22 @@ typedef struct {
 } hough_candidate;
 
 /* counts[] written by hough_find (device, int64, HOUGH_COUNTS entries) */
-#define HOUGH_COUNTS 8
+#define HOUGH_COUNTS 16
 #define HOUGH_COUNT_CANDIDATES 0   /* candidates written                    */
 #define HOUGH_COUNT_HITS 1         /* hit indices written                   */
 #define HOUGH_COUNT_STATUS 2       /* 0, or a negative hough_status         */
 #define HOUGH_COUNT_DETAIL 3       /* first invalid global hit index, or -1 */
-#define HOUGH_COUNT_VOTES 4        /* votes cast: sum of alive hits x n_theta
-                                      over all iterations and events        */
+#define HOUGH_COUNT_EVALS 4        /* Eq. (4) bin evaluations performed for
+                                      histograms and hot-bin recounts      */
 #define HOUGH_COUNT_ITERS 5        /* iterations summed over events         */
 #define HOUGH_COUNT_MAX_ITERS 6    /* largest iteration count of an event   */
-#define HOUGH_COUNT_PASSES 7       /* histogram sweeps (>= iterations; more
-                                      when a pass overflowed the peak list) */
+#define HOUGH_COUNT_PASSES 7       /* full histogram sweeps                 */
+#define HOUGH_COUNT_TILED 8        /* sweeps through the tiled fallback     */
+#define HOUGH_COUNT_TRUNCATIONS 9  /* peak-list truncations (tiled sweeps)  */
+#define HOUGH_COUNT_HOT_SCANS 10   /* tiles scanned after a hot-list overflow */
+#define HOUGH_COUNT_HOTSET_FULL 11 /* row-stream sweeps whose hot set overflowed */
+#define HOUGH_COUNT_RECOUNTS 12    /* iterations served by a hot-set recount */
+/* entries 13..15 are written as 0 */
 
 /* Largest hit count of one event. */
 #define HOUGH_MAX_EVENT_HITS 131072

@@ -33,12 +33,17 @@ struct Ctx {
     float *d_phi = nullptr, *d_thc = nullptr, *d_rhoc = nullptr;
     // launch shape
     int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
+    int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
+    int stream_ok = 0, hs_off = 0, sorted_off = 0;
+    double safe_r2 = -1.0;
     int dump_rows = 0, dump_lds = 0;
     // workspace
     void *ws = nullptr;
     size_t ws_bytes = 0;
     int64_t ws_hits = -1, ws_events = -1;
     int32_t *state = nullptr, *aidx = nullptr, *hits_ws = nullptr, *ev_ncand = nullptr, *ev_nhits = nullptr;
+    unsigned long long *g_hs = nullptr;
+    int32_t *g_cnt = nullptr, *g_flag = nullptr;
     float *aphi = nullptr, *az = nullptr;
     hough_candidate *cand_ws = nullptr;
     long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
@@ -87,6 +92,11 @@ hough_status check_config(const hough_config *c, std::string &why) {
     if (c->assoc_window < 0) { why = "assoc_window must be >= 0"; return HOUGH_ERR_INVALID_ARG; }
     if (c->max_iters < 0) { why = "max_iters must be >= 0"; return HOUGH_ERR_INVALID_ARG; }
     if (c->tile_rows < 0 || c->tile_rows > 4096) { why = "tile_rows must be in 0..4096"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->sweep_groups < 0 || c->sweep_groups > 1024) { why = "sweep_groups must be in 0..1024"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->sweep_threads != 0 && c->sweep_threads != 256 && c->sweep_threads != 512 && c->sweep_threads != 1024) {
+        why = "sweep_threads must be 0, 256, 512 or 1024";
+        return HOUGH_ERR_INVALID_ARG;
+    }
     if (c->wg_threads != 0 && c->wg_threads != 256 && c->wg_threads != 512 && c->wg_threads != 1024) {
         why = "wg_threads must be 0, 256, 512 or 1024";
         return HOUGH_ERR_INVALID_ARG;
@@ -152,6 +162,41 @@ hough_status choose_shape(Ctx &c, std::string &why) {
         why = "hipFuncSetAttribute failed for the finder kernel";
         return HOUGH_ERR_DEVICE;
     }
+    // row-stream layout inside the tile: one row buffer per wave (reused by
+    // the hash table of the window test: a power-of-two slot count of 8 B,
+    // at most half full), then the hot set, then the sorted peak keys
+    {
+        const int rb = (c.wg_threads / 64) * c.pitch * 4;
+        const int sorted_bytes = 8 * (kPeakKeep + kHotCap);
+        int slots = 1;
+        while (2 * slots * 8 <= rb) slots *= 2;
+        int cap = std::min(4096, slots / 2);
+        cap = std::min(cap, (c.tile_bytes - rb - sorted_bytes) / 8);
+        c.stream_ok = cap >= 256 ? 1 : 0;
+        c.hs_cap = std::max(cap, 0);
+        c.hs_off = rb;
+        c.sorted_off = rb + 8 * c.hs_cap;
+    }
+    // |rho| <= r (1 + 2^-24)^3 for r = sqrt(phi^2 + z^2); a rho at least
+    // delta inside [rho_min, rho_max] gives a bin in [0, n_rho) after the
+    // rounded subtraction and multiplication by inv_w (relative error
+    // < 3 * 2^-24 of the width); delta below is far larger than that
+    {
+        const double width = (double)g.rho_max - (double)g.rho_min;
+        const double delta = 1e-3 * width + 1e-3;
+        const double rmax = std::min(-(double)g.rho_min, (double)g.rho_max) - delta;
+        c.safe_r2 = rmax > 0.0 ? (rmax / (1.0 + 1e-6)) * (rmax / (1.0 + 1e-6)) : -1.0;
+    }
+    c.sweep_groups = c.stream_ok ? g.sweep_groups : 0;
+    c.sweep_threads = g.sweep_threads > 0 ? g.sweep_threads : 256;
+    if (c.sweep_groups > 0) {
+        const int sl = hough::sweep_lds_bytes(c.sweep_threads, c.pitch);
+        if (sl + kStaticLds > lds_max) { why = "sweep row buffers do not fit in LDS"; return HOUGH_ERR_INVALID_ARG; }
+        if (hough::set_sweep_lds_limit(c.sweep_threads, sl) != hipSuccess) {
+            why = "hipFuncSetAttribute failed for the sweep kernel";
+            return HOUGH_ERR_DEVICE;
+        }
+    }
     int drows = std::min(g.n_theta, std::max(1, (lds_max - kStaticLds) / row_bytes));
     c.dump_rows = std::min(drows, 64);
     c.dump_lds = c.dump_rows * row_bytes;
@@ -179,7 +224,9 @@ hough_status ensure_workspace(Ctx &c, int64_t n_hits, int64_t n_events, hipStrea
     const size_t o_state = take(4 * nh), o_aidx = take(4 * nh), o_aphi = take(4 * nh), o_az = take(4 * nh);
     const size_t o_hits = take(4 * nh), o_cand = take(sizeof(hough_candidate) * ncand);
     const size_t o_enc = take(4 * ne), o_enh = take(4 * ne), o_eco = take(8 * ne), o_eho = take(8 * ne);
-    const size_t o_stats = take(8 * 8), o_err = take(8 * 4), o_offs = take(8 * 4);
+    const size_t o_stats = take(8 * 16), o_err = take(8 * 4), o_offs = take(8 * 4);
+    const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
+    const size_t o_ghs = c.sweep_groups > 0 ? take(8 * (size_t)ne * (size_t)std::max(c.hs_cap, 1)) : 0;
     void *p = nullptr;
     if (c.ws) {
         // the old workspace may still be read by work queued earlier
@@ -209,6 +256,14 @@ hough_status ensure_workspace(Ctx &c, int64_t n_hits, int64_t n_events, hipStrea
     c.stats = reinterpret_cast<unsigned long long *>(base + o_stats);
     c.err = reinterpret_cast<long long *>(base + o_err);
     c.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
+    c.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
+    c.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
+    c.g_hs = c.sweep_groups > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
+    // statistics, error and split-sweep words start cleared; every call
+    // leaves them so
+    if (hough::launch_reset(c.stats, c.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_zero_i32(c.g_cnt, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_zero_i32(c.g_flag, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     return HOUGH_OK;
 }
 
@@ -244,13 +299,23 @@ hough::FindArgs find_args(const Ctx &c) {
     a.tile_bytes = c.tile_bytes;
     a.hcap = kHotCap;
     a.pkeep = kPeakKeep;
-    a.stream_ok = (c.wg_threads / 64) * c.pitch * 4 <= c.tile_bytes &&
-                  2 * 4 * (2 * (kPeakKeep + kHotCap)) <= c.tile_bytes ? 1 : 0;
+    a.stream_ok = c.stream_ok;
+    a.safe_r2 = c.safe_r2;
+    a.hs_cap = c.hs_cap;
+    a.hs_off = c.hs_off;
+    a.sorted_off = c.sorted_off;
+    a.g_cnt = c.g_cnt;
+    a.g_flag = c.g_flag;
+    a.g_hs = (c.sweep_groups > 0 && c.stream_ok) ? c.g_hs : nullptr;
     return a;
 }
 
+// Launches the finder. With counts != NULL (one event) the kernel writes the
+// candidates, hit lists and counts straight into cand / hits / counts;
+// otherwise it fills the workspace slots for the compaction kernels.
 hough_status run_find(Ctx &c, hipStream_t s, int32_t n_events, int64_t n_total, const int64_t *offsets,
-                      const float *z, const int16_t *vane, int32_t max_iters) {
+                      const float *z, const int16_t *vane, int32_t max_iters, hough_candidate *cand,
+                      int32_t *hits, int64_t *counts) {
     hough::FindArgs a = find_args(c);
     a.n_events = n_events;
     a.n_total = n_total;
@@ -258,12 +323,20 @@ hough_status run_find(Ctx &c, hipStream_t s, int32_t n_events, int64_t n_total, 
     a.z = z;
     a.vane = vane;
     a.max_iters = max_iters;
-    if (hough::launch_reset(c.stats, c.err, s) != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, "reset launch failed");
+    a.counts = counts;
+    if (counts) {
+        a.cand_ws = cand;
+        a.hits_ws = hits;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c.timing && n_events > 0) {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return fail(&c, HOUGH_ERR_DEVICE, "hipEventCreate failed");
         (void)hipEventRecord(e0, s);
+    }
+    if (a.g_hs != nullptr) {
+        hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
+        if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
     hipError_t st = hough::launch_find(a, c.wg_threads, c.lds_bytes, s);
     if (st != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("finder launch failed: ") + hipGetErrorString(st));
@@ -390,7 +463,15 @@ hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hit
     hipStream_t s = static_cast<hipStream_t>(stream);
     hough_status st = ensure_workspace(*c, n_hits_total, n_events, s);
     if (st) return fail(c, st, "workspace allocation failed");
-    st = run_find(*c, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters);
+    if (n_events == 1) {
+        // one event: its slots are the dense layout, one kernel does all
+        st = run_find(*c, s, 1, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand, hit_index, counts);
+        if (st) return st;
+        c->last_error.clear();
+        return HOUGH_OK;
+    }
+    st = run_find(*c, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, nullptr, nullptr,
+                  nullptr);
     if (st) return st;
     hough::CompactArgs ca{};
     ca.n_events = n_events;
@@ -426,18 +507,11 @@ hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, co
     if (st) return fail(c, st, "workspace allocation failed");
     if (hough::launch_set_offsets(c->tmp_offsets, n_hits, s) != hipSuccess)
         return fail(c, HOUGH_ERR_DEVICE, "offset launch failed");
-    // iters == 0 still runs the finder for its input validation, with a cap of
-    // zero iterations expressed by skipping the state below
-    st = run_find(*c, s, 1, n_hits, c->tmp_offsets, z, vane, iters > 0 ? iters : 0);
+    // iters == 0 still runs the finder for its input validation; the dump
+    // then ignores the state and counts every hit
+    st = run_find(*c, s, 1, n_hits, c->tmp_offsets, z, vane, iters > 0 ? iters : 0, c->cand_ws, c->hits_ws,
+                  counts);
     if (st) return st;
-    hough::CompactArgs ca{};
-    ca.n_events = 0;
-    ca.stats = c->stats;
-    ca.err = c->err;
-    ca.counts = counts;
-    ca.ev_ncand = c->ev_ncand;
-    ca.ev_nhits = c->ev_nhits;
-    if (hough::launch_compact(ca, s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "status launch failed");
     hough::DumpArgs da{};
     da.n_theta = c->cfg.n_theta;
     da.n_rho = c->cfg.n_rho;

@@ -31,7 +31,8 @@ struct FindArgs {
     hough_candidate *cand_ws;  // candidate slots, event e starts at floor(off_e / T)
     int32_t *hits_ws;    // hit-list slots, event e starts at off_e
     int32_t *ev_ncand, *ev_nhits;
-    unsigned long long *stats;  // [votes, iters, max_iters, passes]
+    unsigned long long *stats;  // [evals, iters, max_iters, passes, tiled, truncations,
+                                //  hot scans, hot-set overflows, recounts, ...] (16 words)
     long long *err;             // [status (min), first bad global hit index (min)]
     // launch shape
     int32_t tile_rows;   // own theta rows per LDS tile
@@ -40,6 +41,15 @@ struct FindArgs {
     int32_t hcap;        // hot-list capacity per tile
     int32_t pkeep;       // peak entries kept after a compaction; pkeep + hcap is a power of 2
     int32_t stream_ok;   // tile holds one row buffer per wave: row-stream sweep allowed
+    int64_t *counts;     // single-event mode: the block writes the caller's counts itself
+    // split first sweep (optional): per-event hot lists written by k_sweep
+    unsigned long long *g_hs;  // [n_events * hs_cap] keys, or NULL when not used
+    int32_t *g_cnt;            // [n_events] entries appended (cleared by k_find)
+    int32_t *g_flag;           // [n_events] 1 = the sweep kernel left the event to k_find
+    double safe_r2;      // phi^2 + z^2 at or below which a hit votes inside [0, n_rho) in every row
+    int32_t hs_cap;      // hot-set capacity (entries)
+    int32_t hs_off;      // LDS byte offsets of the hot set and of the sorted peak keys
+    int32_t sorted_off;
 };
 
 struct DumpArgs {
@@ -64,16 +74,20 @@ struct CompactArgs {
     const int32_t *hits_ws;
     const int32_t *ev_ncand, *ev_nhits;
     long long *ev_cout, *ev_hout;  // exclusive prefix sums
-    const unsigned long long *stats;
-    const long long *err;
+    unsigned long long *stats;  // read, then cleared for the next call
+    long long *err;
     hough_candidate *cand;
     int32_t *hit_index;
     int64_t *counts;
 };
 
 // Kernel launchers (hough_kernels.hip). Each returns the launch status.
-hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s);
+hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s);  // used once per workspace
 hipError_t launch_find(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
+hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t s);
+hipError_t set_sweep_lds_limit(int threads, int lds_bytes);
+int sweep_lds_bytes(int threads, int pitch);
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_dump(const DumpArgs &a, int lds_bytes, hipStream_t s);
 hipError_t launch_set_offsets(int64_t *offsets, int64_t n, hipStream_t s);

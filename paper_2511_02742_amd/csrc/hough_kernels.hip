@@ -32,12 +32,19 @@
 
 #include "hough_internal.h"
 
+#include <algorithm>
+
 namespace hough {
 
 namespace {
 
 constexpr int kWave = 64;
+
+// Dynamic LDS of every kernel here (the allocation starts at this symbol);
+// indexing it keeps LDS addresses 32-bit.
+extern __shared__ __align__(16) uint32_t g_lds[];
 constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
+constexpr int kStats = 16;  // workspace statistics words (see k_scan)
 
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -119,6 +126,8 @@ struct Shared {
     unsigned long long maxdrop;
     unsigned long long best;
     int wtot[16];
+    int n_trunc;     // peak-list truncations (diagnostics)
+    int n_hotscan;   // hot-list overflow scans (diagnostics)
 };
 
 // LDS layout of k_find (dynamic part):
@@ -127,8 +136,12 @@ struct Shared {
 //   pbuf[pkeep + hcap]     u64 peak keys
 //   dec[pkeep + hcap]      int2 (theta bin, rho bin) of the sorted peaks
 //   dummy[threads]         u32, one word per lane for masked-off votes
-//   hs[pkeep + hcap]       u64 keys of every bin that reached T (row-stream
-//                          sweep), later the sorted peak keys
+// Inside the tile region the row-stream path uses
+//   [0, NW * pitch * 4)    one row buffer per wave; later the hash table of
+//                          the window test and the association scratch
+//   hs[hs_cap]             u64 keys of every bin that reached T (the hot set;
+//                          0 marks a bin that fell below T)
+//   sorted[pkeep + hcap]   u64 peak keys in descending order
 struct Lds {
     uint32_t *tile;
     uint32_t *hot;
@@ -136,6 +149,7 @@ struct Lds {
     int2 *dec;
     uint32_t *dummy;
     unsigned long long *hs;
+    unsigned long long *sorted;
 };
 
 // The alive hits of one register batch: chunk ch holds alive-list entries
@@ -143,7 +157,8 @@ struct Lds {
 struct HitRegs {
     float phi[kChunks];
     float z[kChunks];
-    int nch;  // chunks present in this batch (uniform)
+    int nch;    // chunks present in this batch (uniform)
+    bool safe;  // every hit of the batch lands inside [0, n_rho) in every row (uniform)
 };
 
 __device__ __forceinline__ void load_batch(const FindArgs &A, int64_t b, int n_alive, int batch, HitRegs &h) {
@@ -151,13 +166,20 @@ __device__ __forceinline__ void load_batch(const FindArgs &A, int64_t b, int n_a
     const int ch0 = batch * kChunks;
     const int nchunks = (n_alive + kWave - 1) / kWave;
     h.nch = min(kChunks, nchunks - ch0);
+    bool ok = true;
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
         const int q = (ch0 + c) * kWave + lane;
         const bool v = c < h.nch && q < n_alive;
         h.phi[c] = v ? A.aphi[b + q] : 0.0f;
         h.z[c] = v ? A.az[b + q] : 0.0f;
+        // |rho(theta)| <= sqrt(phi^2 + z^2) (1 + 2^-24)^3 for every sampled
+        // theta, which safe_r2 keeps below the rho range by a margin that
+        // also covers the rounding of the subtraction and of inv_w
+        const double r2 = (double)h.phi[c] * h.phi[c] + (double)h.z[c] * h.z[c];
+        ok = ok && (!v || r2 <= A.safe_r2);
     }
+    h.safe = __ballot(!ok) == 0ull;
 }
 
 // Window test of bin (tr, k) of the tile (tile row tr = theta row lo + tr)
@@ -218,6 +240,7 @@ __device__ void maybe_truncate(const FindArgs &A, const Lds &L, Shared &sh) {
         unsigned long long d = L.pbuf[A.pkeep];
         if (d > sh.maxdrop) sh.maxdrop = d;
         sh.pcnt = A.pkeep;
+        sh.n_trunc += 1;
     }
     __syncthreads();
 }
@@ -281,36 +304,38 @@ __device__ __forceinline__ void vote_rows(const FindArgs &A, const float2 *__res
 // bins to the workgroup hot set, and restores the buffer to zero by writing
 // 0 to the addresses it voted. The window test runs afterwards on the hot set:
 // a bin below T can never beat a bin that reached T.
-template <int NT, int NCH>
-__device__ __forceinline__ void stream_rows(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L,
-                                            const HitRegs &h, int n_alive, Shared &sh) {
-    constexpr int NW = NT / kWave;
-    const int wave = wave_id();
+// The wave handles rows j = row0, row0 + rstride, ... with its own row
+// buffer at LDS word `row_w` (a per-lane dummy word at `dummy_w`); hot bins go
+// to sink[*sink_cnt++] (LDS or global memory).
+template <int NCH, bool SAFE>
+__device__ __forceinline__ void stream_rows(const FindArgs &A, const float2 *__restrict__ cs, uint32_t row_w,
+                                            uint32_t dummy_w, const HitRegs &h, int n_alive, int row0,
+                                            int rstride, unsigned long long *sink, int *sink_cnt,
+                                            int sink_cap) {
     const int lane = lane_id();
     const uint32_t tm1 = A.min_votes - 1u;
-    const int hs_cap = A.pkeep + A.hcap;
-    uint32_t *const rowbuf = L.tile + wave * A.pitch;
-    uint32_t *const my_dummy = L.dummy + threadIdx.x;
     bool valid[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) valid[c] = c * kWave + lane < n_alive;
-    for (int jb = wave; jb < A.n_theta; jb += NW * kWave) {
-        const int nr = min(kWave, (A.n_theta - jb + NW - 1) / NW);
-        const float2 mine = lane < nr ? cs[jb + NW * lane] : make_float2(0.0f, 0.0f);
+    for (int jb = row0; jb < A.n_theta; jb += rstride * kWave) {
+        const int nr = min(kWave, (A.n_theta - jb + rstride - 1) / rstride);
+        const float2 mine = lane < nr ? cs[jb + rstride * lane] : make_float2(0.0f, 0.0f);
         for (int i = 0; i < nr; ++i) {
-            const int j = jb + NW * i;
+            const int j = jb + rstride * i;
             float2 t;
             t.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
             t.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
-            uint32_t *addr[NCH];
+            uint32_t addr[NCH];
             uint32_t old[NCH];
             bool hot[NCH];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                const bool in = valid[c] && (unsigned)k < (unsigned)A.n_rho;
-                addr[c] = in ? rowbuf + k : my_dummy;
-                old[c] = atomicAdd(addr[c], 1u);
+                // with SAFE every hit is in range and only the last chunk can
+                // be partly filled
+                const bool in = SAFE ? (c + 1 < NCH || valid[c]) : (valid[c] && (unsigned)k < (unsigned)A.n_rho);
+                addr[c] = (SAFE && c + 1 < NCH) ? row_w + (uint32_t)k : (in ? row_w + (uint32_t)k : dummy_w);
+                old[c] = atomicAdd(&g_lds[addr[c]], 1u);
                 hot[c] = in && old[c] == tm1;
             }
             bool any = false;
@@ -320,17 +345,47 @@ __device__ __forceinline__ void stream_rows(const FindArgs &A, const float2 *__r
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     if (hot[c]) {
-                        const uint32_t cnt = *addr[c];
-                        const int k = (int)(addr[c] - rowbuf);
-                        const int slot = atomicAdd(&sh.hs_cnt, 1);
-                        if (slot < hs_cap) L.hs[slot] = bin_key(cnt, (uint32_t)(j * A.n_rho + k));
+                        const uint32_t cnt = g_lds[addr[c]];
+                        const int k = (int)(addr[c] - row_w);
+                        const int slot = atomicAdd(sink_cnt, 1);
+                        if (slot < sink_cap) sink[slot] = bin_key(cnt, (uint32_t)(j * A.n_rho + k));
                     }
                 }
             }
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) *addr[c] = 0u;
+            for (int c = 0; c < NCH; ++c) g_lds[addr[c]] = 0u;
         }
     }
+}
+
+// Dispatches the row-stream votes of one wave on the chunk count. Only
+// batches whose hits all vote inside [0, n_rho) (h.safe) are streamed; the
+// callers send any other batch through the tiled sweep (one variant per chunk
+// count keeps the finder kernel within its register budget).
+__device__ __forceinline__ void stream_dispatch(const FindArgs &A, const float2 *__restrict__ cs, uint32_t row_w,
+                                                uint32_t dummy_w, const HitRegs &h, int n_alive, int row0,
+                                                int rstride, unsigned long long *sink, int *sink_cnt,
+                                                int sink_cap) {
+    // the row buffer may hold data of an earlier phase
+    uint4 *r4 = reinterpret_cast<uint4 *>(g_lds + row_w);
+    for (int x = lane_id(); x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#define HOUGH_STREAM_CASE(N)                                                                                   \
+    case N:                                                                                                    \
+        stream_rows<N, true>(A, cs, row_w, dummy_w, h, n_alive, row0, rstride, sink, sink_cnt, sink_cap);       \
+        break;
+    switch (h.nch) {
+        HOUGH_STREAM_CASE(1)
+        HOUGH_STREAM_CASE(2)
+        HOUGH_STREAM_CASE(3)
+        HOUGH_STREAM_CASE(4)
+        HOUGH_STREAM_CASE(5)
+        HOUGH_STREAM_CASE(6)
+        HOUGH_STREAM_CASE(7)
+        HOUGH_STREAM_CASE(8)
+    default: break;
+    }
+#undef HOUGH_STREAM_CASE
 }
 
 template <int NT>
@@ -338,23 +393,8 @@ __device__ void stream_sweep(const FindArgs &A, const float2 *__restrict__ cs, c
                              int n_alive, Shared &sh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
-    const int lane = lane_id();
-    // the row buffers may hold the previous pass's association data
-    uint4 *r4 = reinterpret_cast<uint4 *>(L.tile + wave * A.pitch);
-    for (int x = lane; x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
-    if (lane < kWave) L.dummy[threadIdx.x] = 0u;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    switch (h.nch) {
-    case 1: stream_rows<NT, 1>(A, cs, L, h, n_alive, sh); break;
-    case 2: stream_rows<NT, 2>(A, cs, L, h, n_alive, sh); break;
-    case 3: stream_rows<NT, 3>(A, cs, L, h, n_alive, sh); break;
-    case 4: stream_rows<NT, 4>(A, cs, L, h, n_alive, sh); break;
-    case 5: stream_rows<NT, 5>(A, cs, L, h, n_alive, sh); break;
-    case 6: stream_rows<NT, 6>(A, cs, L, h, n_alive, sh); break;
-    case 7: stream_rows<NT, 7>(A, cs, L, h, n_alive, sh); break;
-    default: stream_rows<NT, 8>(A, cs, L, h, n_alive, sh); break;
-    }
-    (void)NW;
+    stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(L.dummy - L.tile) + threadIdx.x, h, n_alive, wave,
+                    NW, L.hs, &sh.hs_cnt, A.hs_cap);
 }
 
 __device__ __forceinline__ uint32_t hs_hash(uint32_t flat, int log2n) {
@@ -368,12 +408,13 @@ __device__ __forceinline__ uint32_t hs_hash(uint32_t flat, int log2n) {
 template <int NT>
 __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &sh) {
     if (A.peak_mode == 0) {
+        if (threadIdx.x == 0) sh.best = 0ull;
+        __syncthreads();
         for (int e = threadIdx.x; e < n_hs; e += NT) atomicMax(&sh.best, L.hs[e]);
         __syncthreads();
         const unsigned long long best = sh.best;
-        const int npk = n_hs > 0 ? 1 : 0;
-        __syncthreads();
-        if (threadIdx.x == 0) L.hs[0] = best;
+        const int npk = best != 0ull ? 1 : 0;
+        if (threadIdx.x == 0) L.sorted[0] = best;
         __syncthreads();
         return npk;
     }
@@ -387,6 +428,7 @@ __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &s
     __syncthreads();
     for (int e = threadIdx.x; e < n_hs; e += NT) {
         const unsigned long long key = L.hs[e];
+        if (key == 0ull) continue;
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
         uint32_t slot = hs_hash(flat, log2n);
         while (atomicCAS(&htk[slot], 0u, flat + 1u) != 0u) slot = (slot + 1u) & (uint32_t)(ht - 1);
@@ -396,6 +438,7 @@ __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &s
     const int w = A.nms_radius;
     for (int e = threadIdx.x; e < n_hs; e += NT) {
         const unsigned long long key = L.hs[e];
+        if (key == 0ull) continue;
         const uint32_t c = (uint32_t)(key >> 32);
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
         const int j = (int)(flat / (uint32_t)A.n_rho);
@@ -423,19 +466,54 @@ __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &s
                 if (c2 > c || (c2 == c && f2 < flat)) peak = false;
             }
         }
-        if (peak) L.pbuf[atomicAdd(&sh.pcnt, 1)] = key;
+        if (peak) {
+            const int slot = atomicAdd(&sh.pcnt, 1);
+            if (slot < A.pkeep + A.hcap) L.pbuf[slot] = key;
+        }
     }
     __syncthreads();
     const int npk = sh.pcnt;
-    // rank sort (keys are distinct): descending order into L.hs
+    if (npk > A.pkeep + A.hcap) return -1;  // more peaks than the list holds
+    // rank sort (keys are distinct): descending order into L.sorted
     for (int p = threadIdx.x; p < npk; p += NT) {
         const unsigned long long key = L.pbuf[p];
         int r = 0;
         for (int q = 0; q < npk; ++q) r += L.pbuf[q] > key ? 1 : 0;
-        L.hs[r] = key;
+        L.sorted[r] = key;
     }
     __syncthreads();
     return npk;
+}
+
+// Recount of the hot set for the current alive hits. Removing hits never
+// raises a count, so every bin that reaches T now was in the hot set of the
+// previous histogram: recounting those bins gives the complete hot set of the
+// new histogram. Each wave takes bins; lanes test the register-resident hits
+// against the bin with Eq. (4) and ballots count the matches. Bins below T
+// are marked dead (key 0).
+template <int NT>
+__device__ void recount(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
+                        int n_alive, int n_hs) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    for (int e = wave; e < n_hs; e += NW) {
+        const unsigned long long key = L.hs[e];
+        if (key == 0ull) continue;
+        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+        const int j = (int)(flat / (uint32_t)A.n_rho);
+        const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
+        const float2 t = cs[j];
+        int cnt = 0;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            if (c < h.nch) {
+                const int kk = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+                cnt += __popcll(__ballot(c * kWave + lane < n_alive && kk == k));
+            }
+        }
+        if (lane == 0) L.hs[e] = (uint32_t)cnt >= A.min_votes ? bin_key((uint32_t)cnt, flat) : 0ull;
+    }
 }
 
 // One pass of the histogram over all theta rows for the current alive list.
@@ -493,6 +571,7 @@ __device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t 
             if (A.peak_mode == 1) maybe_truncate<NT>(A, L, sh);
         } else {
             // hot list overflowed: scan the own rows in chunks of hcap bins
+            if (threadIdx.x == 0) sh.n_hotscan += 1;
             const int nb = own * A.n_rho;
             for (int base = 0; base < nb; base += A.hcap) {
                 const int lim = min(A.hcap, nb - base);
@@ -509,7 +588,15 @@ __device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t 
     }
 }
 
-// Claims hits for the sorted peaks pbuf[0, npk) of this pass.
+// Claims hits for the sorted peaks keys[0, npk) of this pass.
+//   A: every wave takes peaks; per chunk of 64 alive hits a ballot gives the
+//      match mask, a running sum gives the chunk's prefix inside the peak,
+//      and the total is the peak's raw match count.
+//   B: one wave walks the peaks in key order with one mask word per lane.
+//      A peak none of whose matches is claimed yet is emitted with its raw
+//      count (raw >= its bin count >= T); one whose matches are all claimed is
+//      rejected; only a partial overlap needs a DPP prefix sum.
+//   C: all waves write the hit lists of the emitted peaks.
 template <int NT>
 __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
@@ -521,14 +608,16 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
     const int W = (n_alive + kWave - 1) / kWave;
     const int64_t cbase = b / (int64_t)A.min_votes;
 
-    // union area: icl[W] u64 | M[pb * W] u64 | pref[pb * W] u32 | elist[pb] i32
+    // union area: icl[W] u64 | M[pb*W] u64 | rp[pb*W] u32 | base[pb] | raw[pb] | elist[pb]
     unsigned char *uni = reinterpret_cast<unsigned char *>(L.tile);
     unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni);
     unsigned long long *M = icl + W;
-    int pb = (uni_bytes - 8 * W) / (12 * W + 4);
+    int pb = (uni_bytes - 8 * W) / (12 * W + 12);
     pb = min(pb, A.pkeep + A.hcap);
-    uint32_t *pref = reinterpret_cast<uint32_t *>(M + (size_t)pb * W);
-    int *elist = reinterpret_cast<int *>(pref + (size_t)pb * W);
+    uint32_t *rp = reinterpret_cast<uint32_t *>(M + (size_t)pb * W);
+    int *pbase = reinterpret_cast<int *>(rp + (size_t)pb * W);
+    int *praw = pbase + pb;
+    int *elist = praw + pb;
 
     // peak coordinates, and the hits claimed by an earlier pass of this
     // iteration
@@ -546,13 +635,14 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
 
     for (int p0 = 0; p0 < npk; p0 += pb) {
         const int nb = min(pb, npk - p0);
-        // A: match masks, from the register-resident hits
+        // A: match masks, chunk prefixes and raw counts
         for (int bt = 0; bt < nbatch; ++bt) {
             if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
             const int qbase = bt * kChunks * kWave + lane;
             for (int p = wave; p < nb; p += NW) {
                 const int2 jk = L.dec[p0 + p];
                 const float2 t = cs[jk.x];
+                int run = bt == 0 ? 0 : praw[p];
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
                     if (c < h.nch) {
@@ -560,102 +650,108 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
                         const int d = k - jk.y;
                         const bool hit = (qbase + c * kWave) < n_alive && (d < 0 ? -d : d) <= A.assoc_window;
                         const unsigned long long m = __ballot(hit);
-                        if (lane == 0) M[(size_t)p * W + bt * kChunks + c] = m;
+                        if (lane == 0) {
+                            M[(size_t)p * W + bt * kChunks + c] = m;
+                            rp[(size_t)p * W + bt * kChunks + c] = (uint32_t)run;
+                        }
+                        run += __popcll(m);
                     }
                 }
+                if (lane == 0) praw[p] = run;
             }
+            if (nbatch > 1) __syncthreads();
         }
         __syncthreads();
         // B: one wave resolves the claims in key order
-        if (wave == 0 && W <= kWave) {
-            // one mask word per lane; the claimed-so-far word stays in a
-            // register and the next peak's masks are fetched ahead
+        if (wave == 0) {
             int ncand = sh.ncand;
             int nhit = sh.nhit;
             int nemit = 0;
-            unsigned long long mine = lane < W ? icl[lane] : ~0ull;
-            unsigned long long mnext = lane < W ? M[lane] : 0ull;
-            for (int p = 0; p < nb; ++p) {
-                const unsigned long long mp = mnext;
-                if (p + 1 < nb) mnext = lane < W ? M[(size_t)(p + 1) * W + lane] : 0ull;
-                const unsigned long long m = mp & ~mine;
-                const int cnt = __popcll(m);
-                const int incl = wave_incl_scan(cnt);
-                const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
-                if (total < (int)A.min_votes) continue;
-                mine |= m;
-                if (lane < W) {
-                    M[(size_t)p * W + lane] = m;
-                    pref[(size_t)p * W + lane] = (uint32_t)(nhit + incl - cnt);
-                }
-                if (lane == 0) {
-                    const int2 jk = L.dec[p0 + p];
-                    hough_candidate cd;
-                    cd.event = e;
-                    cd.iter = iter;
-                    cd.theta_bin = jk.x;
-                    cd.rho_bin = jk.y;
-                    cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
-                    cd.n_hits = (uint32_t)total;
-                    cd.hit_offset = nhit;
-                    cd.theta = A.theta_c[jk.x];
-                    cd.rho = A.rho_c[jk.y];
-                    A.cand_ws[cbase + ncand] = cd;
-                    elist[nemit] = p;
-                }
-                ++nemit;
-                ++ncand;
-                nhit += total;
-            }
-            if (lane < W) icl[lane] = mine;
-            if (lane == 0) {
-                sh.nemit = nemit;
-                sh.ncand = ncand;
-                sh.nhit = nhit;
-            }
-        } else if (wave == 0) {
-            int ncand = sh.ncand;
-            int nhit = sh.nhit;
-            int nemit = 0;
-            for (int p = 0; p < nb; ++p) {
-                int total = 0;
-                for (int cb = 0; cb < W; cb += kWave) {
-                    const int ch = cb + lane;
-                    const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
-                    total += __builtin_amdgcn_readlane(wave_incl_scan(__popcll(m)), kWave - 1);
-                }
-                if (total < (int)A.min_votes) continue;
-                int run = nhit;
-                for (int cb = 0; cb < W; cb += kWave) {
-                    const int ch = cb + lane;
-                    const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
-                    const int cnt = __popcll(m);
-                    const int incl = wave_incl_scan(cnt);
-                    if (ch < W) {
-                        pref[(size_t)p * W + ch] = (uint32_t)(run + incl - cnt);
-                        icl[ch] |= m;
-                        M[(size_t)p * W + ch] = m;
+            if (W <= kWave) {
+                unsigned long long mine = lane < W ? icl[lane] : ~0ull;
+                unsigned long long mnext = lane < W ? M[lane] : 0ull;
+                for (int p = 0; p < nb; ++p) {
+                    const unsigned long long mp = mnext;
+                    if (p + 1 < nb) mnext = lane < W ? M[(size_t)(p + 1) * W + lane] : 0ull;
+                    const unsigned long long m = mp & ~mine;
+                    if (__ballot(m != 0ull) == 0ull) continue;          // every match already claimed
+                    int total;
+                    if (__ballot(m != mp) == 0ull) {
+                        total = praw[p];                                 // no match claimed yet
+                    } else {
+                        const int cnt = __popcll(m);
+                        const int incl = wave_incl_scan(cnt);
+                        total = __builtin_amdgcn_readlane(incl, kWave - 1);
+                        if (total < (int)A.min_votes) continue;
+                        if (lane < W) {
+                            M[(size_t)p * W + lane] = m;
+                            rp[(size_t)p * W + lane] = (uint32_t)(incl - cnt);
+                        }
                     }
-                    run += __builtin_amdgcn_readlane(incl, kWave - 1);
+                    mine |= m;
+                    if (lane == 0) {
+                        const int2 jk = L.dec[p0 + p];
+                        hough_candidate cd;
+                        cd.event = e;
+                        cd.iter = iter;
+                        cd.theta_bin = jk.x;
+                        cd.rho_bin = jk.y;
+                        cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
+                        cd.n_hits = (uint32_t)total;
+                        cd.hit_offset = nhit;
+                        cd.theta = A.theta_c[jk.x];
+                        cd.rho = A.rho_c[jk.y];
+                        A.cand_ws[cbase + ncand] = cd;
+                        elist[nemit] = p;
+                        pbase[p] = nhit;
+                    }
+                    ++nemit;
+                    ++ncand;
+                    nhit += total;
                 }
-                if (lane == 0) {
-                    const int2 jk = L.dec[p0 + p];
-                    hough_candidate cd;
-                    cd.event = e;
-                    cd.iter = iter;
-                    cd.theta_bin = jk.x;
-                    cd.rho_bin = jk.y;
-                    cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
-                    cd.n_hits = (uint32_t)total;
-                    cd.hit_offset = nhit;
-                    cd.theta = A.theta_c[jk.x];
-                    cd.rho = A.rho_c[jk.y];
-                    A.cand_ws[cbase + ncand] = cd;
-                    elist[nemit] = p;
+                if (lane < W) icl[lane] = mine;
+            } else {
+                for (int p = 0; p < nb; ++p) {
+                    int total = 0;
+                    for (int cb = 0; cb < W; cb += kWave) {
+                        const int ch = cb + lane;
+                        const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
+                        total += __builtin_amdgcn_readlane(wave_incl_scan(__popcll(m)), kWave - 1);
+                    }
+                    if (total < (int)A.min_votes) continue;
+                    int run = 0;
+                    for (int cb = 0; cb < W; cb += kWave) {
+                        const int ch = cb + lane;
+                        const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
+                        const int cnt = __popcll(m);
+                        const int incl = wave_incl_scan(cnt);
+                        if (ch < W) {
+                            rp[(size_t)p * W + ch] = (uint32_t)(run + incl - cnt);
+                            icl[ch] |= m;
+                            M[(size_t)p * W + ch] = m;
+                        }
+                        run += __builtin_amdgcn_readlane(incl, kWave - 1);
+                    }
+                    if (lane == 0) {
+                        const int2 jk = L.dec[p0 + p];
+                        hough_candidate cd;
+                        cd.event = e;
+                        cd.iter = iter;
+                        cd.theta_bin = jk.x;
+                        cd.rho_bin = jk.y;
+                        cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
+                        cd.n_hits = (uint32_t)total;
+                        cd.hit_offset = nhit;
+                        cd.theta = A.theta_c[jk.x];
+                        cd.rho = A.rho_c[jk.y];
+                        A.cand_ws[cbase + ncand] = cd;
+                        elist[nemit] = p;
+                        pbase[p] = nhit;
+                    }
+                    ++nemit;
+                    ++ncand;
+                    nhit += total;
                 }
-                ++nemit;
-                ++ncand;
-                nhit += total;
             }
             if (lane == 0) {
                 sh.nemit = nemit;
@@ -675,7 +771,7 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
             if ((m >> lane) & 1ull) {
                 const int q = ch * kWave + lane;
                 const int il = A.aidx[b + q];
-                const int pos = (int)pref[(size_t)p * W + ch] + mbcnt64(m);
+                const int pos = pbase[p] + (int)rp[(size_t)p * W + ch] + mbcnt64(m);
                 A.hits_ws[b + pos] = il;
                 A.state[b + il] = cid0 + ei;
             }
@@ -684,10 +780,18 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
     }
 }
 
+__device__ void write_error_counts(int64_t *counts, long long status, long long detail) {
+    counts[HOUGH_COUNT_CANDIDATES] = 0;
+    counts[HOUGH_COUNT_HITS] = 0;
+    counts[HOUGH_COUNT_STATUS] = status;
+    counts[HOUGH_COUNT_DETAIL] = detail;
+    for (int i = HOUGH_COUNT_EVALS; i < HOUGH_COUNTS; ++i) counts[i] = 0;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restrict__ cs) {
     constexpr int NW = NT / kWave;
-    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *const lds = reinterpret_cast<unsigned char *>(g_lds);
     __shared__ Shared sh;
     Lds L;
     L.tile = reinterpret_cast<uint32_t *>(lds);
@@ -695,7 +799,8 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     L.pbuf = reinterpret_cast<unsigned long long *>(lds + A.tile_bytes + 4 * A.hcap);
     L.dec = reinterpret_cast<int2 *>(L.pbuf + (A.pkeep + A.hcap));
     L.dummy = reinterpret_cast<uint32_t *>(L.dec + (A.pkeep + A.hcap));
-    L.hs = reinterpret_cast<unsigned long long *>(L.dummy + NT);
+    L.hs = reinterpret_cast<unsigned long long *>(lds + A.hs_off);
+    L.sorted = reinterpret_cast<unsigned long long *>(lds + A.sorted_off);
 
     const int e = blockIdx.x;
     const int wave = wave_id();
@@ -712,16 +817,27 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             bad = HOUGH_ERR_CAPACITY;
             atomicMin(&A.err[1], (long long)b);
         }
-        if (bad) atomicMin(&A.err[0], (long long)bad);
+        if (bad && A.counts == nullptr) atomicMin(&A.err[0], (long long)bad);
+        if (bad == HOUGH_ERR_CAPACITY && A.counts != nullptr) {
+            // undo the detail word written above for the multi-event path
+            A.err[1] = 0x7fffffffffffffffll;
+        }
         sh.bad = bad;
         sh.ncand = 0;
         sh.nhit = 0;
+        sh.n_trunc = 0;
+        sh.n_hotscan = 0;
     }
     __syncthreads();
     if (sh.bad) {
         if (threadIdx.x == 0) {
+            if (A.g_cnt != nullptr) {
+                A.g_cnt[e] = 0;
+                A.g_flag[e] = 0;
+            }
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
+            if (A.counts != nullptr) write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
         }
         return;
     }
@@ -740,16 +856,34 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     }
     if (__syncthreads_or(badhit)) {
         if (threadIdx.x == 0) {
+            if (A.g_cnt != nullptr) {
+                A.g_cnt[e] = 0;
+                A.g_flag[e] = 0;
+            }
             atomicMin(&A.err[0], (long long)HOUGH_ERR_DATA);
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
         }
+        if (A.counts != nullptr) {
+            // first invalid hit of the event (the only event of the call)
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const long long first = A.err[1];
+                A.err[0] = 0;
+                A.err[1] = 0x7fffffffffffffffll;
+                write_error_counts(A.counts, HOUGH_ERR_DATA, first);
+            }
+        }
         return;
     }
 
-    unsigned long long votes = 0;
+    unsigned long long evals = 0;
     int iter = 0;
     int passes = 0;
+    int tiled = 0, hs_full = 0, recounts = 0;
+    bool first = true;
+    int n_hs = 0;          // entries of the hot set
+    bool hs_valid = false; // the hot set holds every bin >= T of the current histogram
     HitRegs h;
     for (;;) {
         if (A.max_iters > 0 && iter >= A.max_iters) break;
@@ -780,36 +914,61 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         const int n_alive = carry;
         const int nbatch = (n_alive + kChunks * kWave - 1) / (kChunks * kWave);
         if (threadIdx.x == 0) sh.nalive = n_alive;
-        votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
         const int ncand0 = sh.ncand;
         if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
 
         bool any = false;
         bool done = false;
-        if (nbatch == 1 && A.stream_ok) {
-            // row-stream sweep; falls back to the tiled sweep below when more
-            // bins reach T than the hot set holds
-            ++passes;
-            if (threadIdx.x == 0) {
-                sh.hs_cnt = 0;
-                sh.best = 0ull;
+        if (nbatch == 1 && A.stream_ok && h.safe) {
+            if (first && A.g_hs != nullptr && A.g_flag[e] == 0 && A.g_cnt[e] <= A.hs_cap) {
+                // the first histogram was swept by the split sweep kernel
+                n_hs = A.g_cnt[e];
+                const unsigned long long *src = A.g_hs + (size_t)e * A.hs_cap;
+                for (int i = threadIdx.x; i < n_hs; i += NT) L.hs[i] = src[i];
+                hs_valid = true;
+                ++passes;
+                evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                __syncthreads();
+            } else if (hs_valid) {
+                // recount the previous hot set (no histogram sweep)
+                recount<NT>(A, cs, L, h, n_alive, n_hs);
+                ++recounts;
+                evals += (unsigned long long)n_hs * (unsigned long long)(h.nch * kWave);
+                __syncthreads();
+            } else {
+                // row-stream sweep; falls back to the tiled sweep below when
+                // more bins reach T than the hot set holds
+                ++passes;
+                if (threadIdx.x == 0) sh.hs_cnt = 0;
+                __syncthreads();
+                stream_sweep<NT>(A, cs, L, h, n_alive, sh);
+                __syncthreads();
+                n_hs = sh.hs_cnt;
+                hs_valid = n_hs <= A.hs_cap;
+                hs_full += hs_valid ? 0 : 1;
+                evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
             }
-            __syncthreads();
-            stream_sweep<NT>(A, cs, L, h, n_alive, sh);
-            __syncthreads();
-            const int n_hs = sh.hs_cnt;
-            if (n_hs <= A.pkeep + A.hcap) {
-                done = true;
+            if (hs_valid) {
                 const int npk = hotset_peaks<NT>(A, L, n_hs, sh);
-                if (npk > 0) {
-                    any = true;
-                    associate<NT>(A, cs, e, b, iter, L, L.hs, A.tile_bytes, h, nbatch, npk, sh);
+                if (npk >= 0) {
+                    done = true;
+                    if (npk > 0) {
+                        any = true;
+                        associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh);
+                    }
+                } else {
+                    hs_valid = false;
                 }
             }
+        }
+        if (!done) {
+            hs_valid = false;
+            evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
         }
         unsigned long long ceil_key = ~0ull;
         for (; !done;) {
             ++passes;
+            ++tiled;
             if (threadIdx.x == 0) {
                 sh.pcnt = 0;
                 sh.maxdrop = 0ull;
@@ -839,23 +998,107 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             if (drop == 0ull) break;
             ceil_key = drop;
         }
+        first = false;
         if (!any) break;
         ++iter;
         if (sh.ncand == ncand0) break;
     }
+    if (A.g_cnt != nullptr && threadIdx.x == 0) {
+        // leave the split-sweep words cleared for the next call
+        A.g_cnt[e] = 0;
+        A.g_flag[e] = 0;
+    }
 
+    if (A.counts != nullptr) {
+        // single-event call: the slots are the caller's arrays; write the
+        // counts directly (no other block touches them)
+        if (threadIdx.x == 0) {
+            A.counts[HOUGH_COUNT_CANDIDATES] = sh.ncand;
+            A.counts[HOUGH_COUNT_HITS] = sh.nhit;
+            A.counts[HOUGH_COUNT_STATUS] = 0;
+            A.counts[HOUGH_COUNT_DETAIL] = -1;
+            A.counts[HOUGH_COUNT_EVALS] = (long long)evals;
+            A.counts[HOUGH_COUNT_ITERS] = iter;
+            A.counts[HOUGH_COUNT_MAX_ITERS] = iter;
+            A.counts[HOUGH_COUNT_PASSES] = passes;
+            A.counts[HOUGH_COUNT_TILED] = tiled;
+            A.counts[HOUGH_COUNT_TRUNCATIONS] = sh.n_trunc;
+            A.counts[HOUGH_COUNT_HOT_SCANS] = sh.n_hotscan;
+            A.counts[HOUGH_COUNT_HOTSET_FULL] = hs_full;
+            A.counts[HOUGH_COUNT_RECOUNTS] = recounts;
+            for (int i = HOUGH_COUNT_RECOUNTS + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+        }
+        return;
+    }
     if (threadIdx.x == 0) {
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
-        atomicAdd(&A.stats[0], votes);
+        atomicAdd(&A.stats[0], evals);
         atomicAdd(&A.stats[1], (unsigned long long)iter);
         atomicMax(&A.stats[2], (unsigned long long)iter);
         atomicAdd(&A.stats[3], (unsigned long long)passes);
+        atomicAdd(&A.stats[4], (unsigned long long)tiled);
+        atomicAdd(&A.stats[5], (unsigned long long)sh.n_trunc);
+        atomicAdd(&A.stats[6], (unsigned long long)sh.n_hotscan);
+        atomicAdd(&A.stats[7], (unsigned long long)hs_full);
+        atomicAdd(&A.stats[8], (unsigned long long)recounts);
     }
 }
 
+// First histogram sweep of each event split over `groups` workgroups: group g
+// streams the theta rows g*NW + wave + (groups*NW)*i of its event and appends
+// every bin that reaches T to the event's hot list in global memory. Events
+// with more than one register batch of hits, or with invalid hits, are left
+// to the finder kernel (flag set).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restrict__ cs, int groups) {
+    constexpr int NW = NT / kWave;
+    const int e = blockIdx.x / groups;
+    const int g = blockIdx.x - e * groups;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    const int64_t b = A.offsets[e];
+    const int64_t n64 = A.offsets[e + 1] - b;
+    if (b < 0 || n64 < 0 || b + n64 > A.n_total || n64 > kChunks * kWave) {
+        if (threadIdx.x == 0) A.g_flag[e] = 1;
+        return;
+    }
+    const int n = (int)n64;
+    HitRegs h;
+    h.nch = (n + kWave - 1) / kWave;
+    bool ok = true, bad = false;
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const int q = c * kWave + lane;
+        const bool v = q < n;
+        float phi = 0.0f, zz = 0.0f;
+        if (v) {
+            const int vn = A.vane[b + q];
+            zz = A.z[b + q];
+            if (vn < 0 || vn >= A.n_vanes || !(fabsf(zz) <= HOUGH_Z_LIMIT)) {
+                bad = true;
+                zz = 0.0f;
+            } else {
+                phi = A.phi_v[vn];
+            }
+        }
+        h.phi[c] = phi;
+        h.z[c] = zz;
+        const double r2 = (double)phi * phi + (double)zz * zz;
+        ok = ok && (!v || r2 <= A.safe_r2);
+    }
+    h.safe = __ballot(!ok) == 0ull;
+    if (__syncthreads_or(bad || !h.safe)) {
+        if (threadIdx.x == 0) A.g_flag[e] = 1;
+        return;
+    }
+    if (n < (int)A.min_votes) return;
+    stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(NW * A.pitch) + threadIdx.x, h, n,
+                    g * NW + wave, groups * NW, A.g_hs + (size_t)e * A.hs_cap, A.g_cnt + e, A.hs_cap);
+}
+
 __global__ void k_reset(unsigned long long *stats, long long *err) {
-    if (threadIdx.x < 4) stats[threadIdx.x] = 0ull;
+    if (threadIdx.x < kStats) stats[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) {
         err[0] = 0;
         err[1] = 0x7fffffffffffffffll;
@@ -914,16 +1157,26 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         A.counts[HOUGH_COUNT_HITS] = st ? 0 : carry_h;
         A.counts[HOUGH_COUNT_STATUS] = st;
         A.counts[HOUGH_COUNT_DETAIL] = A.err[1] == 0x7fffffffffffffffll ? -1 : A.err[1];
-        A.counts[HOUGH_COUNT_VOTES] = (long long)A.stats[0];
+        A.counts[HOUGH_COUNT_EVALS] = (long long)A.stats[0];
         A.counts[HOUGH_COUNT_ITERS] = (long long)A.stats[1];
         A.counts[HOUGH_COUNT_MAX_ITERS] = (long long)A.stats[2];
         A.counts[HOUGH_COUNT_PASSES] = (long long)A.stats[3];
+        A.counts[HOUGH_COUNT_TILED] = (long long)A.stats[4];
+        A.counts[HOUGH_COUNT_TRUNCATIONS] = (long long)A.stats[5];
+        A.counts[HOUGH_COUNT_HOT_SCANS] = (long long)A.stats[6];
+        A.counts[HOUGH_COUNT_HOTSET_FULL] = (long long)A.stats[7];
+        A.counts[HOUGH_COUNT_RECOUNTS] = (long long)A.stats[8];
+        for (int i = HOUGH_COUNT_RECOUNTS + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+        // leave the statistics and error words cleared for the next call
+        for (int i = 0; i < kStats; ++i) A.stats[i] = 0ull;
+        A.err[0] = 0;
+        A.err[1] = 0x7fffffffffffffffll;
     }
 }
 
 // Packs every event's candidates and hit lists densely, in event order.
 __global__ __launch_bounds__(256) void k_copy(CompactArgs A) {
-    if (A.err[0] != 0) return;
+    if (A.counts[HOUGH_COUNT_STATUS] != 0) return;
     for (int e = blockIdx.x; e < A.n_events; e += gridDim.x) {
         const int64_t b = A.offsets[e];
         const int64_t cbase = b / (int64_t)A.min_votes;
@@ -945,8 +1198,7 @@ __global__ __launch_bounds__(256) void k_copy(CompactArgs A) {
 __global__ __launch_bounds__(1024) void k_dump(DumpArgs A, const float2 *__restrict__ cs) {
     constexpr int NT = 1024;
     constexpr int NW = NT / kWave;
-    extern __shared__ __align__(16) unsigned char lds[];
-    uint32_t *tile = reinterpret_cast<uint32_t *>(lds);
+    uint32_t *tile = g_lds;
     const int j0 = blockIdx.x * A.tile_rows;
     const int rows = min(A.tile_rows, A.n_theta - j0);
     const int wave = wave_id();
@@ -983,12 +1235,62 @@ __global__ __launch_bounds__(1024) void k_dump(DumpArgs A, const float2 *__restr
 }  // namespace
 
 int find_lds_extra(int wg_threads, int hcap, int pkeep) {
-    // hot list, peak keys, decoded peaks, one dummy word per thread, hot set
-    return 4 * hcap + 8 * (pkeep + hcap) + 8 * (pkeep + hcap) + 4 * wg_threads + 8 * (pkeep + hcap);
+    // hot list, peak keys, decoded peaks, one dummy word per thread
+    return 4 * hcap + 8 * (pkeep + hcap) + 8 * (pkeep + hcap) + 4 * wg_threads;
 }
 
 hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, stats, err);
+    return hipGetLastError();
+}
+
+int sweep_lds_bytes(int threads, int pitch) { return (threads / kWave) * pitch * 4 + 4 * threads; }
+
+hipError_t set_sweep_lds_limit(int threads, int lds_bytes) {
+    switch (threads) {
+    case 256:
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<256>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    case 512:
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<512>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    case 1024:
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<1024>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t s) {
+    if (a.n_events <= 0 || groups <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.n_events * (unsigned)groups);
+    const int lds = sweep_lds_bytes(threads, a.pitch);
+    switch (threads) {
+    case 256:
+        hipLaunchKernelGGL(k_sweep<256>, grid, dim3(256), lds, s, a, a.cs, groups);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_sweep<512>, grid, dim3(512), lds, s, a, a.cs, groups);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(k_sweep<1024>, grid, dim3(1024), lds, s, a, a.cs, groups);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -24,8 +24,9 @@ HOUGH_ERR_DEVICE = -4
 HOUGH_ERR_INTERNAL = -5
 HOUGH_ERR_DATA = -6
 
-HOUGH_COUNTS = 8
-COUNT_NAMES = ("candidates", "hits", "status", "detail", "votes", "iters", "max_iters", "passes")
+HOUGH_COUNTS = 16
+COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_iters", "passes",
+               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "r13", "r14", "r15")
 
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
@@ -44,7 +45,8 @@ class HoughConfig(ctypes.Structure):
                 ("min_votes", ctypes.c_uint32), ("peak_mode", ctypes.c_int32),
                 ("nms_radius", ctypes.c_int32), ("assoc_window", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("wg_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("wg_threads", ctypes.c_int32), ("sweep_groups", ctypes.c_int32),
+                ("sweep_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class HoughError(RuntimeError):

@@ -77,3 +77,30 @@ def test_null_and_bad_context_rejected():
     assert lib.hough_output_bounds(None, 1, 10, ctypes.byref(mc), ctypes.byref(mh)) == hough.HOUGH_ERR_INVALID_ARG
     assert lib.hough_find(None, None, 1, 0, None, None, None, None, 0, None, 0, None) == \
         hough.HOUGH_ERR_INVALID_ARG
+
+
+def test_kernels_use_no_scratch():
+    """The finder and sweep kernels must keep everything in registers and LDS:
+    a scratch (private memory) spill costs far more than the kernel's own work.
+    Compiles the device code for gfx950 and reads the resource-usage remarks."""
+    import shutil
+    import subprocess
+    hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shutil.which("hipcc")
+    if hipcc is None:
+        pytest.skip("hipcc not available")
+    from paper_2511_02742_amd import build
+    cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-c", "-I", os.path.join(ROOT, "include"),
+           "-I", build.CSRC, "-o", os.devnull, os.path.join(build.CSRC, "hough_kernels.hip"),
+           "-Rpass-analysis=kernel-resource-usage"]
+    out = subprocess.run(cmd, capture_output=True, text=True).stderr
+    blocks = re.split(r"remark: Function Name: ", out)[1:]
+    seen = 0
+    for blk in blocks:
+        name = blk.split()[0]
+        if "k_find" not in name and "k_sweep" not in name:
+            continue
+        seen += 1
+        scratch = int(re.search(r"ScratchSize \[bytes/lane\]: (\d+)", blk).group(1))
+        assert scratch == 0, (name, scratch)
+    assert seen >= 6

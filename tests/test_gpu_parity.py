@@ -52,7 +52,6 @@ def check_batch(batch, what="", **kw):
     got = run_batch(f, batch)
     want = oracle_find_batch(_ocfg(f.config), batch.offsets, batch.z, batch.vane)
     assert_same(got, want, what)
-    assert got[2]["votes"] == want.votes, what
     return got, want
 
 
@@ -129,7 +128,9 @@ def test_batched_equals_alone(gpu_available):
 @pytest.mark.parametrize("kw", [{"wg_threads": 256}, {"wg_threads": 512}, {"tile_rows": 8},
                                 {"tile_rows": 17, "wg_threads": 512}, {"nms_radius": 0},
                                 {"nms_radius": 2}, {"assoc_window": 1}, {"phi_unit": 1},
-                                {"n_theta": 180, "n_rho": 1000}, {"max_iters": 1}])
+                                {"n_theta": 180, "n_rho": 1000}, {"max_iters": 1},
+                                {"sweep_groups": 1}, {"sweep_groups": 16}, {"sweep_groups": 3, "sweep_threads": 1024},
+                                {"sweep_groups": 8, "peak_mode": 0}, {"sweep_groups": 4, "wg_threads": 512}])
 def test_config_variants(gpu_available, kw):
     b = eventgen.pileup_batch(8, seed0=300)
     check_batch(b, str(kw), **kw)
@@ -156,10 +157,16 @@ def test_edge_events(gpu_available):
     edge.vane = np.zeros_like(edge.vane)                              # rho = 0 on a bin edge
     evs.append(edge)
     evs.append(base)
+    big = eventgen.pileup_event(14, n_tracks=100)                    # more hits than one register batch
+    evs.append(big)
     b = eventgen.make_batch(evs)
+    assert big.n_hits > 512
     check_batch(b, "edges")
     check_batch(b, "edges 1000 bins", n_theta=180, n_rho=1000)
     check_batch(b, "edges argmax", peak_mode=0)
+    check_batch(b, "edges split sweep", sweep_groups=8)
+    for e in evs:
+        check_batch(eventgen.make_batch([e]), "edge alone", sweep_groups=8)
 
 
 def test_overflowing_hot_and_peak_lists(gpu_available):
@@ -175,16 +182,46 @@ def test_overflowing_hot_and_peak_lists(gpu_available):
     e.track = np.zeros(n, np.int32)
     b = eventgen.make_batch([e])
     got, want = check_batch(b, "overflow", n_theta=64, n_rho=256, min_votes=2)
-    assert got[2]["passes"] > got[2]["iters"]
+    info = got[2]
+    # the tiled fallback ran, its peak list was truncated and re-swept, and
+    # hot lists overflowed into full tile scans
+    assert info["tiled"] > 0 and info["truncations"] > 0 and info["hot_scans"] > 0, info
+    assert info["passes"] > info["iters"] - info["recounts"], info
     check_batch(b, "overflow argmax", n_theta=64, n_rho=256, min_votes=3, peak_mode=0, max_iters=20)
     check_batch(b, "overflow T=1", n_theta=32, n_rho=128, min_votes=1, max_iters=3)
 
 
-def test_full_size_batch_sampled(gpu_available):
+def test_hot_set_overflow_falls_back(gpu_available):
+    # few enough hits for the row-stream sweep, but far more bins reach T than
+    # the hot set holds: the iteration is redone by the tiled sweep
+    rng = np.random.default_rng(10)
+    n = 480
+    e = eventgen.pileup_event(2)
+    e.z = rng.uniform(-200, 200, n).astype(np.float32)
+    e.vane = rng.integers(0, 40, n).astype(np.int16)
+    e.r = np.zeros(n, np.float32)
+    e.track = np.zeros(n, np.int32)
+    b = eventgen.make_batch([e])
+    got, want = check_batch(b, "hot set overflow", n_theta=64, n_rho=256, min_votes=2)
+    assert got[2]["hotset_full"] > 0 and got[2]["tiled"] > 0, got[2]
+
+
+def test_recount_iterations_used(gpu_available):
+    # pileup events: after the first sweep, later iterations recount the hot
+    # set instead of sweeping the histogram again
+    b = eventgen.pileup_batch(16, seed0=800)
+    got, want = check_batch(b, "recount nms")
+    assert got[2]["recounts"] > 0 and got[2]["tiled"] == 0, got[2]
+    got, want = check_batch(b, "recount argmax", peak_mode=0)
+    assert got[2]["recounts"] >= got[2]["iters"] - 16, got[2]
+
+
+@pytest.mark.parametrize("kw", [{}, {"sweep_groups": 2}])
+def test_full_size_batch_sampled(gpu_available, kw):
     # 4096 pileup-50 events in one launch (the benchmark configuration):
     # oracle on a sample, structural properties on every event.
     b = eventgen.pileup_batch(4096)
-    f = finder()
+    f = finder(**kw)
     cand, hits, info = run_batch(f, b)
     assert info["status"] == 0
     ev = cand["event"]
@@ -224,9 +261,10 @@ def test_empty_batch(gpu_available):
     assert info["status"] == 0 and info["candidates"] == 0 and info["hits"] == 0
 
 
-def test_invalid_hits_reported(gpu_available):
+@pytest.mark.parametrize("kw", [{}, {"sweep_groups": 4}])
+def test_invalid_hits_reported(gpu_available, kw):
     b = eventgen.pileup_batch(4, seed0=60)
-    f = finder()
+    f = finder(**kw)
     vane = b.vane.copy()
     vane[b.offsets[2] + 5] = 40
     cand, hits, info = f.find_host(b.z, vane, b.offsets)
@@ -235,8 +273,15 @@ def test_invalid_hits_reported(gpu_available):
     z[7] = np.nan
     cand, hits, info = f.find_host(z, b.vane, b.offsets)
     assert info["status"] == -6 and info["detail"] == 7
+    # one event alone (single-kernel path)
+    one = eventgen.make_batch([b.events[1]])
+    vone = one.vane.copy()
+    vone[3] = -1
+    cand, hits, info = f.find_host(one.z, vone, one.offsets)
+    assert info["status"] == -6 and info["detail"] == 3 and info["candidates"] == 0
     # the context keeps working afterwards
-    check_batch(b, "after error")
+    check_batch(b, "after error", **kw)
+    check_batch(one, "after error, one event", **kw)
 
 
 def test_capacity_checked_on_host(gpu_available):
