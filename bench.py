@@ -126,11 +126,27 @@ def main():
     log("plain: %.0f events/s, p50 %.1f us, p99 %.1f us" % (plain_rate, 1e6 * np.percentile(lat, 50),
                                                               1e6 * np.percentile(lat, 99)))
 
+    # ---- HBM traffic of the finder kernel from the committed counter summary
+    # (reported only while the kernel source still matches the one profiled)
+    traffic = None
+    try:
+        from paper_2511_02742_amd.prof_summary import kernel_source_hash
+        kv = {}
+        with open(os.path.join(ROOT, "profiles", "k_find_pileup50.txt")) as fh:
+            for line in fh:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_sha256_16") == kernel_source_hash() and "fetch_bytes_per_launch" in kv:
+            traffic = float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (OSError, ValueError):
+        traffic = None
+
     # ---- roofline of the finder kernel ------------------------------------
     flops = FLOPS_PER_VOTE * info["evals"]
     achieved = flops / (kern_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
                 "evals_per_launch": info["evals"], "flops_per_eval": FLOPS_PER_VOTE,
                 "evals_per_s": round(info["evals"] / (kern_avg_ms * 1e-3), 1)}

@@ -204,6 +204,40 @@ hough_status hough_launch_shape(const void *ctx, int32_t *tile_rows, int32_t *wg
 hough_status hough_set_timing(void *ctx, int enable);
 hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, int reset);
 
+/*
+ * Captured launch (batched form). Records the kernel sequence hough_find
+ * enqueues for exactly these arguments into a HIP graph, instantiated once;
+ * each hough_graph_launch replays it on `stream` and computes what hough_find
+ * would compute for the data the buffers hold at replay time. The graph owns
+ * a private workspace, so the context's own calls do not disturb it; the
+ * context (tables) must outlive the graph, and hough_destroy refuses a
+ * context with live graphs. Replays on one graph must not overlap (they share
+ * the graph's workspace). Arguments as for hough_find; *graph receives a host
+ * handle. Nothing is enqueued by hough_graph_create itself except the
+ * workspace setup, which it synchronises.
+ */
+hough_status hough_graph_create(void *ctx, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
+                                const float *z, const int16_t *vane, hough_candidate *cand, int64_t cand_capacity,
+                                int32_t *hit_index, int64_t hit_capacity, int64_t *counts, void **graph);
+hough_status hough_graph_launch(void *graph, void *stream);
+hough_status hough_graph_destroy(void *graph);
+
+/*
+ * Launch-shape autotuner. Times every candidate shape (finder workgroup of
+ * 1024 or 512 threads; first sweep inside the finder, or split over 1, 2, 4
+ * or 8 workgroups per event of 256 or 512 threads) on the given batch
+ * (device arrays as for hough_find), `repeats` timed calls each after one
+ * warm-up call, on `stream`. Every shape must produce byte-identical outputs
+ * (else HOUGH_ERR_INTERNAL). *best receives `base` with the launch fields of
+ * the fastest shape, *best_ms its time per call, *n_tried (may be NULL) the
+ * number of shapes measured. Synchronises the stream; allocates and frees its
+ * own temporary outputs and contexts.
+ */
+hough_status hough_autotune(const hough_config *base, int device, void *stream, int32_t n_events,
+                            int64_t n_hits_total, const int64_t *event_offsets, const float *z,
+                            const int16_t *vane, int32_t repeats, hough_config *best, double *best_ms,
+                            int32_t *n_tried);
+
 const char *hough_status_string(hough_status st);
 /* Detail of the last failing call on ctx (empty string if none). */
 const char *hough_last_error(const void *ctx);

@@ -1,4 +1,5 @@
-// C-ABI layer: context, lookup tables, workspace, argument checks, launches.
+// C-ABI layer: context, lookup tables, workspace, argument checks, launches,
+// captured graphs and the launch-shape autotuner.
 
 #include <hip/hip_runtime.h>
 
@@ -20,9 +21,26 @@ constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 constexpr int kAssocMinBytes = 2048 * 20 + 64;  // one peak at the largest event (2048 chunks)
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
+constexpr uint32_t kCtxMagic = 0x48544631u;
+constexpr uint32_t kGraphMagic = 0x48544647u;
+
+// Device scratch of the finder, sized for a number of hits and events.
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+    int64_t hits = -1, events = -1;
+    int32_t *state = nullptr, *aidx = nullptr, *hits_ws = nullptr, *ev_ncand = nullptr, *ev_nhits = nullptr;
+    float *aphi = nullptr, *az = nullptr;
+    hough_candidate *cand_ws = nullptr;
+    long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
+    unsigned long long *stats = nullptr;
+    int64_t *tmp_offsets = nullptr;
+    unsigned long long *g_hs = nullptr;
+    int32_t *g_cnt = nullptr, *g_flag = nullptr;
+};
 
 struct Ctx {
-    uint32_t magic = 0x48544631u;
+    uint32_t magic = kCtxMagic;
     hough_config cfg{};
     int device = 0;
     // tables, host copies and device copies
@@ -37,18 +55,8 @@ struct Ctx {
     int stream_ok = 0, hs_off = 0, sorted_off = 0;
     double safe_r2 = -1.0;
     int dump_rows = 0, dump_lds = 0;
-    // workspace
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-    int64_t ws_hits = -1, ws_events = -1;
-    int32_t *state = nullptr, *aidx = nullptr, *hits_ws = nullptr, *ev_ncand = nullptr, *ev_nhits = nullptr;
-    unsigned long long *g_hs = nullptr;
-    int32_t *g_cnt = nullptr, *g_flag = nullptr;
-    float *aphi = nullptr, *az = nullptr;
-    hough_candidate *cand_ws = nullptr;
-    long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
-    unsigned long long *stats = nullptr;
-    int64_t *tmp_offsets = nullptr;
+    Workspace ws;
+    int graphs = 0;  // live captured graphs (they reference the tables)
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
@@ -57,15 +65,24 @@ struct Ctx {
     std::string last_error;
 };
 
+// A captured launch of the finder for fixed arguments, with its own workspace.
+struct Graph {
+    uint32_t magic = kGraphMagic;
+    Ctx *ctx = nullptr;
+    Workspace ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 thread_local std::string g_last_global_error;
 
 Ctx *as_ctx(void *p) {
     Ctx *c = static_cast<Ctx *>(p);
-    return (c && c->magic == 0x48544631u) ? c : nullptr;
+    return (c && c->magic == kCtxMagic) ? c : nullptr;
 }
 const Ctx *as_ctx(const void *p) {
     const Ctx *c = static_cast<const Ctx *>(p);
-    return (c && c->magic == 0x48544631u) ? c : nullptr;
+    return (c && c->magic == kCtxMagic) ? c : nullptr;
 }
 
 hough_status fail(Ctx *c, hough_status st, const std::string &msg) {
@@ -209,14 +226,21 @@ hough_status choose_shape(Ctx &c, std::string &why) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Grows the workspace for n_hits hits and n_events events.
-hough_status ensure_workspace(Ctx &c, int64_t n_hits, int64_t n_events, hipStream_t s) {
-    if (c.ws && n_hits <= c.ws_hits && n_events <= c.ws_events) return HOUGH_OK;
-    int64_t nh = std::max<int64_t>(n_hits, std::max<int64_t>(c.ws_hits, 1024));
-    int64_t ne = std::max<int64_t>(n_events, std::max<int64_t>(c.ws_events, 64));
-    if (c.ws) {
-        nh = std::max<int64_t>(nh, c.ws_hits + c.ws_hits / 2);
-        ne = std::max<int64_t>(ne, c.ws_events + c.ws_events / 2);
+void free_workspace(Workspace &w) {
+    if (w.base) (void)hipFree(w.base);
+    w = Workspace();
+}
+
+// Grows workspace w for n_hits hits and n_events events (work queued earlier
+// on stream s may still use the old block, so the stream is synchronised
+// before it is freed).
+hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_t n_events, hipStream_t s) {
+    if (w.base && n_hits <= w.hits && n_events <= w.events) return HOUGH_OK;
+    int64_t nh = std::max<int64_t>(n_hits, std::max<int64_t>(w.hits, 1024));
+    int64_t ne = std::max<int64_t>(n_events, std::max<int64_t>(w.events, 64));
+    if (w.base) {
+        nh = std::max<int64_t>(nh, w.hits + w.hits / 2);
+        ne = std::max<int64_t>(ne, w.events + w.events / 2);
     }
     const int64_t ncand = nh / (int64_t)c.cfg.min_votes + 1;
     size_t off = 0;
@@ -227,47 +251,42 @@ hough_status ensure_workspace(Ctx &c, int64_t n_hits, int64_t n_events, hipStrea
     const size_t o_stats = take(8 * 16), o_err = take(8 * 4), o_offs = take(8 * 4);
     const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
     const size_t o_ghs = c.sweep_groups > 0 ? take(8 * (size_t)ne * (size_t)std::max(c.hs_cap, 1)) : 0;
-    void *p = nullptr;
-    if (c.ws) {
-        // the old workspace may still be read by work queued earlier
+    if (w.base) {
         if (hipStreamSynchronize(s) != hipSuccess) return HOUGH_ERR_DEVICE;
-        (void)hipFree(c.ws);
-        c.ws = nullptr;
+        free_workspace(w);
     }
-    if (hipMalloc(&p, off) != hipSuccess) {
-        c.ws_hits = c.ws_events = -1;
-        return HOUGH_ERR_OOM;
-    }
+    void *p = nullptr;
+    if (hipMalloc(&p, off) != hipSuccess) return HOUGH_ERR_OOM;
     char *base = static_cast<char *>(p);
-    c.ws = p;
-    c.ws_bytes = off;
-    c.ws_hits = nh;
-    c.ws_events = ne;
-    c.state = reinterpret_cast<int32_t *>(base + o_state);
-    c.aidx = reinterpret_cast<int32_t *>(base + o_aidx);
-    c.aphi = reinterpret_cast<float *>(base + o_aphi);
-    c.az = reinterpret_cast<float *>(base + o_az);
-    c.hits_ws = reinterpret_cast<int32_t *>(base + o_hits);
-    c.cand_ws = reinterpret_cast<hough_candidate *>(base + o_cand);
-    c.ev_ncand = reinterpret_cast<int32_t *>(base + o_enc);
-    c.ev_nhits = reinterpret_cast<int32_t *>(base + o_enh);
-    c.ev_cout = reinterpret_cast<long long *>(base + o_eco);
-    c.ev_hout = reinterpret_cast<long long *>(base + o_eho);
-    c.stats = reinterpret_cast<unsigned long long *>(base + o_stats);
-    c.err = reinterpret_cast<long long *>(base + o_err);
-    c.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
-    c.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
-    c.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
-    c.g_hs = c.sweep_groups > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
+    w.base = p;
+    w.bytes = off;
+    w.hits = nh;
+    w.events = ne;
+    w.state = reinterpret_cast<int32_t *>(base + o_state);
+    w.aidx = reinterpret_cast<int32_t *>(base + o_aidx);
+    w.aphi = reinterpret_cast<float *>(base + o_aphi);
+    w.az = reinterpret_cast<float *>(base + o_az);
+    w.hits_ws = reinterpret_cast<int32_t *>(base + o_hits);
+    w.cand_ws = reinterpret_cast<hough_candidate *>(base + o_cand);
+    w.ev_ncand = reinterpret_cast<int32_t *>(base + o_enc);
+    w.ev_nhits = reinterpret_cast<int32_t *>(base + o_enh);
+    w.ev_cout = reinterpret_cast<long long *>(base + o_eco);
+    w.ev_hout = reinterpret_cast<long long *>(base + o_eho);
+    w.stats = reinterpret_cast<unsigned long long *>(base + o_stats);
+    w.err = reinterpret_cast<long long *>(base + o_err);
+    w.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
+    w.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
+    w.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
+    w.g_hs = c.sweep_groups > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
     // statistics, error and split-sweep words start cleared; every call
     // leaves them so
-    if (hough::launch_reset(c.stats, c.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
-    if (hough::launch_zero_i32(c.g_cnt, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
-    if (hough::launch_zero_i32(c.g_flag, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_reset(w.stats, w.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_zero_i32(w.g_cnt, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_zero_i32(w.g_flag, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     return HOUGH_OK;
 }
 
-hough::FindArgs find_args(const Ctx &c) {
+hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     hough::FindArgs a{};
     const hough_config &g = c.cfg;
     a.n_theta = g.n_theta;
@@ -284,16 +303,16 @@ hough::FindArgs find_args(const Ctx &c) {
     a.phi_v = c.d_phi;
     a.theta_c = c.d_thc;
     a.rho_c = c.d_rhoc;
-    a.state = c.state;
-    a.aidx = c.aidx;
-    a.aphi = c.aphi;
-    a.az = c.az;
-    a.cand_ws = c.cand_ws;
-    a.hits_ws = c.hits_ws;
-    a.ev_ncand = c.ev_ncand;
-    a.ev_nhits = c.ev_nhits;
-    a.stats = c.stats;
-    a.err = c.err;
+    a.state = w.state;
+    a.aidx = w.aidx;
+    a.aphi = w.aphi;
+    a.az = w.az;
+    a.cand_ws = w.cand_ws;
+    a.hits_ws = w.hits_ws;
+    a.ev_ncand = w.ev_ncand;
+    a.ev_nhits = w.ev_nhits;
+    a.stats = w.stats;
+    a.err = w.err;
     a.tile_rows = c.tile_rows;
     a.pitch = c.pitch;
     a.tile_bytes = c.tile_bytes;
@@ -304,39 +323,41 @@ hough::FindArgs find_args(const Ctx &c) {
     a.hs_cap = c.hs_cap;
     a.hs_off = c.hs_off;
     a.sorted_off = c.sorted_off;
-    a.g_cnt = c.g_cnt;
-    a.g_flag = c.g_flag;
-    a.g_hs = (c.sweep_groups > 0 && c.stream_ok) ? c.g_hs : nullptr;
+    a.g_cnt = w.g_cnt;
+    a.g_flag = w.g_flag;
+    a.g_hs = (c.sweep_groups > 0 && c.stream_ok) ? w.g_hs : nullptr;
     return a;
 }
 
-// Launches the finder. With counts != NULL (one event) the kernel writes the
-// candidates, hit lists and counts straight into cand / hits / counts;
-// otherwise it fills the workspace slots for the compaction kernels.
-hough_status run_find(Ctx &c, hipStream_t s, int32_t n_events, int64_t n_total, const int64_t *offsets,
-                      const float *z, const int16_t *vane, int32_t max_iters, hough_candidate *cand,
-                      int32_t *hits, int64_t *counts) {
-    hough::FindArgs a = find_args(c);
+// Enqueues the whole finder on stream s: the optional split sweep, the finder
+// and, for several events, the compaction. One event takes the single-kernel
+// path: its slots are the dense layout, so the finder writes cand, hit_index
+// and counts itself. With timing on, HIP events bracket the finder kernel.
+hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
+                          const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
+                          hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed) {
+    hough::FindArgs a = find_args(c, w);
     a.n_events = n_events;
     a.n_total = n_total;
     a.offsets = offsets;
     a.z = z;
     a.vane = vane;
     a.max_iters = max_iters;
-    a.counts = counts;
-    if (counts) {
+    const bool single = n_events == 1;
+    if (single) {
+        a.counts = counts;
         a.cand_ws = cand;
-        a.hits_ws = hits;
+        a.hits_ws = hit_index;
+    }
+    if (a.g_hs != nullptr && n_events > 0) {
+        hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
+        if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c.timing && n_events > 0) {
+    if (timed && n_events > 0) {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return fail(&c, HOUGH_ERR_DEVICE, "hipEventCreate failed");
         (void)hipEventRecord(e0, s);
-    }
-    if (a.g_hs != nullptr) {
-        hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
-        if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
     hipError_t st = hough::launch_find(a, c.wg_threads, c.lds_bytes, s);
     if (st != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("finder launch failed: ") + hipGetErrorString(st));
@@ -344,32 +365,49 @@ hough_status run_find(Ctx &c, hipStream_t s, int32_t n_events, int64_t n_total, 
         (void)hipEventRecord(e1, s);
         c.ev_pairs.emplace_back(e0, e1);
     }
+    if (single) return HOUGH_OK;
+    hough::CompactArgs ca{};
+    ca.n_events = n_events;
+    ca.n_total = n_total;
+    ca.min_votes = c.cfg.min_votes;
+    ca.offsets = offsets;
+    ca.cand_ws = w.cand_ws;
+    ca.hits_ws = w.hits_ws;
+    ca.ev_ncand = w.ev_ncand;
+    ca.ev_nhits = w.ev_nhits;
+    ca.ev_cout = w.ev_cout;
+    ca.ev_hout = w.ev_hout;
+    ca.stats = w.stats;
+    ca.err = w.err;
+    ca.cand = cand;
+    ca.hit_index = hit_index;
+    ca.counts = counts;
+    if (hough::launch_compact(ca, s) != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, "compaction launch failed");
     return HOUGH_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-hough_status hough_config_default(hough_config *cfg) {
-    if (!cfg) return HOUGH_ERR_INVALID_ARG;
-    std::memset(cfg, 0, sizeof(*cfg));
-    cfg->n_theta = 1024;
-    cfg->n_rho = 1024;
-    cfg->rho_min = -500.0f;
-    cfg->rho_max = 500.0f;
-    cfg->n_vanes = 40;
-    cfg->phi_unit = 0;
-    cfg->min_votes = 6;
-    cfg->peak_mode = 1;
-    cfg->nms_radius = 1;
-    cfg->assoc_window = 0;
-    cfg->max_iters = 0;
+// Host-side argument checks shared by hough_find and hough_graph_create.
+hough_status check_find_args(Ctx *c, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
+                             const float *z, const int16_t *vane, const hough_candidate *cand,
+                             int64_t cand_capacity, const int32_t *hit_index, int64_t hit_capacity,
+                             const int64_t *counts) {
+    if (n_events < 0 || n_hits_total < 0) return fail(c, HOUGH_ERR_INVALID_ARG, "negative size");
+    if (!event_offsets || !counts) return fail(c, HOUGH_ERR_INVALID_ARG, "null offsets or counts");
+    if (n_hits_total > 0 && (!z || !vane)) return fail(c, HOUGH_ERR_INVALID_ARG, "null hit arrays");
+    if (n_events == 0 && n_hits_total != 0) return fail(c, HOUGH_ERR_INVALID_ARG, "hits without events");
+    if (n_hits_total > 0x7fffffffLL) return fail(c, HOUGH_ERR_INVALID_ARG, "more than 2^31-1 hits per call");
+    const int64_t need_c = n_hits_total / (int64_t)c->cfg.min_votes;
+    if (cand_capacity < need_c || hit_capacity < n_hits_total) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "output capacity too small: need %lld candidates and %lld hit indices",
+                      (long long)need_c, (long long)n_hits_total);
+        return fail(c, HOUGH_ERR_CAPACITY, buf);
+    }
+    if ((need_c > 0 && !cand) || (n_hits_total > 0 && !hit_index)) return fail(c, HOUGH_ERR_INVALID_ARG, "null outputs");
     return HOUGH_OK;
 }
 
-hough_status hough_create(const hough_config *cfg, int device, void **out) {
-    if (!out) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "null output pointer");
+hough_status make_context(const hough_config *cfg, int device, Ctx **out) {
     *out = nullptr;
     std::string why;
     hough_status st = check_config(cfg, why);
@@ -415,19 +453,53 @@ hough_status hough_create(const hough_config *cfg, int device, void **out) {
     return HOUGH_OK;
 }
 
-hough_status hough_destroy(void *ctx) {
-    if (!ctx) return HOUGH_OK;
-    Ctx *c = as_ctx(ctx);
-    if (!c) return HOUGH_ERR_INVALID_ARG;
+void free_context(Ctx *c) {
     (void)hipSetDevice(c->device);
     for (auto &pr : c->ev_pairs) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
-    if (c->ws) (void)hipFree(c->ws);
+    free_workspace(c->ws);
     if (c->d_tables) (void)hipFree(c->d_tables);
     c->magic = 0;
     delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+hough_status hough_config_default(hough_config *cfg) {
+    if (!cfg) return HOUGH_ERR_INVALID_ARG;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_theta = 1024;
+    cfg->n_rho = 1024;
+    cfg->rho_min = -500.0f;
+    cfg->rho_max = 500.0f;
+    cfg->n_vanes = 40;
+    cfg->phi_unit = 0;
+    cfg->min_votes = 6;
+    cfg->peak_mode = 1;
+    cfg->nms_radius = 1;
+    cfg->assoc_window = 0;
+    cfg->max_iters = 0;
+    return HOUGH_OK;
+}
+
+hough_status hough_create(const hough_config *cfg, int device, void **out) {
+    if (!out) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "null output pointer");
+    Ctx *c = nullptr;
+    hough_status st = make_context(cfg, device, &c);
+    *out = c;
+    return st;
+}
+
+hough_status hough_destroy(void *ctx) {
+    if (!ctx) return HOUGH_OK;
+    Ctx *c = as_ctx(ctx);
+    if (!c) return HOUGH_ERR_INVALID_ARG;
+    if (c->graphs > 0) return fail(c, HOUGH_ERR_INVALID_ARG, "destroy the context's graphs first");
+    free_context(c);
     return HOUGH_OK;
 }
 
@@ -446,50 +518,16 @@ hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hit
                         int64_t hit_capacity, int64_t *counts) {
     Ctx *c = as_ctx(ctx);
     if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
-    if (n_events < 0 || n_hits_total < 0) return fail(c, HOUGH_ERR_INVALID_ARG, "negative size");
-    if (!event_offsets || !counts) return fail(c, HOUGH_ERR_INVALID_ARG, "null offsets or counts");
-    if (n_hits_total > 0 && (!z || !vane)) return fail(c, HOUGH_ERR_INVALID_ARG, "null hit arrays");
-    if (n_events == 0 && n_hits_total != 0) return fail(c, HOUGH_ERR_INVALID_ARG, "hits without events");
-    if (n_hits_total > 0x7fffffffLL) return fail(c, HOUGH_ERR_INVALID_ARG, "more than 2^31-1 hits per call");
-    const int64_t need_c = n_hits_total / (int64_t)c->cfg.min_votes;
-    if (cand_capacity < need_c || hit_capacity < n_hits_total) {
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "output capacity too small: need %lld candidates and %lld hit indices",
-                      (long long)need_c, (long long)n_hits_total);
-        return fail(c, HOUGH_ERR_CAPACITY, buf);
-    }
-    if ((need_c > 0 && !cand) || (n_hits_total > 0 && !hit_index)) return fail(c, HOUGH_ERR_INVALID_ARG, "null outputs");
+    hough_status st = check_find_args(c, n_events, n_hits_total, event_offsets, z, vane, cand, cand_capacity,
+                                      hit_index, hit_capacity, counts);
+    if (st) return st;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hough_status st = ensure_workspace(*c, n_hits_total, n_events, s);
+    st = ensure_workspace(*c, c->ws, n_hits_total, n_events, s);
     if (st) return fail(c, st, "workspace allocation failed");
-    if (n_events == 1) {
-        // one event: its slots are the dense layout, one kernel does all
-        st = run_find(*c, s, 1, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand, hit_index, counts);
-        if (st) return st;
-        c->last_error.clear();
-        return HOUGH_OK;
-    }
-    st = run_find(*c, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, nullptr, nullptr,
-                  nullptr);
+    st = enqueue_find(*c, c->ws, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand,
+                      hit_index, counts, c->timing);
     if (st) return st;
-    hough::CompactArgs ca{};
-    ca.n_events = n_events;
-    ca.n_total = n_hits_total;
-    ca.min_votes = c->cfg.min_votes;
-    ca.offsets = event_offsets;
-    ca.cand_ws = c->cand_ws;
-    ca.hits_ws = c->hits_ws;
-    ca.ev_ncand = c->ev_ncand;
-    ca.ev_nhits = c->ev_nhits;
-    ca.ev_cout = c->ev_cout;
-    ca.ev_hout = c->ev_hout;
-    ca.stats = c->stats;
-    ca.err = c->err;
-    ca.cand = cand;
-    ca.hit_index = hit_index;
-    ca.counts = counts;
-    if (hough::launch_compact(ca, s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "compaction launch failed");
     c->last_error.clear();
     return HOUGH_OK;
 }
@@ -503,14 +541,15 @@ hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, co
         return fail(c, HOUGH_ERR_INVALID_ARG, "bad debug_accumulator arguments");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hough_status st = ensure_workspace(*c, n_hits, 1, s);
+    Workspace &w = c->ws;
+    hough_status st = ensure_workspace(*c, w, n_hits, 1, s);
     if (st) return fail(c, st, "workspace allocation failed");
-    if (hough::launch_set_offsets(c->tmp_offsets, n_hits, s) != hipSuccess)
+    if (hough::launch_set_offsets(w.tmp_offsets, n_hits, s) != hipSuccess)
         return fail(c, HOUGH_ERR_DEVICE, "offset launch failed");
     // iters == 0 still runs the finder for its input validation; the dump
     // then ignores the state and counts every hit
-    st = run_find(*c, s, 1, n_hits, c->tmp_offsets, z, vane, iters > 0 ? iters : 0, c->cand_ws, c->hits_ws,
-                  counts);
+    st = enqueue_find(*c, w, s, 1, n_hits, w.tmp_offsets, z, vane, iters > 0 ? iters : 0, w.cand_ws, w.hits_ws,
+                      counts, false);
     if (st) return st;
     hough::DumpArgs da{};
     da.n_theta = c->cfg.n_theta;
@@ -523,7 +562,7 @@ hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, co
     da.n = n_hits;
     da.z = z;
     da.vane = vane;
-    da.state = iters > 0 ? c->state : nullptr;
+    da.state = iters > 0 ? w.state : nullptr;
     da.acc = acc_out;
     da.tile_rows = c->dump_rows;
     da.pitch = c->pitch;
@@ -580,6 +619,173 @@ hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, 
         c->timed_ms = 0.0;
         c->timed_launches = 0;
     }
+    return HOUGH_OK;
+}
+
+hough_status hough_graph_create(void *ctx, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
+                                const float *z, const int16_t *vane, hough_candidate *cand, int64_t cand_capacity,
+                                int32_t *hit_index, int64_t hit_capacity, int64_t *counts, void **graph) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
+    if (!graph) return fail(c, HOUGH_ERR_INVALID_ARG, "null graph pointer");
+    *graph = nullptr;
+    hough_status st = check_find_args(c, n_events, n_hits_total, event_offsets, z, vane, cand, cand_capacity,
+                                      hit_index, hit_capacity, counts);
+    if (st) return st;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    Graph *g = new (std::nothrow) Graph();
+    if (!g) return fail(c, HOUGH_ERR_OOM, "host allocation failed");
+    g->ctx = c;
+    hipStream_t cap = nullptr;
+    auto cleanup = [&](hough_status code, const char *msg) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (cap) {
+            (void)hipStreamSynchronize(cap);
+            (void)hipStreamDestroy(cap);
+        }
+        free_workspace(g->ws);
+        delete g;
+        return fail(c, code, msg);
+    };
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(HOUGH_ERR_DEVICE, "hipStreamCreate failed");
+    // the workspace (and its one-time clearing) is set up before capture
+    st = ensure_workspace(*c, g->ws, n_hits_total, n_events, cap);
+    if (st) return cleanup(st, "graph workspace allocation failed");
+    if (hipStreamSynchronize(cap) != hipSuccess) return cleanup(HOUGH_ERR_DEVICE, "hipStreamSynchronize failed");
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return cleanup(HOUGH_ERR_DEVICE, "hipStreamBeginCapture failed");
+    st = enqueue_find(*c, g->ws, cap, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand,
+                      hit_index, counts, false);
+    hipGraph_t captured = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cap, &captured);
+    g->graph = captured;
+    if (st) return cleanup(st, "capture failed");
+    if (ec != hipSuccess || !captured) return cleanup(HOUGH_ERR_DEVICE, "hipStreamEndCapture failed");
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        return cleanup(HOUGH_ERR_DEVICE, "hipGraphInstantiate failed");
+    (void)hipStreamDestroy(cap);
+    c->graphs += 1;
+    *graph = g;
+    c->last_error.clear();
+    return HOUGH_OK;
+}
+
+hough_status hough_graph_launch(void *graph, void *stream) {
+    Graph *g = static_cast<Graph *>(graph);
+    if (!g || g->magic != kGraphMagic) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad graph");
+    if (hipSetDevice(g->ctx->device) != hipSuccess) return fail(g->ctx, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    if (hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(g->ctx, HOUGH_ERR_DEVICE, "hipGraphLaunch failed");
+    return HOUGH_OK;
+}
+
+hough_status hough_graph_destroy(void *graph) {
+    if (!graph) return HOUGH_OK;
+    Graph *g = static_cast<Graph *>(graph);
+    if (g->magic != kGraphMagic) return HOUGH_ERR_INVALID_ARG;
+    (void)hipSetDevice(g->ctx->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    free_workspace(g->ws);
+    g->ctx->graphs -= 1;
+    g->magic = 0;
+    delete g;
+    return HOUGH_OK;
+}
+
+hough_status hough_autotune(const hough_config *base, int device, void *stream, int32_t n_events,
+                            int64_t n_hits_total, const int64_t *event_offsets, const float *z, const int16_t *vane,
+                            int32_t repeats, hough_config *best, double *best_ms, int32_t *n_tried) {
+    if (!base || !best || !best_ms || repeats < 1 || n_events < 1) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad autotune arguments");
+    std::string why;
+    hough_status st = check_config(base, why);
+    if (st) return fail(nullptr, st, why);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // candidate launch shapes: the finder's workgroup size, and the split
+    // first sweep's workgroups per event and threads
+    std::vector<hough_config> cands;
+    const int wgs[] = {1024, 512};
+    const int sweeps[][2] = {{0, 0}, {1, 256}, {1, 512}, {2, 256}, {2, 512}, {4, 256}, {8, 256}};
+    for (int wg : wgs)
+        for (auto &sw : sweeps) {
+            hough_config cfg = *base;
+            cfg.tile_rows = 0;
+            cfg.wg_threads = wg;
+            cfg.sweep_groups = sw[0];
+            cfg.sweep_threads = sw[1];
+            cands.push_back(cfg);
+        }
+    const int64_t ccap = std::max<int64_t>(n_hits_total / (int64_t)base->min_votes, 1);
+    const int64_t hcap = std::max<int64_t>(n_hits_total, 1);
+    hough_candidate *d_cand = nullptr;
+    int32_t *d_hits = nullptr;
+    int64_t *d_counts = nullptr;
+    if (hipMalloc(&d_cand, sizeof(hough_candidate) * ccap) != hipSuccess ||
+        hipMalloc(&d_hits, sizeof(int32_t) * hcap) != hipSuccess ||
+        hipMalloc(&d_counts, sizeof(int64_t) * HOUGH_COUNTS) != hipSuccess) {
+        (void)hipFree(d_cand);
+        (void)hipFree(d_hits);
+        (void)hipFree(d_counts);
+        return fail(nullptr, HOUGH_ERR_OOM, "autotune output allocation failed");
+    }
+    std::vector<unsigned char> ref, cur;
+    std::vector<int64_t> counts(HOUGH_COUNTS);
+    double best_t = 1e30;
+    int tried = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    st = HOUGH_OK;
+    for (const hough_config &cfg : cands) {
+        Ctx *c = nullptr;
+        if (make_context(&cfg, device, &c) != HOUGH_OK) continue;  // shape not supported here
+        hough_status r = hough_find(c, stream, n_events, n_hits_total, event_offsets, z, vane, d_cand, ccap, d_hits,
+                                    hcap, d_counts);
+        if (r == HOUGH_OK) {
+            (void)hipEventRecord(e0, s);
+            for (int i = 0; i < repeats && r == HOUGH_OK; ++i)
+                r = hough_find(c, stream, n_events, n_hits_total, event_offsets, z, vane, d_cand, ccap, d_hits,
+                               hcap, d_counts);
+            (void)hipEventRecord(e1, s);
+        }
+        float ms = 0.f;
+        if (r == HOUGH_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            hipMemcpy(counts.data(), d_counts, sizeof(int64_t) * HOUGH_COUNTS, hipMemcpyDeviceToHost) == hipSuccess &&
+            counts[HOUGH_COUNT_STATUS] == 0) {
+            // every shape must produce the same bytes
+            const size_t nc = (size_t)counts[HOUGH_COUNT_CANDIDATES], nh = (size_t)counts[HOUGH_COUNT_HITS];
+            cur.resize(nc * sizeof(hough_candidate) + nh * sizeof(int32_t));
+            (void)hipMemcpy(cur.data(), d_cand, nc * sizeof(hough_candidate), hipMemcpyDeviceToHost);
+            (void)hipMemcpy(cur.data() + nc * sizeof(hough_candidate), d_hits, nh * sizeof(int32_t),
+                            hipMemcpyDeviceToHost);
+            if (tried == 0) {
+                ref = cur;
+            } else if (cur != ref) {
+                st = fail(nullptr, HOUGH_ERR_INTERNAL, "launch shapes disagree on the result");
+            }
+            ++tried;
+            const double t = ms / repeats;
+            if (t < best_t) {
+                best_t = t;
+                *best = cfg;
+                best->tile_rows = c->tile_rows;
+            }
+        }
+        free_context(c);
+        if (st) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_cand);
+    (void)hipFree(d_hits);
+    (void)hipFree(d_counts);
+    if (st) return st;
+    if (tried == 0) return fail(nullptr, HOUGH_ERR_DEVICE, "no launch shape ran");
+    *best_ms = best_t;
+    if (n_tried) *n_tried = tried;
     return HOUGH_OK;
 }
 

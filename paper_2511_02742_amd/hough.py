@@ -30,7 +30,8 @@ COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_
 
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
-           "hough_timing", "hough_status_string", "hough_last_error")
+           "hough_timing", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
+           "hough_autotune", "hough_status_string", "hough_last_error")
 
 cand_dtype = np.dtype([("event", "<i4"), ("iter", "<i4"), ("theta_bin", "<i4"), ("rho_bin", "<i4"),
                        ("peak_votes", "<u4"), ("n_hits", "<u4"), ("hit_offset", "<i8"),
@@ -93,6 +94,15 @@ def load_library(path: str = LIB_PATH):
     lib.hough_set_timing.restype = st
     lib.hough_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), ctypes.c_int]
     lib.hough_timing.restype = st
+    lib.hough_graph_create.argtypes = [P, I32, I64, P, P, P, P, I64, P, I64, P, ctypes.POINTER(P)]
+    lib.hough_graph_create.restype = st
+    lib.hough_graph_launch.argtypes = [P, P]
+    lib.hough_graph_launch.restype = st
+    lib.hough_graph_destroy.argtypes = [P]
+    lib.hough_graph_destroy.restype = st
+    lib.hough_autotune.argtypes = [cfgp, ctypes.c_int, P, I32, I64, P, P, P, I32, cfgp,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
+    lib.hough_autotune.restype = st
     lib.hough_status_string.argtypes = [ctypes.c_int]
     lib.hough_status_string.restype = ctypes.c_char_p
     lib.hough_last_error.argtypes = [P]
@@ -258,6 +268,23 @@ class HoughFinder:
         self.lib.hough_launch_shape(self._h, ctypes.byref(t), ctypes.byref(w), ctypes.byref(l))
         return {"tile_rows": t.value, "wg_threads": w.value, "lds_bytes": l.value}
 
+    def capture(self, z, vane, offsets, out: Optional[FindOutput] = None) -> "FindGraph":
+        """Captures the batched launch for these device tensors (see hough_graph_create)."""
+        torch = self._torch
+        n_events = offsets.numel() - 1
+        n_hits = z.numel()
+        if out is None:
+            out = self.alloc_outputs(n_events, n_hits)
+        g = ctypes.c_void_p()
+        st = self.lib.hough_graph_create(self._h, n_events, n_hits, ctypes.c_void_p(offsets.data_ptr()),
+                                         ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(vane.data_ptr()),
+                                         ctypes.c_void_p(out.cand.data_ptr()), out.cand.shape[0],
+                                         ctypes.c_void_p(out.hit_index.data_ptr()), out.hit_index.numel(),
+                                         ctypes.c_void_p(out.counts.data_ptr()), ctypes.byref(g))
+        if st != HOUGH_OK:
+            raise self._err(st)
+        return FindGraph(self, g, out, (z, vane, offsets))
+
     def set_timing(self, enable: bool):
         self.lib.hough_set_timing(self._h, 1 if enable else 0)
 
@@ -268,3 +295,48 @@ class HoughFinder:
         if st != HOUGH_OK:
             raise self._err(st)
         return ms.value, n.value
+
+
+class FindGraph:
+    """A captured launch; keeps its context and buffers alive."""
+
+    def __init__(self, finder: HoughFinder, handle, out: FindOutput, inputs):
+        self.finder = finder
+        self._g = handle
+        self.out = out
+        self._inputs = inputs
+
+    def launch(self, stream=None) -> FindOutput:
+        st = self.finder.lib.hough_graph_launch(self._g, self.finder._stream(stream))
+        if st != HOUGH_OK:
+            raise self.finder._err(st)
+        return self.out
+
+    def close(self):
+        if getattr(self, "_g", None) is not None and self._g.value:
+            self.finder.lib.hough_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(z, vane, offsets, device: int = 0, repeats: int = 3, stream=None, **overrides):
+    """Runs hough_autotune on device tensors; returns (best config, ms per call, shapes tried)."""
+    import torch
+    lib = load_library()
+    base = default_config(**overrides)
+    best = HoughConfig()
+    ms = ctypes.c_double()
+    tried = ctypes.c_int32()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    st = lib.hough_autotune(ctypes.byref(base), device, ctypes.c_void_p(s.cuda_stream), offsets.numel() - 1,
+                            z.numel(), ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                            ctypes.c_void_p(vane.data_ptr()), repeats, ctypes.byref(best), ctypes.byref(ms),
+                            ctypes.byref(tried))
+    if st != HOUGH_OK:
+        raise HoughError(st, lib.hough_last_error(None).decode())
+    return best, ms.value, tried.value

@@ -1,0 +1,137 @@
+"""Summaries of rocprofv3 runs of the benchmark, written under ``profiles/``.
+
+Inputs are rocprofv3 output directories written with ``--output-format csv``:
+
+* a ``--kernel-trace --stats`` run (``*_kernel_stats.csv``): per-kernel call
+  counts and durations;
+* optionally one ``--pmc FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run
+  (``*_counter_collection.csv``) of a benchmark started with
+  ``--copy-calibration-mib M``: the device copy of M MiB is the reference
+  that turns the counters (KiB per dispatch) into bytes.
+
+The summary (markdown) states the command lines, the kernel table and the
+traffic figures; a key/value file next to it carries the figures the
+benchmark reports, with the hash of the kernel source they were taken from.
+
+python -m paper_2511_02742_amd.prof_summary --trace DIR [--fetch DIR --write DIR --copy-mib M]
+        --name NAME --command "..." [--command "..."]
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+from collections import defaultdict
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+KERNEL_SOURCE = os.path.join(PKG, "csrc", "hough_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    name = name.replace("hough::(anonymous namespace)::", "")
+    return name.split("(")[0][:60]
+
+
+def kernel_stats(trace_dir: str):
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no kernel_stats.csv under %s" % trace_dir)
+    rows = list(csv.DictReader(open(files[0])))
+    out = []
+    for r in rows:
+        out.append({"name": _short(r["Name"]), "calls": int(r["Calls"]),
+                     "total_ns": float(r["TotalDurationNs"]), "avg_ns": float(r["AverageNs"]),
+                     "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"]),
+                     "pct": float(r["Percentage"])})
+    return out
+
+
+def counter_per_dispatch(pmc_dir: str, counter: str):
+    files = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no counter_collection.csv under %s" % pmc_dir)
+    per = defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(files[0])):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        per[d] += float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"]
+    return per, names
+
+
+def traffic(fetch_dir: str, write_dir: str, copy_mib: int, kernel: str = "k_find"):
+    """HBM bytes per launch of `kernel` (median over dispatches of the largest
+    grid), scaled by the counters of the calibration copy."""
+    copy_bytes = float(copy_mib) * (1 << 20)
+    res = {}
+    for label, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        per, names = counter_per_dispatch(d, counter)
+        copies = [v for k, v in per.items() if "copy" in names[k].lower()]
+        if not copies:
+            raise ValueError("no copy kernel in %s" % d)
+        ref = max(copies) * 1024.0           # counter in KiB
+        scale = copy_bytes / ref if ref > 0 else float("nan")
+        mine = [v for k, v in per.items() if kernel in names[k]]
+        big = max(mine)
+        batched = [v for v in mine if v >= 0.5 * big]
+        res[label + "_bytes"] = statistics.median(batched) * 1024.0 * scale
+        res[label + "_scale"] = scale
+        res[label + "_dispatches"] = len(batched)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--name", required=True, help="summary base name under profiles/")
+    ap.add_argument("--command", action="append", default=[], help="a command line that produced the data")
+    ap.add_argument("--note", default="")
+    args = ap.parse_args()
+
+    stats = kernel_stats(args.trace)
+    h = kernel_source_hash()
+    lines = ["# %s" % args.name, ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += ["Kernel source hash (sha256/16 of csrc/hough_kernels.hip): `%s`" % h, "", "Commands:", ""]
+    lines += ["    %s" % c for c in args.command] + [""]
+    lines += ["| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append("| %s | %d | %.2f | %.2f | %.2f | %.3f | %.1f |" % (
+            r["name"], r["calls"], r["avg_ns"] / 1e3, r["min_ns"] / 1e3, r["max_ns"] / 1e3,
+            r["total_ns"] / 1e6, r["pct"]))
+    kv = {"kernel_sha256_16": h}
+    if args.fetch and args.write and args.copy_mib:
+        t = traffic(args.fetch, args.write, args.copy_mib)
+        lines += ["", "HBM traffic of the batched k_find launch (median over %d dispatches), from "
+                  "FETCH_SIZE / WRITE_SIZE scaled by a %d MiB device copy (scale fetch %.3f, write %.3f):"
+                  % (t["fetch_dispatches"], args.copy_mib, t["fetch_scale"], t["write_scale"]), "",
+                  "| read bytes | written bytes | total |", "|---|---|---|",
+                  "| %.0f | %.0f | %.0f |" % (t["fetch_bytes"], t["write_bytes"], t["fetch_bytes"] + t["write_bytes"])]
+        kv.update({"fetch_bytes_per_launch": "%.0f" % t["fetch_bytes"],
+                   "write_bytes_per_launch": "%.0f" % t["write_bytes"]})
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", args.name + ".md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(ROOT, "profiles", args.name + ".txt"), "w") as f:
+        for k, v in kv.items():
+            f.write("%s: %s\n" % (k, v))
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

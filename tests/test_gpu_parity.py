@@ -305,3 +305,59 @@ def test_deterministic_repeats(gpu_available):
     for _ in range(3):
         r = run_batch(f, b)
         assert np.array_equal(r[0], r0[0]) and np.array_equal(r[1], r0[1])
+
+
+def _permute_within_events(batch, seed):
+    rng = np.random.default_rng(seed)
+    z = batch.z.copy()
+    v = batch.vane.copy()
+    for e in range(batch.n_events):
+        lo, hi = batch.offsets[e], batch.offsets[e + 1]
+        p = lo + rng.permutation(hi - lo)
+        z[lo:hi] = batch.z[p]
+        v[lo:hi] = batch.vane[p]
+    return z, v
+
+
+@pytest.mark.parametrize("kw,n_events", [({}, 96), ({"sweep_groups": 2}, 96), ({}, 1)])
+def test_graph_replays_match_oracle(gpu_available, kw, n_events):
+    # captured launch: replays with eager work and synchronisations between
+    # them, the input buffers rewritten between replays; every replay is
+    # checked against the oracle of the data it saw
+    import torch
+    b = eventgen.poisson_batch(n_events, seed0=7000)
+    f = finder(**kw)
+    dev = torch.device("cuda", 0)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.vane).to(dev)
+    o = torch.from_numpy(b.offsets).to(dev)
+    g = f.capture(z, v, o)
+    other = eventgen.pileup_batch(3, seed0=7100)
+    ocfg = _ocfg(f.config)
+    for rep in range(4):
+        zz, vv = (b.z, b.vane) if rep == 0 else _permute_within_events(b, rep)
+        z.copy_(torch.from_numpy(zz))
+        v.copy_(torch.from_numpy(vv))
+        out = g.launch()
+        torch.cuda.synchronize(dev)
+        got = out.to_host()
+        want = oracle_find_batch(ocfg, b.offsets, zz, vv)
+        assert_same(got, want, "replay %d" % rep)
+        # eager work on the same context between replays
+        check_batch(other, "eager between replays", **kw)
+    g.close()
+
+
+def test_autotune_picks_a_shape_that_matches(gpu_available):
+    import torch
+    from paper_2511_02742_amd.hough import HoughFinder, autotune
+    b = eventgen.poisson_batch(128, seed0=7200)
+    dev = torch.device("cuda", 0)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.vane).to(dev)
+    o = torch.from_numpy(b.offsets).to(dev)
+    best, ms, tried = autotune(z, v, o, repeats=1)
+    assert tried >= 8 and ms > 0
+    f = HoughFinder(0, config=best)
+    got = f.find_host(b.z, b.vane, b.offsets)
+    assert_same(got, oracle_find_batch(_ocfg(f.config), b.offsets, b.z, b.vane), "autotuned")
