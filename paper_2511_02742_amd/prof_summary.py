@@ -29,6 +29,9 @@ from collections import defaultdict
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 KERNEL_SOURCE = os.path.join(PKG, "csrc", "hough_kernels.hip")
+# The benchmark's calibration kernel: torch.mul over M MiB of float32, which
+# reads and writes exactly M MiB each.
+COPY_KERNEL = "MulFunctor"
 
 
 def kernel_source_hash() -> str:
@@ -72,14 +75,14 @@ def counter_per_dispatch(pmc_dir: str, counter: str):
 
 def traffic(fetch_dir: str, write_dir: str, copy_mib: int, kernel: str = "k_find"):
     """HBM bytes per launch of `kernel` (median over dispatches of the largest
-    grid), scaled by the counters of the calibration copy."""
+    grid), scaled by the counters of the calibration kernel."""
     copy_bytes = float(copy_mib) * (1 << 20)
     res = {}
     for label, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         per, names = counter_per_dispatch(d, counter)
-        copies = [v for k, v in per.items() if "copy" in names[k].lower()]
+        copies = [v for k, v in per.items() if COPY_KERNEL in names[k]]
         if not copies:
-            raise ValueError("no copy kernel in %s" % d)
+            raise ValueError("no calibration kernel (%s) in %s" % (COPY_KERNEL, d))
         ref = max(copies) * 1024.0           # counter in KiB
         scale = copy_bytes / ref if ref > 0 else float("nan")
         mine = [v for k, v in per.items() if kernel in names[k]]
