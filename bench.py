@@ -41,6 +41,11 @@ def main():
     ap.add_argument("--plain-events", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-events", type=int, default=50000,
+                    help="requests per offered rate in the served-stream leg (0: skip it)")
+    ap.add_argument("--serve-rates", default="20000,50000,100000")
+    ap.add_argument("--serve-lanes", type=int, default=3)
+    ap.add_argument("--serve-pool", type=int, default=4096)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first, as the reference kernel for "
                          "FETCH_SIZE / WRITE_SIZE counter scaling")
@@ -170,6 +175,8 @@ def main():
                          % (n_done, N_EVENTS, tc)}
         log("cpu oracle: %.1f events/s over %d events" % (n_done / tc, n_done))
 
+    served = serve_bench(args, f, log) if args.serve_events > 0 else None
+
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -188,8 +195,93 @@ def main():
                                       "truncations", "hot_scans", "hotset_full", "recounts")},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "served": served,
     }
     print(json.dumps(rec), flush=True)
+
+
+def serve_bench(args, finder, log):
+    """Served stream: requests of mixed pileup (uniform over 1, 10, 25, 50,
+    100 tracks, drawn from a pool of seeded events) arrive as a Poisson
+    process at each offered rate and go through the server's continuous
+    batching. Latency is the server's completion time minus the request's
+    arrival time. A final burst (every request arriving at once) gives the
+    most the served form sustains."""
+    import torch
+    from paper_2511_02742_amd import eventgen
+    from paper_2511_02742_amd.hough import HoughServer
+
+    pool = eventgen.mixed_pileup_batch(args.serve_pool, seed0=2_000_000)
+    P = len(pool.offsets) - 1
+    lens = np.diff(pool.offsets)
+    # expected per-event results from one batched call on the pool
+    dev = torch.device("cuda", 0)
+    out = finder.find(torch.from_numpy(pool.z).to(dev), torch.from_numpy(pool.vane).to(dev),
+                      torch.from_numpy(pool.offsets).to(dev))
+    cand, _, info = out.to_host()
+    assert info["status"] == 0
+    want_nc = np.bincount(cand["event"], minlength=P)
+    want_nh = np.bincount(cand["event"], weights=cand["n_hits"], minlength=P).astype(np.int64)
+
+    rates = [float(r) for r in args.serve_rates.split(",") if r] + [float("inf")]
+    res = []
+    with HoughServer(0, lanes=args.serve_lanes, queue_events=1 << 21, queue_hits=1 << 28) as srv:
+        # warm-up
+        srv.submit(pool.z, pool.vane, pool.offsets[:65])
+        srv.drain(60.0)
+        srv.poll_records()
+        for rate in rates:
+            n = args.serve_events
+            rng = np.random.default_rng(12345 + (0 if rate == float("inf") else int(rate)))
+            idx = rng.integers(0, P, n)
+            st0 = srv.stats()
+            t_start = srv.clock() + 0.1
+            arr = t_start + (np.zeros(n) if rate == float("inf") else np.cumsum(rng.exponential(1.0 / rate, n)))
+            sub = 0
+            recs = []
+            got = 0
+            chunk = 8192 if rate == float("inf") else 4096
+            while got < n:
+                now = srv.clock()
+                while sub < n and arr[sub] - now < 0.2:
+                    hi = min(n, sub + chunk)
+                    sel = idx[sub:hi]
+                    ln = lens[sel]
+                    offs = np.zeros(len(sel) + 1, np.int64)
+                    np.cumsum(ln, out=offs[1:])
+                    gather = np.repeat(pool.offsets[sel] - offs[:-1], ln) + np.arange(offs[-1])
+                    acc = srv.submit(pool.z[gather], pool.vane[gather], offs,
+                                     tags=np.arange(sub, hi, dtype=np.uint64), t_arrival=arr[sub:hi])
+                    assert acc == hi - sub, (acc, hi - sub)
+                    sub = hi
+                r, _, _ = srv.poll_records()
+                if len(r):
+                    recs.append(r)
+                    got += len(r)
+                else:
+                    time.sleep(0.0002)
+            r = np.concatenate(recs)
+            st1 = srv.stats()
+            assert (r["status"] == 0).all()
+            ev = idx[r["tag"].astype(np.int64)]
+            mism = int(((r["n_candidates"] != want_nc[ev]) | (r["n_hit_index"] != want_nh[ev])).sum())
+            lat = r["t_done"] - r["t_arrival"]
+            span = float(r["t_done"].max() - r["t_arrival"].min())
+            launches = st1["launches"] - st0["launches"]
+            ent = {"offered_per_s": None if rate == float("inf") else rate, "requests": n,
+                   "sustained_per_s": round(n / span, 1),
+                   "latency_us_p50": round(1e6 * float(np.percentile(lat, 50)), 1),
+                   "latency_us_p99": round(1e6 * float(np.percentile(lat, 99)), 1),
+                   "queue_us_p50": round(1e6 * float(np.percentile(r["t_admit"] - r["t_arrival"], 50)), 1),
+                   "launches": launches, "events_per_launch": round(n / max(launches, 1), 2),
+                   "max_lanes_busy": st1["max_lanes_busy"], "mismatches": mism}
+            log("served %s: %s" % ("burst" if rate == float("inf") else "%.0f/s" % rate, ent))
+            res.append(ent)
+        dev_bytes = srv.stats()["device_bytes"]
+    return {"workload": "mixed pileup {1,10,25,50,100} tracks + 1% noise, pool of %d seeded events "
+                        "(seeds 2000000..), Poisson arrivals" % P,
+            "lanes": args.serve_lanes, "device_bytes": dev_bytes, "mean_hits": round(float(lens.mean()), 1),
+            "rates": res}
 
 
 if __name__ == "__main__":

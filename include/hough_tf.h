@@ -238,6 +238,106 @@ hough_status hough_autotune(const hough_config *base, int device, void *stream, 
                             const int16_t *vane, int32_t repeats, hough_config *best, double *best_ms,
                             int32_t *n_tried);
 
+/*
+ * Served form: a request loop with continuous batching.
+ *
+ * A server owns a context of its own, a dispatcher thread and `lanes`
+ * launch slots. Each lane has its own stream and resident device memory
+ * (input buffer and finder workspace for max_batch_hits hits and
+ * max_batch_events events) plus pinned host memory the device writes the
+ * results into. Requests (one event each: host arrays) wait in an admission
+ * queue in arrival order. Whenever a lane is free the dispatcher admits the
+ * queued requests that have arrived, oldest first, as long as they fit the
+ * lane's memory, copies them to the device in one transfer and enqueues the
+ * finder on the lane's stream; requests that arrive while lanes are busy are
+ * admitted by the next lane that frees, so the launches of several lanes
+ * overlap on the device. A finished launch is split into per-request results
+ * that hough_server_poll hands out. A request's result is exactly what a
+ * one-event hough_find on the same hits returns (candidates with event 0 and
+ * hit_offset from 0, hit indices local to the request).
+ *
+ * Times are seconds on the server clock (hough_server_clock: a monotonic
+ * clock, 0 at creation). All calls may come from any host thread.
+ */
+typedef struct {
+    int32_t lanes;            /* launch slots in flight at once, 1..8 (0: 3)            */
+    int32_t max_batch_events; /* requests per launch, >= 1 (0: 4096)                    */
+    int64_t max_batch_hits;   /* hits per launch: each lane's device memory; also the
+                                 largest request accepted (0: 1 << 20)                  */
+    int64_t queue_hits;       /* hits the admission queue holds (0: 1 << 26)            */
+    int32_t queue_events;     /* requests the admission queue holds (0: 1 << 20)        */
+    int32_t reserved[3];      /* must be 0                                              */
+} hough_server_config;
+
+typedef struct {              /* 72 bytes, one per finished request                    */
+    uint64_t tag;             /* the caller's tag of the request                       */
+    int32_t status;           /* HOUGH_OK; HOUGH_ERR_DATA (invalid hit) or
+                                 HOUGH_ERR_CAPACITY (too many hits) for a request
+                                 refused at submission; otherwise the error of the
+                                 launch that carried it (no candidates then)           */
+    int32_t n_hits;           /* hits of the request                                   */
+    int32_t n_candidates;
+    int32_t lane;             /* lane that ran it (-1: refused at submission)          */
+    int64_t cand_offset;      /* its first candidate in this poll's cand array         */
+    int64_t hit_offset;       /* its first hit index in this poll's hit_index array    */
+    int64_t n_hit_index;      /* hit indices it holds                                  */
+    double t_arrival;         /* arrival time given at submission                     */
+    double t_admit;           /* time its launch was enqueued                          */
+    double t_done;            /* time the dispatcher saw its launch finish             */
+} hough_served;
+
+typedef struct {
+    int64_t submitted;        /* requests accepted into the queue                      */
+    int64_t refused;          /* requests refused at submission (invalid or too big)   */
+    int64_t completed;        /* results produced (including refused ones)             */
+    int64_t launches;         /* finder launches                                       */
+    int64_t launched_events;
+    int64_t launched_hits;
+    int64_t pending_events;   /* waiting for admission now                             */
+    int64_t max_pending_events;
+    int64_t max_lanes_busy;   /* most lanes in flight at once                          */
+    int64_t device_bytes;     /* resident device memory of all lanes                   */
+    int64_t results_waiting;  /* finished results not yet polled                       */
+    int64_t reserved[5];
+} hough_server_stats;
+
+/* Creates a server for config `cfg` on `device` (scfg may be NULL for the
+ * defaults) and starts its dispatcher thread. All device and pinned memory
+ * is allocated here. */
+hough_status hough_server_create(const hough_config *cfg, int device, const hough_server_config *scfg,
+                                 void **server);
+/* Stops the dispatcher after the launches in flight finish; requests still
+ * queued and results not polled are dropped. */
+hough_status hough_server_destroy(void *server);
+double hough_server_clock(const void *server);
+/*
+ * Queues n requests: request r has hits [offsets[r], offsets[r+1]) of the
+ * host arrays z and vane (offsets[0] may be nonzero; the hits are copied
+ * before the call returns), the tag tags[r] (NULL: r) and the arrival time
+ * t_arrival[r] (NULL: now). A request is not admitted before its arrival
+ * time, so a stream can be queued ahead of time. Requests with an invalid
+ * hit or more than max_batch_hits hits become results with an error status
+ * at once. *n_accepted receives how many requests, from the first, were
+ * taken; it is less than n only when the queue is full (back-pressure: submit
+ * the rest later). Returns HOUGH_ERR_INVALID_ARG for bad pointers or offsets.
+ */
+hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
+                                 const float *z, const int16_t *vane, const double *t_arrival,
+                                 int32_t *n_accepted);
+/*
+ * Moves up to max_results finished results, oldest launch first, into
+ * `results`, their candidates into `cand` and their hit indices into
+ * `hit_index` (host arrays of the given capacities), stopping before the
+ * first result that does not fit. *n_results receives the number moved.
+ */
+hough_status hough_server_poll(void *server, int32_t max_results, hough_served *results, hough_candidate *cand,
+                               int64_t cand_capacity, int32_t *hit_index, int64_t hit_capacity,
+                               int32_t *n_results);
+/* Waits until no request is queued or in flight (HOUGH_ERR_CAPACITY after
+ * timeout_s seconds). */
+hough_status hough_server_drain(void *server, double timeout_s);
+hough_status hough_server_get_stats(const void *server, hough_server_stats *stats);
+
 const char *hough_status_string(hough_status st);
 /* Detail of the last failing call on ctx (empty string if none). */
 const char *hough_last_error(const void *ctx);

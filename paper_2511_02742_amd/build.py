@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhough_tf.so")
-SOURCES = [os.path.join(CSRC, "hough_kernels.hip"), os.path.join(CSRC, "hough_host.hip")]
+SOURCES = [os.path.join(CSRC, "hough_kernels.hip"), os.path.join(CSRC, "hough_host.hip"),
+           os.path.join(CSRC, "hough_serve.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -13,67 +13,17 @@
 #include <vector>
 
 #include "hough_internal.h"
+#include "hough_runtime.h"
 #include "hough_tf.h"
 
-namespace {
+namespace hough {
+namespace rt {
 
+namespace {
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
-constexpr int kAssocMinBytes = 2048 * 20 + 64;  // one peak at the largest event (2048 chunks)
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
-constexpr uint32_t kCtxMagic = 0x48544631u;
-constexpr uint32_t kGraphMagic = 0x48544647u;
-
-// Device scratch of the finder, sized for a number of hits and events.
-struct Workspace {
-    void *base = nullptr;
-    size_t bytes = 0;
-    int64_t hits = -1, events = -1;
-    int32_t *state = nullptr, *aidx = nullptr, *hits_ws = nullptr, *ev_ncand = nullptr, *ev_nhits = nullptr;
-    float *aphi = nullptr, *az = nullptr;
-    hough_candidate *cand_ws = nullptr;
-    long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
-    unsigned long long *stats = nullptr;
-    int64_t *tmp_offsets = nullptr;
-    unsigned long long *g_hs = nullptr;
-    int32_t *g_cnt = nullptr, *g_flag = nullptr;
-};
-
-struct Ctx {
-    uint32_t magic = kCtxMagic;
-    hough_config cfg{};
-    int device = 0;
-    // tables, host copies and device copies
-    std::vector<float> cos_t, sin_t, phi_v, theta_c, rho_c;
-    float inv_w = 0.f;
-    float *d_tables = nullptr;
-    float2 *d_cs = nullptr;
-    float *d_phi = nullptr, *d_thc = nullptr, *d_rhoc = nullptr;
-    // launch shape
-    int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
-    int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
-    int stream_ok = 0, hs_off = 0, sorted_off = 0;
-    double safe_r2 = -1.0;
-    int dump_rows = 0, dump_lds = 0;
-    Workspace ws;
-    int graphs = 0;  // live captured graphs (they reference the tables)
-    // timing
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
-    std::string last_error;
-};
-
-// A captured launch of the finder for fixed arguments, with its own workspace.
-struct Graph {
-    uint32_t magic = kGraphMagic;
-    Ctx *ctx = nullptr;
-    Workspace ws;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
+}  // namespace
 thread_local std::string g_last_global_error;
 
 Ctx *as_ctx(void *p) {
@@ -171,7 +121,12 @@ hough_status choose_shape(Ctx &c, std::string &why) {
     rows = std::min(rows, g.n_theta);
     if (rows + 2 * halo > total_fit) { why = "tile_rows does not fit in LDS"; return HOUGH_ERR_INVALID_ARG; }
     c.tile_rows = rows;
-    c.tile_bytes = std::max(row_bytes * (rows + 2 * halo), kAssocMinBytes);
+    // the association scratch reuses the tile: one peak per pass must fit
+    // at every event size up to the largest
+    int assoc_min = 0;
+    for (int w = 1; w <= HOUGH_MAX_EVENT_HITS / 64; ++w)
+        assoc_min = std::max(assoc_min, hough::assoc_fixed_bytes(w, kPeakKeep + kHotCap) + hough::assoc_peak_bytes(w));
+    c.tile_bytes = std::max(row_bytes * (rows + 2 * halo), assoc_min);
     c.tile_bytes = (c.tile_bytes + 15) & ~15;
     c.lds_bytes = c.tile_bytes + hough::find_lds_extra(c.wg_threads, kHotCap, kPeakKeep);
     if (c.lds_bytes + kStaticLds > lds_max) { why = "LDS budget exceeded"; return HOUGH_ERR_INVALID_ARG; }
@@ -189,7 +144,10 @@ hough_status choose_shape(Ctx &c, std::string &why) {
         while (2 * slots * 8 <= rb) slots *= 2;
         int cap = std::min(4096, slots / 2);
         cap = std::min(cap, (c.tile_bytes - rb - sorted_bytes) / 8);
-        c.stream_ok = cap >= 256 ? 1 : 0;
+        // the row-stream path (at most 512 alive hits, 8 words) runs the
+        // association inside the row buffers
+        const int assoc_stream = hough::assoc_fixed_bytes(8, kPeakKeep + kHotCap) + 2 * hough::assoc_peak_bytes(8);
+        c.stream_ok = cap >= 256 && rb >= assoc_stream ? 1 : 0;
         c.hs_cap = std::max(cap, 0);
         c.hs_off = rb;
         c.sorted_off = rb + 8 * c.hs_cap;
@@ -465,7 +423,10 @@ void free_context(Ctx *c) {
     delete c;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace hough
+
+using namespace hough::rt;
 
 extern "C" {
 

@@ -8,6 +8,16 @@
 
 namespace hough {
 
+// LDS scratch of one association pass over W 64-hit words and npk peaks:
+// a fixed part (per-peak (cos, sin), the claimed mask, and for W up to
+// kAssocRoundMaxW the per-hit table of the parallel claim rounds) plus a
+// per-peak part (match masks, word prefixes, three ints).
+constexpr int kAssocRoundMaxW = 64;
+__host__ __device__ inline int assoc_fixed_bytes(int W, int npk) {
+    return ((8 * npk + 15) & ~15) + 8 * W + (W <= kAssocRoundMaxW ? 4 * 64 * W : 0);
+}
+__host__ __device__ inline int assoc_peak_bytes(int W) { return 12 * W + 12; }
+
 // Everything the finder kernel needs, passed by value.
 struct FindArgs {
     // configuration

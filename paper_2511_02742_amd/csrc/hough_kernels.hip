@@ -128,6 +128,7 @@ struct Shared {
     int wtot[16];
     int n_trunc;     // peak-list truncations (diagnostics)
     int n_hotscan;   // hot-list overflow scans (diagnostics)
+    int rcnt[2];     // open peaks of the current and the next claim round
 };
 
 // LDS layout of k_find (dynamic part):
@@ -474,12 +475,18 @@ __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &s
     __syncthreads();
     const int npk = sh.pcnt;
     if (npk > A.pkeep + A.hcap) return -1;  // more peaks than the list holds
-    // rank sort (keys are distinct): descending order into L.sorted
-    for (int p = threadIdx.x; p < npk; p += NT) {
+    // rank sort (keys are distinct): descending order into L.sorted.  G
+    // adjacent lanes share a key and split its comparisons.
+    int G = 1;
+    while (G < kWave && 2 * G * npk <= NT) G *= 2;
+    const int g = threadIdx.x & (G - 1);
+    for (int p = threadIdx.x / G; p < npk; p += NT / G) {
         const unsigned long long key = L.pbuf[p];
         int r = 0;
-        for (int q = 0; q < npk; ++q) r += L.pbuf[q] > key ? 1 : 0;
-        L.sorted[r] = key;
+#pragma unroll 4
+        for (int q = g; q < npk; q += G) r += L.pbuf[q] > key ? 1 : 0;
+        for (int m = 1; m < G; m <<= 1) r += __shfl_xor(r, m);
+        if (g == 0) L.sorted[r] = key;
     }
     __syncthreads();
     return npk;
@@ -497,22 +504,34 @@ __device__ void recount(const FindArgs &A, const float2 *__restrict__ cs, const 
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
-    for (int e = wave; e < n_hs; e += NW) {
-        const unsigned long long key = L.hs[e];
-        if (key == 0ull) continue;
+    for (int e0 = wave * kWave; e0 < n_hs; e0 += NW * kWave) {
+        // 64 bins at once: lane l loads bin e0 + l and its (cos, sin), then
+        // the wave counts the bins one after another
+        const int e = e0 + lane;
+        const unsigned long long key = e < n_hs ? L.hs[e] : 0ull;
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
-        const int j = (int)(flat / (uint32_t)A.n_rho);
+        const int j = key != 0ull ? (int)(flat / (uint32_t)A.n_rho) : 0;
         const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
         const float2 t = cs[j];
-        int cnt = 0;
+        const unsigned long long live = __ballot(key != 0ull);
+        unsigned long long out = 0ull;
+        const int nb = min(kWave, n_hs - e0);
+        for (int i = 0; i < nb; ++i) {
+            if (!((live >> i) & 1ull)) continue;
+            const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.x), i));
+            const float sn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.y), i));
+            const int ki = __builtin_amdgcn_readlane(k, i);
+            int cnt = 0;
 #pragma unroll
-        for (int c = 0; c < kChunks; ++c) {
-            if (c < h.nch) {
-                const int kk = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                cnt += __popcll(__ballot(c * kWave + lane < n_alive && kk == k));
+            for (int ch = 0; ch < kChunks; ++ch) {
+                if (ch < h.nch) {
+                    const int kk = rho_bin(h.phi[ch], h.z[ch], c, sn, A.rho_min, A.inv_w);
+                    cnt += __popcll(__ballot(ch * kWave + lane < n_alive && kk == ki));
+                }
             }
+            if (lane == i) out = (uint32_t)cnt >= A.min_votes ? bin_key((uint32_t)cnt, flat) : 0ull;
         }
-        if (lane == 0) L.hs[e] = (uint32_t)cnt >= A.min_votes ? bin_key((uint32_t)cnt, flat) : 0ull;
+        if (key != 0ull) L.hs[e] = out;
     }
 }
 
@@ -597,6 +616,110 @@ __device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t 
 //      count (raw >= its bin count >= T); one whose matches are all claimed is
 //      rejected; only a partial overlap needs a DPP prefix sum.
 //   C: all waves write the hit lists of the emitted peaks.
+// Claims of one association pass, resolved in parallel rounds.  Peak p is
+// taken in key order when at least T of its matches are still unclaimed by
+// the peaks taken before it.  A round first rejects every open peak whose
+// unclaimed matches number fewer than T (claims only grow, so this is
+// final), then takes every remaining open peak none of whose unclaimed
+// matches is also wanted by an earlier open peak (per-hit minimum of the
+// wanting peak indices).  A taken peak's unclaimed set cannot change later:
+// an earlier peak taken afterwards must avoid it, and later peaks do not
+// count.  The lowest open peak is always taken or rejected, so each round
+// makes progress; pileup events settle in a handful of rounds.
+//   pst[p]: 0 open, -1 rejected, > 0 taken with that many hits (bit 24 set
+//   in the round it was taken).  M[p] becomes the taken peak's claimed set.
+template <int NT>
+__device__ void claim_rounds(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
+                             int *owner, int W, int nb, Shared &sh) {
+    constexpr int kFresh = 1 << 24;
+    const int T = (int)A.min_votes;
+    for (int p = threadIdx.x; p < nb; p += NT) pst[p] = 0;
+    for (int q = threadIdx.x; q < W * kWave; q += NT) owner[q] = 0x7fffffff;
+    if (threadIdx.x == 0) {
+        sh.rcnt[0] = 0;
+        sh.rcnt[1] = 0;
+    }
+    __syncthreads();
+    for (int round = 0;; ++round) {
+        int *open = &sh.rcnt[round & 1];
+        for (int p = threadIdx.x; p < nb; p += NT) {
+            if (pst[p] != 0) continue;
+            const unsigned long long *mp = M + (size_t)p * W;
+            int c = 0;
+            for (int w = 0; w < W; ++w) c += __popcll(mp[w] & ~icl[w]);
+            if (c < T) {
+                pst[p] = -1;
+                continue;
+            }
+            atomicAdd(open, 1);
+            for (int w = 0; w < W; ++w) {
+                unsigned long long m = mp[w] & ~icl[w];
+                while (m) {
+                    atomicMin(&owner[w * kWave + (__ffsll((long long)m) - 1)], p);
+                    m &= m - 1;
+                }
+            }
+        }
+        __syncthreads();
+        if (*open == 0) break;
+        for (int p = threadIdx.x; p < nb; p += NT) {
+            if (pst[p] != 0) continue;
+            unsigned long long *mp = M + (size_t)p * W;
+            bool first = true;
+            int c = 0;
+            for (int w = 0; w < W && first; ++w) {
+                unsigned long long m = mp[w] & ~icl[w];
+                c += __popcll(m);
+                while (m) {
+                    first &= owner[w * kWave + (__ffsll((long long)m) - 1)] == p;
+                    m &= m - 1;
+                }
+            }
+            if (first) {
+                for (int w = 0; w < W; ++w) mp[w] &= ~icl[w];
+                pst[p] = c | kFresh;
+            }
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < nb; p += NT) {
+            if (pst[p] > 0 && (pst[p] & kFresh)) {
+                const unsigned long long *mp = M + (size_t)p * W;
+                for (int w = 0; w < W; ++w)
+                    if (mp[w]) atomicOr(&icl[w], mp[w]);
+                pst[p] &= ~kFresh;
+            }
+        }
+        for (int q = threadIdx.x; q < W * kWave; q += NT) owner[q] = 0x7fffffff;
+        if (threadIdx.x == 0) sh.rcnt[(round + 1) & 1] = 0;
+        __syncthreads();
+    }
+}
+
+// The same claims, one peak after another by one wave (events too large for
+// the per-hit table of claim_rounds).  Lane l holds words l, l + 64, ...
+template <int NT>
+__device__ void claim_serial(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst, int W,
+                             int nb) {
+    if (wave_id() != 0) return;
+    const int lane = lane_id();
+    for (int p = 0; p < nb; ++p) {
+        unsigned long long *mp = M + (size_t)p * W;
+        int cnt = 0;
+        for (int w = lane; w < W; w += kWave) cnt += __popcll(mp[w] & ~icl[w]);
+        const int total = __builtin_amdgcn_readlane(wave_incl_scan(cnt), kWave - 1);
+        if (total < (int)A.min_votes) {
+            if (lane == 0) pst[p] = -1;
+            continue;
+        }
+        for (int w = lane; w < W; w += kWave) {
+            const unsigned long long m = mp[w] & ~icl[w];
+            mp[w] = m;
+            icl[w] |= m;
+        }
+        if (lane == 0) pst[p] = total;
+    }
+}
+
 template <int NT>
 __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
@@ -607,23 +730,31 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
     const int n_alive = sh.nalive;
     const int W = (n_alive + kWave - 1) / kWave;
     const int64_t cbase = b / (int64_t)A.min_votes;
+    const bool rounds = W <= kAssocRoundMaxW;
 
-    // union area: icl[W] u64 | M[pb*W] u64 | rp[pb*W] u32 | base[pb] | raw[pb] | elist[pb]
+    // union area: pcs[npk] float2 | icl[W] u64 | owner[64 W] (rounds only)
+    //             | M[pb*W] u64 | rp[pb*W] u32 | pbase[pb] | pst[pb] | elist[pb]
     unsigned char *uni = reinterpret_cast<unsigned char *>(L.tile);
-    unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni);
-    unsigned long long *M = icl + W;
-    int pb = (uni_bytes - 8 * W) / (12 * W + 12);
+    float2 *pcs = reinterpret_cast<float2 *>(uni);
+    const int pcs_bytes = (8 * npk + 15) & ~15;
+    unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni + pcs_bytes);
+    int *owner = reinterpret_cast<int *>(icl + W);
+    unsigned long long *M = reinterpret_cast<unsigned long long *>(owner + (rounds ? W * kWave : 0));
+    // at least one peak per pass: the host sizes uni_bytes for the largest W
+    int pb = (uni_bytes - assoc_fixed_bytes(W, npk)) / assoc_peak_bytes(W);
     pb = min(pb, A.pkeep + A.hcap);
     uint32_t *rp = reinterpret_cast<uint32_t *>(M + (size_t)pb * W);
     int *pbase = reinterpret_cast<int *>(rp + (size_t)pb * W);
-    int *praw = pbase + pb;
-    int *elist = praw + pb;
+    int *pst = pbase + pb;
+    int *elist = pst + pb;
 
-    // peak coordinates, and the hits claimed by an earlier pass of this
-    // iteration
+    // peak coordinates and their (cos, sin), and the hits claimed by an
+    // earlier pass of this iteration
     for (int p = threadIdx.x; p < npk; p += NT) {
         const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p] & 0xffffffffull);
-        L.dec[p] = make_int2((int)(flat / (uint32_t)A.n_rho), (int)(flat % (uint32_t)A.n_rho));
+        const int j = (int)(flat / (uint32_t)A.n_rho);
+        L.dec[p] = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
+        pcs[p] = cs[j];
     }
     for (int ch = wave; ch < W; ch += NW) {
         const int q = ch * kWave + lane;
@@ -635,134 +766,81 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
 
     for (int p0 = 0; p0 < npk; p0 += pb) {
         const int nb = min(pb, npk - p0);
-        // A: match masks, chunk prefixes and raw counts
+        // A: match masks
         for (int bt = 0; bt < nbatch; ++bt) {
             if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
             const int qbase = bt * kChunks * kWave + lane;
             for (int p = wave; p < nb; p += NW) {
-                const int2 jk = L.dec[p0 + p];
-                const float2 t = cs[jk.x];
-                int run = bt == 0 ? 0 : praw[p];
+                const int kp = L.dec[p0 + p].y;
+                const float2 t = pcs[p0 + p];
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
                     if (c < h.nch) {
                         const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                        const int d = k - jk.y;
+                        const int d = k - kp;
                         const bool hit = (qbase + c * kWave) < n_alive && (d < 0 ? -d : d) <= A.assoc_window;
                         const unsigned long long m = __ballot(hit);
-                        if (lane == 0) {
-                            M[(size_t)p * W + bt * kChunks + c] = m;
-                            rp[(size_t)p * W + bt * kChunks + c] = (uint32_t)run;
-                        }
-                        run += __popcll(m);
+                        if (lane == 0) M[(size_t)p * W + bt * kChunks + c] = m;
                     }
                 }
-                if (lane == 0) praw[p] = run;
             }
             if (nbatch > 1) __syncthreads();
         }
         __syncthreads();
-        // B: one wave resolves the claims in key order
+        // B: which peaks claim which hits
+        if (rounds)
+            claim_rounds<NT>(A, icl, M, pst, owner, W, nb, sh);
+        else
+            claim_serial<NT>(A, icl, M, pst, W, nb);
+        __syncthreads();
+        // emission order = key order of the taken peaks
         if (wave == 0) {
-            int ncand = sh.ncand;
-            int nhit = sh.nhit;
             int nemit = 0;
-            if (W <= kWave) {
-                unsigned long long mine = lane < W ? icl[lane] : ~0ull;
-                unsigned long long mnext = lane < W ? M[lane] : 0ull;
-                for (int p = 0; p < nb; ++p) {
-                    const unsigned long long mp = mnext;
-                    if (p + 1 < nb) mnext = lane < W ? M[(size_t)(p + 1) * W + lane] : 0ull;
-                    const unsigned long long m = mp & ~mine;
-                    if (__ballot(m != 0ull) == 0ull) continue;          // every match already claimed
-                    int total;
-                    if (__ballot(m != mp) == 0ull) {
-                        total = praw[p];                                 // no match claimed yet
-                    } else {
-                        const int cnt = __popcll(m);
-                        const int incl = wave_incl_scan(cnt);
-                        total = __builtin_amdgcn_readlane(incl, kWave - 1);
-                        if (total < (int)A.min_votes) continue;
-                        if (lane < W) {
-                            M[(size_t)p * W + lane] = m;
-                            rp[(size_t)p * W + lane] = (uint32_t)(incl - cnt);
-                        }
-                    }
-                    mine |= m;
-                    if (lane == 0) {
-                        const int2 jk = L.dec[p0 + p];
-                        hough_candidate cd;
-                        cd.event = e;
-                        cd.iter = iter;
-                        cd.theta_bin = jk.x;
-                        cd.rho_bin = jk.y;
-                        cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
-                        cd.n_hits = (uint32_t)total;
-                        cd.hit_offset = nhit;
-                        cd.theta = A.theta_c[jk.x];
-                        cd.rho = A.rho_c[jk.y];
-                        A.cand_ws[cbase + ncand] = cd;
-                        elist[nemit] = p;
-                        pbase[p] = nhit;
-                    }
-                    ++nemit;
-                    ++ncand;
-                    nhit += total;
+            int nhit = sh.nhit;
+            for (int c0 = 0; c0 < nb; c0 += kWave) {
+                const int p = c0 + lane;
+                const int tot = p < nb && pst[p] > 0 ? pst[p] : 0;
+                const unsigned long long took = __ballot(tot > 0);
+                const int incl = wave_incl_scan(tot);
+                if (tot > 0) {
+                    elist[nemit + mbcnt64(took)] = p;
+                    pbase[p] = nhit + incl - tot;
                 }
-                if (lane < W) icl[lane] = mine;
-            } else {
-                for (int p = 0; p < nb; ++p) {
-                    int total = 0;
-                    for (int cb = 0; cb < W; cb += kWave) {
-                        const int ch = cb + lane;
-                        const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
-                        total += __builtin_amdgcn_readlane(wave_incl_scan(__popcll(m)), kWave - 1);
-                    }
-                    if (total < (int)A.min_votes) continue;
-                    int run = 0;
-                    for (int cb = 0; cb < W; cb += kWave) {
-                        const int ch = cb + lane;
-                        const unsigned long long m = ch < W ? (M[(size_t)p * W + ch] & ~icl[ch]) : 0ull;
-                        const int cnt = __popcll(m);
-                        const int incl = wave_incl_scan(cnt);
-                        if (ch < W) {
-                            rp[(size_t)p * W + ch] = (uint32_t)(run + incl - cnt);
-                            icl[ch] |= m;
-                            M[(size_t)p * W + ch] = m;
-                        }
-                        run += __builtin_amdgcn_readlane(incl, kWave - 1);
-                    }
-                    if (lane == 0) {
-                        const int2 jk = L.dec[p0 + p];
-                        hough_candidate cd;
-                        cd.event = e;
-                        cd.iter = iter;
-                        cd.theta_bin = jk.x;
-                        cd.rho_bin = jk.y;
-                        cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
-                        cd.n_hits = (uint32_t)total;
-                        cd.hit_offset = nhit;
-                        cd.theta = A.theta_c[jk.x];
-                        cd.rho = A.rho_c[jk.y];
-                        A.cand_ws[cbase + ncand] = cd;
-                        elist[nemit] = p;
-                        pbase[p] = nhit;
-                    }
-                    ++nemit;
-                    ++ncand;
-                    nhit += total;
-                }
+                nemit += __popcll(took);
+                nhit += __builtin_amdgcn_readlane(incl, kWave - 1);
             }
             if (lane == 0) {
                 sh.nemit = nemit;
-                sh.ncand = ncand;
+                sh.ncand += nemit;
                 sh.nhit = nhit;
             }
         }
         __syncthreads();
-        // C: hit lists (ascending alive-list position = ascending hit index)
         const int nemit = sh.nemit;
         const int cid0 = sh.ncand - nemit;
+        // candidate records and word prefixes of the claimed sets
+        for (int ei = threadIdx.x; ei < nemit; ei += NT) {
+            const int p = elist[ei];
+            const int2 jk = L.dec[p0 + p];
+            hough_candidate cd;
+            cd.event = e;
+            cd.iter = iter;
+            cd.theta_bin = jk.x;
+            cd.rho_bin = jk.y;
+            cd.peak_votes = (uint32_t)(keys[p0 + p] >> 32);
+            cd.n_hits = (uint32_t)pst[p];
+            cd.hit_offset = pbase[p];
+            cd.theta = A.theta_c[jk.x];
+            cd.rho = A.rho_c[jk.y];
+            A.cand_ws[cbase + cid0 + ei] = cd;
+            uint32_t run = 0;
+            for (int w = 0; w < W; ++w) {
+                rp[(size_t)p * W + w] = run;
+                run += (uint32_t)__popcll(M[(size_t)p * W + w]);
+            }
+        }
+        __syncthreads();
+        // C: hit lists (ascending alive-list position = ascending hit index)
         for (int t = wave; t < nemit * W; t += NW) {
             const int ei = t / W;
             const int ch = t - ei * W;

@@ -1,0 +1,89 @@
+// Host runtime internals shared by the C-ABI layer and the served form:
+// the context (tables, launch shape), the finder workspace and the enqueue
+// of one finder call on a stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hough_internal.h"
+#include "hough_tf.h"
+
+namespace hough {
+namespace rt {
+
+constexpr uint32_t kCtxMagic = 0x48544631u;
+constexpr uint32_t kGraphMagic = 0x48544647u;
+
+// Device scratch of the finder, sized for a number of hits and events.
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+    int64_t hits = -1, events = -1;
+    int32_t *state = nullptr, *aidx = nullptr, *hits_ws = nullptr, *ev_ncand = nullptr, *ev_nhits = nullptr;
+    float *aphi = nullptr, *az = nullptr;
+    hough_candidate *cand_ws = nullptr;
+    long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
+    unsigned long long *stats = nullptr;
+    int64_t *tmp_offsets = nullptr;
+    unsigned long long *g_hs = nullptr;
+    int32_t *g_cnt = nullptr, *g_flag = nullptr;
+};
+
+struct Ctx {
+    uint32_t magic = kCtxMagic;
+    hough_config cfg{};
+    int device = 0;
+    // tables, host copies and device copies
+    std::vector<float> cos_t, sin_t, phi_v, theta_c, rho_c;
+    float inv_w = 0.f;
+    float *d_tables = nullptr;
+    float2 *d_cs = nullptr;
+    float *d_phi = nullptr, *d_thc = nullptr, *d_rhoc = nullptr;
+    // launch shape
+    int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
+    int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
+    int stream_ok = 0, hs_off = 0, sorted_off = 0;
+    double safe_r2 = -1.0;
+    int dump_rows = 0, dump_lds = 0;
+    Workspace ws;
+    int graphs = 0;  // live captured graphs (they reference the tables)
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    std::string last_error;
+};
+
+// A captured launch of the finder for fixed arguments, with its own workspace.
+struct Graph {
+    uint32_t magic = kGraphMagic;
+    Ctx *ctx = nullptr;
+    Workspace ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+Ctx *as_ctx(void *p);
+const Ctx *as_ctx(const void *p);
+// Records msg as the context's (and the thread's) last error; returns st.
+hough_status fail(Ctx *c, hough_status st, const std::string &msg);
+hough_status make_context(const hough_config *cfg, int device, Ctx **out);
+void free_context(Ctx *c);
+// Grows w to hold n_hits hits and n_events events (synchronises s first when
+// an old block has to go).
+hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_t n_events, hipStream_t s);
+void free_workspace(Workspace &w);
+// Enqueues one finder call on s (split sweep, finder, compaction); outputs
+// as in hough_find.
+hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
+                          const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
+                          hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed);
+
+}  // namespace rt
+}  // namespace hough

@@ -1,0 +1,510 @@
+// Served form: an admission queue, a dispatcher thread and a few launch
+// lanes with resident device memory (continuous batching of streamed events).
+//
+// Each lane is one launch in flight: its own stream, a device input buffer
+// and a finder workspace sized for max_batch_hits / max_batch_events, and
+// pinned host memory the finder's compaction writes the results into (no
+// copy back). The dispatcher loops: it harvests every lane whose completion
+// event has fired, then fills every free lane with the queued requests that
+// have arrived (oldest first, while they fit the lane), one host-to-device
+// copy and one finder enqueue per lane. Requests that arrive while the lanes
+// are busy join the next free lane, so launches of several lanes overlap on
+// the device and a lane never waits for a fixed batch size.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hough_runtime.h"
+#include "hough_tf.h"
+
+namespace {
+
+using hough::rt::Ctx;
+using hough::rt::Workspace;
+using Clock = std::chrono::steady_clock;
+
+constexpr uint32_t kServerMagic = 0x48545353u;
+constexpr int kMaxLanes = 8;
+
+struct Request {
+    uint64_t tag = 0;
+    double t_arrival = 0.0;
+    int32_t n = 0;
+    std::vector<float> z;
+    std::vector<int16_t> vane;
+};
+
+struct Result {
+    hough_served rec{};
+    std::vector<hough_candidate> cand;
+    std::vector<int32_t> hits;
+};
+
+struct Lane {
+    int id = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Workspace ws;
+    char *d_in = nullptr;      // device: offsets | z | vane of one launch
+    char *h_in = nullptr;      // pinned staging of the same bytes
+    size_t in_bytes = 0;
+    char *h_out = nullptr;     // pinned, written by the device: counts | cand | hit_index
+    int64_t *counts = nullptr;
+    hough_candidate *cand = nullptr;
+    int32_t *hits = nullptr;
+    std::vector<Request> reqs;
+    double t_admit = 0.0;
+    bool busy = false;
+};
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct Server {
+    uint32_t magic = kServerMagic;
+    Ctx *ctx = nullptr;
+    hough_server_config sc{};
+    Clock::time_point t0;
+    std::vector<Lane> lanes;
+
+    std::mutex mq;             // queue, its counters, stats
+    std::condition_variable cv;
+    std::deque<Request> queue;
+    int64_t q_hits = 0;
+    hough_server_stats st{};
+    int lanes_busy = 0;
+
+    std::mutex mr;             // results
+    std::deque<Result> results;
+
+    std::atomic<bool> stop{false};
+    std::thread thread;
+    std::string thread_error;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    size_t input_bytes(int64_t events, int64_t hits) const {
+        return align16(align16(8 * (size_t)(events + 1)) + 4 * (size_t)hits) + 2 * (size_t)hits;
+    }
+
+    // Packs the requests into the lane's staging buffer, copies them to the
+    // device and enqueues the finder and the completion event.
+    hough_status launch(Lane &L, double t) {
+        const int64_t ne = (int64_t)L.reqs.size();
+        int64_t nh = 0;
+        for (const Request &r : L.reqs) nh += r.n;
+        const size_t zo = align16(8 * (size_t)(ne + 1));
+        const size_t vo = align16(zo + 4 * (size_t)nh);
+        int64_t *offs = reinterpret_cast<int64_t *>(L.h_in);
+        float *zz = reinterpret_cast<float *>(L.h_in + zo);
+        int16_t *vv = reinterpret_cast<int16_t *>(L.h_in + vo);
+        int64_t o = 0;
+        for (int64_t e = 0; e < ne; ++e) {
+            const Request &r = L.reqs[e];
+            offs[e] = o;
+            if (r.n > 0) {
+                std::memcpy(zz + o, r.z.data(), 4 * (size_t)r.n);
+                std::memcpy(vv + o, r.vane.data(), 2 * (size_t)r.n);
+            }
+            o += r.n;
+        }
+        offs[ne] = o;
+        const size_t bytes = vo + 2 * (size_t)nh;
+        if (hipMemcpyAsync(L.d_in, L.h_in, bytes, hipMemcpyHostToDevice, L.stream) != hipSuccess)
+            return HOUGH_ERR_DEVICE;
+        hough_status s = hough::rt::enqueue_find(*ctx, L.ws, L.stream, (int32_t)ne, nh,
+                                                 reinterpret_cast<const int64_t *>(L.d_in),
+                                                 reinterpret_cast<const float *>(L.d_in + zo),
+                                                 reinterpret_cast<const int16_t *>(L.d_in + vo), ctx->cfg.max_iters,
+                                                 L.cand, L.hits, L.counts, false);
+        if (s) return s;
+        if (hipEventRecord(L.done, L.stream) != hipSuccess) return HOUGH_ERR_DEVICE;
+        L.t_admit = t;
+        L.busy = true;
+        return HOUGH_OK;
+    }
+
+    // Takes the arrived requests that fit a lane, oldest first.
+    bool admit(Lane &L) {
+        double t;
+        {
+            std::lock_guard<std::mutex> g(mq);
+            t = now();
+            int64_t hits = 0;
+            while (!queue.empty() && (int64_t)L.reqs.size() < sc.max_batch_events) {
+                Request &r = queue.front();
+                if (r.t_arrival > t || hits + r.n > sc.max_batch_hits) break;
+                hits += r.n;
+                L.reqs.push_back(std::move(r));
+                queue.pop_front();
+            }
+            if (L.reqs.empty()) return false;
+            q_hits -= hits;
+            st.pending_events -= (int64_t)L.reqs.size();
+            st.launches += 1;
+            st.launched_events += (int64_t)L.reqs.size();
+            st.launched_hits += hits;
+            ++lanes_busy;
+            st.max_lanes_busy = std::max<int64_t>(st.max_lanes_busy, lanes_busy);
+        }
+        L.t_admit = t;
+        const hough_status s = launch(L, t);
+        if (s) finish(L, s, t);
+        return true;
+    }
+
+    // Splits a finished launch into per-request results (status s != OK:
+    // every request of the launch carries that error).
+    void finish(Lane &L, hough_status s, double t_done) {
+        if (s == HOUGH_OK && L.counts[HOUGH_COUNT_STATUS] != 0) s = (hough_status)L.counts[HOUGH_COUNT_STATUS];
+        std::vector<Result> out(L.reqs.size());
+        const int64_t ncand = s == HOUGH_OK ? L.counts[HOUGH_COUNT_CANDIDATES] : 0;
+        int64_t ci = 0;
+        for (size_t e = 0; e < L.reqs.size(); ++e) {
+            Result &R = out[e];
+            const Request &q = L.reqs[e];
+            R.rec.tag = q.tag;
+            R.rec.status = s;
+            R.rec.n_hits = q.n;
+            R.rec.lane = L.id;
+            R.rec.t_arrival = q.t_arrival;
+            R.rec.t_admit = L.t_admit;
+            R.rec.t_done = t_done;
+            if (s != HOUGH_OK) continue;
+            const int64_t c0 = ci;
+            while (ci < ncand && L.cand[ci].event == (int32_t)e) ++ci;
+            if (ci == c0) continue;
+            const int64_t h0 = L.cand[c0].hit_offset;
+            int64_t nh = 0;
+            R.cand.assign(L.cand + c0, L.cand + ci);
+            for (hough_candidate &cd : R.cand) {
+                cd.event = 0;
+                cd.hit_offset -= h0;
+                nh += cd.n_hits;
+            }
+            R.hits.assign(L.hits + h0, L.hits + h0 + nh);
+            R.rec.n_candidates = (int32_t)R.cand.size();
+            R.rec.n_hit_index = nh;
+        }
+        {
+            std::lock_guard<std::mutex> g(mr);
+            for (Result &R : out) results.push_back(std::move(R));
+        }
+        {
+            std::lock_guard<std::mutex> g(mq);
+            st.completed += (int64_t)L.reqs.size();
+            --lanes_busy;
+        }
+        cv.notify_all();
+        L.reqs.clear();
+        L.busy = false;
+    }
+
+    void run() {
+        (void)hipSetDevice(ctx->device);
+        for (;;) {
+            bool progress = false;
+            int busy = 0;
+            for (Lane &L : lanes) {
+                if (!L.busy) continue;
+                const hipError_t q = hipEventQuery(L.done);
+                if (q == hipSuccess) {
+                    finish(L, HOUGH_OK, now());
+                    progress = true;
+                } else if (q != hipErrorNotReady) {
+                    finish(L, HOUGH_ERR_DEVICE, now());
+                    progress = true;
+                } else {
+                    ++busy;
+                }
+            }
+            for (Lane &L : lanes) {
+                if (L.busy) continue;
+                if (!admit(L)) break;
+                progress = true;
+                ++busy;
+            }
+            if (progress) continue;
+            if (busy > 0) {
+                // launches in flight: poll their events again shortly
+                std::this_thread::yield();
+                continue;
+            }
+            std::unique_lock<std::mutex> g(mq);
+            if (stop.load()) break;
+            if (queue.empty()) {
+                cv.wait_for(g, std::chrono::milliseconds(5));
+            } else {
+                const double wait = queue.front().t_arrival - now();
+                if (wait > 0) cv.wait_for(g, std::chrono::duration<double>(std::min(wait, 0.005)));
+            }
+        }
+    }
+};
+
+Server *as_server(void *p) {
+    Server *s = static_cast<Server *>(p);
+    return (s && s->magic == kServerMagic) ? s : nullptr;
+}
+const Server *as_server(const void *p) {
+    const Server *s = static_cast<const Server *>(p);
+    return (s && s->magic == kServerMagic) ? s : nullptr;
+}
+
+void free_lane(Lane &L) {
+    if (L.stream) (void)hipStreamSynchronize(L.stream);
+    hough::rt::free_workspace(L.ws);
+    if (L.d_in) (void)hipFree(L.d_in);
+    if (L.h_in) (void)hipHostFree(L.h_in);
+    if (L.h_out) (void)hipHostFree(L.h_out);
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+    L = Lane();
+}
+
+void free_server(Server *s) {
+    if (s->thread.joinable()) {
+        s->stop.store(true);
+        s->cv.notify_all();
+        s->thread.join();
+    }
+    if (s->ctx) (void)hipSetDevice(s->ctx->device);
+    for (Lane &L : s->lanes) free_lane(L);
+    if (s->ctx) hough::rt::free_context(s->ctx);
+    s->magic = 0;
+    delete s;
+}
+
+hough_status make_lane(Server &s, Lane &L, int id) {
+    const hough_server_config &c = s.sc;
+    L.id = id;
+    if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) return HOUGH_ERR_DEVICE;
+    hough_status st = hough::rt::ensure_workspace(*s.ctx, L.ws, c.max_batch_hits, c.max_batch_events, L.stream);
+    if (st) return st;
+    L.in_bytes = s.input_bytes(c.max_batch_events, c.max_batch_hits);
+    if (hipMalloc(&L.d_in, L.in_bytes) != hipSuccess) return HOUGH_ERR_OOM;
+    if (hipHostMalloc(reinterpret_cast<void **>(&L.h_in), L.in_bytes, hipHostMallocDefault) != hipSuccess)
+        return HOUGH_ERR_OOM;
+    const int64_t ncand = c.max_batch_hits / (int64_t)s.ctx->cfg.min_votes + 1;
+    const size_t o_cand = align16(8 * HOUGH_COUNTS);
+    const size_t o_hits = align16(o_cand + sizeof(hough_candidate) * (size_t)ncand);
+    const size_t out_bytes = o_hits + 4 * (size_t)c.max_batch_hits;
+    // written by the device and read by the host after the completion event
+    if (hipHostMalloc(reinterpret_cast<void **>(&L.h_out), out_bytes, hipHostMallocCoherent) != hipSuccess)
+        return HOUGH_ERR_OOM;
+    void *dev = nullptr;
+    if (hipHostGetDevicePointer(&dev, L.h_out, 0) != hipSuccess) return HOUGH_ERR_DEVICE;
+    // the host pointer is the device pointer (one address space); keep both
+    // views apart in case a platform maps them differently
+    if (dev != L.h_out) return HOUGH_ERR_DEVICE;
+    L.counts = reinterpret_cast<int64_t *>(L.h_out);
+    L.cand = reinterpret_cast<hough_candidate *>(L.h_out + o_cand);
+    L.hits = reinterpret_cast<int32_t *>(L.h_out + o_hits);
+    if (hipStreamSynchronize(L.stream) != hipSuccess) return HOUGH_ERR_DEVICE;
+    s.st.device_bytes += (int64_t)(L.ws.bytes + L.in_bytes);
+    return HOUGH_OK;
+}
+
+bool valid_hits(const Server &s, const float *z, const int16_t *vane, int64_t b, int64_t n) {
+    const int nv = s.ctx->cfg.n_vanes;
+    for (int64_t i = b; i < b + n; ++i) {
+        if (vane[i] < 0 || vane[i] >= nv) return false;
+        if (!(std::fabs(z[i]) <= HOUGH_Z_LIMIT)) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+hough_status hough_server_create(const hough_config *cfg, int device, const hough_server_config *scfg,
+                                 void **server) {
+    if (!server) return HOUGH_ERR_INVALID_ARG;
+    *server = nullptr;
+    hough_server_config c{};
+    if (scfg) c = *scfg;
+    if (c.lanes == 0) c.lanes = 3;
+    if (c.max_batch_events == 0) c.max_batch_events = 4096;
+    if (c.max_batch_hits == 0) c.max_batch_hits = 1 << 20;
+    if (c.queue_hits == 0) c.queue_hits = (int64_t)1 << 26;
+    if (c.queue_events == 0) c.queue_events = 1 << 20;
+    if (c.lanes < 1 || c.lanes > kMaxLanes || c.max_batch_events < 1 || c.max_batch_hits < 1 ||
+        c.max_batch_hits > 0x7fffffffLL || c.queue_hits < 1 || c.queue_events < 1)
+        return HOUGH_ERR_INVALID_ARG;
+    for (int r : c.reserved)
+        if (r != 0) return HOUGH_ERR_INVALID_ARG;
+    Server *s = new (std::nothrow) Server();
+    if (!s) return HOUGH_ERR_OOM;
+    s->sc = c;
+    Ctx *ctx = nullptr;
+    hough_status st = hough::rt::make_context(cfg, device, &ctx);
+    if (st) {
+        delete s;
+        return st;
+    }
+    s->ctx = ctx;
+    s->lanes.resize(c.lanes);
+    for (int i = 0; i < c.lanes; ++i) {
+        st = make_lane(*s, s->lanes[i], i);
+        if (st) {
+            free_server(s);
+            return st;
+        }
+    }
+    s->t0 = Clock::now();
+    try {
+        s->thread = std::thread([s] { s->run(); });
+    } catch (...) {
+        free_server(s);
+        return HOUGH_ERR_INTERNAL;
+    }
+    *server = s;
+    return HOUGH_OK;
+}
+
+hough_status hough_server_destroy(void *server) {
+    if (!server) return HOUGH_OK;
+    Server *s = as_server(server);
+    if (!s) return HOUGH_ERR_INVALID_ARG;
+    {
+        // drop what has not been admitted; launches in flight finish first
+        std::lock_guard<std::mutex> g(s->mq);
+        s->queue.clear();
+        s->q_hits = 0;
+        s->st.pending_events = 0;
+    }
+    free_server(s);
+    return HOUGH_OK;
+}
+
+double hough_server_clock(const void *server) {
+    const Server *s = as_server(server);
+    return s ? s->now() : -1.0;
+}
+
+hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
+                                 const float *z, const int16_t *vane, const double *t_arrival,
+                                 int32_t *n_accepted) {
+    Server *s = as_server(server);
+    if (!s || n < 0 || !n_accepted || (n > 0 && !offsets)) return HOUGH_ERR_INVALID_ARG;
+    *n_accepted = 0;
+    for (int32_t r = 0; r < n; ++r)
+        if (offsets[r + 1] < offsets[r] || offsets[r] < 0) return HOUGH_ERR_INVALID_ARG;
+    if (n > 0 && offsets[n] > offsets[0] && (!z || !vane)) return HOUGH_ERR_INVALID_ARG;
+    std::vector<Result> refused;
+    int32_t r = 0;
+    {
+        std::unique_lock<std::mutex> g(s->mq);
+        const double t = s->now();
+        for (; r < n; ++r) {
+            const int64_t b = offsets[r];
+            const int64_t cnt = offsets[r + 1] - b;
+            const uint64_t tag = tags ? tags[r] : (uint64_t)r;
+            const double ta = t_arrival ? t_arrival[r] : t;
+            hough_status bad = HOUGH_OK;
+            if (cnt > s->sc.max_batch_hits || cnt > HOUGH_MAX_EVENT_HITS)
+                bad = HOUGH_ERR_CAPACITY;
+            else if (!valid_hits(*s, z, vane, b, cnt))
+                bad = HOUGH_ERR_DATA;
+            if (bad) {
+                Result R;
+                R.rec.tag = tag;
+                R.rec.status = bad;
+                R.rec.n_hits = (int32_t)std::min<int64_t>(cnt, 0x7fffffff);
+                R.rec.lane = -1;
+                R.rec.t_arrival = ta;
+                R.rec.t_admit = t;
+                R.rec.t_done = t;
+                refused.push_back(std::move(R));
+                s->st.refused += 1;
+                s->st.completed += 1;
+                continue;
+            }
+            if ((int64_t)s->queue.size() + 1 > s->sc.queue_events || s->q_hits + cnt > s->sc.queue_hits) break;
+            Request q;
+            q.tag = tag;
+            q.t_arrival = ta;
+            q.n = (int32_t)cnt;
+            q.z.assign(z + b, z + b + cnt);
+            q.vane.assign(vane + b, vane + b + cnt);
+            s->queue.push_back(std::move(q));
+            s->q_hits += cnt;
+            s->st.submitted += 1;
+            s->st.pending_events += 1;
+            s->st.max_pending_events = std::max(s->st.max_pending_events, s->st.pending_events);
+        }
+    }
+    if (!refused.empty()) {
+        std::lock_guard<std::mutex> g(s->mr);
+        for (Result &R : refused) s->results.push_back(std::move(R));
+    }
+    s->cv.notify_all();
+    *n_accepted = r;
+    return HOUGH_OK;
+}
+
+hough_status hough_server_poll(void *server, int32_t max_results, hough_served *results, hough_candidate *cand,
+                               int64_t cand_capacity, int32_t *hit_index, int64_t hit_capacity,
+                               int32_t *n_results) {
+    Server *s = as_server(server);
+    if (!s || max_results < 0 || !n_results || (max_results > 0 && !results) || cand_capacity < 0 ||
+        hit_capacity < 0 || (cand_capacity > 0 && !cand) || (hit_capacity > 0 && !hit_index))
+        return HOUGH_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(s->mr);
+    int32_t k = 0;
+    int64_t co = 0, ho = 0;
+    while (k < max_results && !s->results.empty()) {
+        Result &R = s->results.front();
+        const int64_t nc = (int64_t)R.cand.size(), nh = (int64_t)R.hits.size();
+        if (co + nc > cand_capacity || ho + nh > hit_capacity) break;
+        hough_served rec = R.rec;
+        rec.cand_offset = co;
+        rec.hit_offset = ho;
+        if (nc) std::memcpy(cand + co, R.cand.data(), sizeof(hough_candidate) * (size_t)nc);
+        if (nh) std::memcpy(hit_index + ho, R.hits.data(), 4 * (size_t)nh);
+        results[k++] = rec;
+        co += nc;
+        ho += nh;
+        s->results.pop_front();
+    }
+    *n_results = k;
+    return HOUGH_OK;
+}
+
+hough_status hough_server_drain(void *server, double timeout_s) {
+    Server *s = as_server(server);
+    if (!s) return HOUGH_ERR_INVALID_ARG;
+    const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                          std::chrono::duration<double>(std::max(0.0, timeout_s)));
+    std::unique_lock<std::mutex> g(s->mq);
+    const bool ok = s->cv.wait_until(g, until, [s] { return s->queue.empty() && s->lanes_busy == 0; });
+    return ok ? HOUGH_OK : HOUGH_ERR_CAPACITY;
+}
+
+hough_status hough_server_get_stats(const void *server, hough_server_stats *out) {
+    const Server *s = as_server(server);
+    if (!s || !out) return HOUGH_ERR_INVALID_ARG;
+    Server *m = const_cast<Server *>(s);
+    {
+        std::lock_guard<std::mutex> g(m->mq);
+        *out = m->st;
+    }
+    std::lock_guard<std::mutex> g(m->mr);
+    out->results_waiting = (int64_t)m->results.size();
+    return HOUGH_OK;
+}
+
+}  // extern "C"

@@ -31,7 +31,9 @@ COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
            "hough_timing", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
-           "hough_autotune", "hough_status_string", "hough_last_error")
+           "hough_autotune", "hough_server_create", "hough_server_destroy", "hough_server_clock",
+           "hough_server_submit", "hough_server_poll", "hough_server_drain", "hough_server_get_stats",
+           "hough_status_string", "hough_last_error")
 
 cand_dtype = np.dtype([("event", "<i4"), ("iter", "<i4"), ("theta_bin", "<i4"), ("rho_bin", "<i4"),
                        ("peak_votes", "<u4"), ("n_hits", "<u4"), ("hit_offset", "<i8"),
@@ -48,6 +50,23 @@ class HoughConfig(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("wg_threads", ctypes.c_int32), ("sweep_groups", ctypes.c_int32),
                 ("sweep_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("max_batch_events", ctypes.c_int32),
+                ("max_batch_hits", ctypes.c_int64), ("queue_hits", ctypes.c_int64),
+                ("queue_events", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+served_dtype = np.dtype([("tag", "<u8"), ("status", "<i4"), ("n_hits", "<i4"), ("n_candidates", "<i4"),
+                         ("lane", "<i4"), ("cand_offset", "<i8"), ("hit_offset", "<i8"),
+                         ("n_hit_index", "<i8"), ("t_arrival", "<f8"), ("t_admit", "<f8"),
+                         ("t_done", "<f8")])
+assert served_dtype.itemsize == 72
+
+SERVER_STAT_NAMES = ("submitted", "refused", "completed", "launches", "launched_events", "launched_hits",
+                     "pending_events", "max_pending_events", "max_lanes_busy", "device_bytes",
+                     "results_waiting")
 
 
 class HoughError(RuntimeError):
@@ -103,6 +122,21 @@ def load_library(path: str = LIB_PATH):
     lib.hough_autotune.argtypes = [cfgp, ctypes.c_int, P, I32, I64, P, P, P, I32, cfgp,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I32)]
     lib.hough_autotune.restype = st
+    scfgp = ctypes.POINTER(ServerConfig)
+    lib.hough_server_create.argtypes = [cfgp, ctypes.c_int, scfgp, ctypes.POINTER(P)]
+    lib.hough_server_create.restype = st
+    lib.hough_server_destroy.argtypes = [P]
+    lib.hough_server_destroy.restype = st
+    lib.hough_server_clock.argtypes = [P]
+    lib.hough_server_clock.restype = ctypes.c_double
+    lib.hough_server_submit.argtypes = [P, I32, P, P, P, P, P, ctypes.POINTER(I32)]
+    lib.hough_server_submit.restype = st
+    lib.hough_server_poll.argtypes = [P, I32, P, P, I64, P, I64, ctypes.POINTER(I32)]
+    lib.hough_server_poll.restype = st
+    lib.hough_server_drain.argtypes = [P, ctypes.c_double]
+    lib.hough_server_drain.restype = st
+    lib.hough_server_get_stats.argtypes = [P, P]
+    lib.hough_server_get_stats.restype = st
     lib.hough_status_string.argtypes = [ctypes.c_int]
     lib.hough_status_string.restype = ctypes.c_char_p
     lib.hough_last_error.argtypes = [P]
@@ -340,3 +374,150 @@ def autotune(z, vane, offsets, device: int = 0, repeats: int = 3, stream=None, *
     if st != HOUGH_OK:
         raise HoughError(st, lib.hough_last_error(None).decode())
     return best, ms.value, tried.value
+
+
+@dataclasses.dataclass
+class Served:
+    """One finished request: its record (a served_dtype row), candidates and
+    hit indices (exactly what a one-event find on the same hits returns)."""
+    rec: np.void
+    cand: np.ndarray
+    hit_index: np.ndarray
+
+    @property
+    def tag(self) -> int:
+        return int(self.rec["tag"])
+
+    @property
+    def status(self) -> int:
+        return int(self.rec["status"])
+
+    @property
+    def latency(self) -> float:
+        return float(self.rec["t_done"] - self.rec["t_arrival"])
+
+
+class HoughServer:
+    """Served form: continuous batching of streamed events over launch lanes
+    (hough_server_* in the C ABI). Hits are host numpy arrays; results come
+    back as host arrays."""
+
+    def __init__(self, device: int = 0, lanes: int = 0, max_batch_events: int = 0,
+                 max_batch_hits: int = 0, queue_hits: int = 0, queue_events: int = 0, **cfg_overrides):
+        self._lib = load_library()
+        self.config = default_config(**cfg_overrides)
+        sc = ServerConfig()
+        sc.lanes, sc.max_batch_events, sc.max_batch_hits = lanes, max_batch_events, max_batch_hits
+        sc.queue_hits, sc.queue_events = queue_hits, queue_events
+        h = ctypes.c_void_p()
+        st = self._lib.hough_server_create(ctypes.byref(self.config), device, ctypes.byref(sc), ctypes.byref(h))
+        if st != HOUGH_OK:
+            raise HoughError(st, "hough_server_create")
+        self._h = h
+        self._cbuf = np.zeros(1 << 16, cand_dtype)
+        self._hbuf = np.zeros(1 << 20, np.int32)
+        self._rbuf = np.zeros(4096, served_dtype)
+
+    def clock(self) -> float:
+        return float(self._lib.hough_server_clock(self._h))
+
+    def submit(self, z: np.ndarray, vane: np.ndarray, offsets: np.ndarray, tags: Optional[np.ndarray] = None,
+               t_arrival: Optional[np.ndarray] = None) -> int:
+        """Queues the events of a CSR batch (host arrays); returns how many,
+        from the first, were taken (fewer only when the queue is full)."""
+        z = np.ascontiguousarray(z, np.float32)
+        vane = np.ascontiguousarray(vane, np.int16)
+        offsets = np.ascontiguousarray(offsets, np.int64)
+        n = len(offsets) - 1
+        if tags is not None:
+            tags = np.ascontiguousarray(tags, np.uint64)
+            assert len(tags) == n
+        if t_arrival is not None:
+            t_arrival = np.ascontiguousarray(t_arrival, np.float64)
+            assert len(t_arrival) == n
+        acc = ctypes.c_int32()
+        ptr = lambda a: a.ctypes.data if a is not None and a.size else None
+        st = self._lib.hough_server_submit(self._h, n, ptr(tags), offsets.ctypes.data, ptr(z), ptr(vane),
+                                           ptr(t_arrival), ctypes.byref(acc))
+        if st != HOUGH_OK:
+            raise HoughError(st, "hough_server_submit")
+        return int(acc.value)
+
+    def poll(self, max_results: int = 4096) -> list:
+        """Finished results, oldest launch first."""
+        out = []
+        while True:
+            if len(self._rbuf) < max_results:
+                self._rbuf = np.zeros(max_results, served_dtype)
+            k = ctypes.c_int32()
+            st = self._lib.hough_server_poll(self._h, max_results, self._rbuf.ctypes.data, self._cbuf.ctypes.data,
+                                             len(self._cbuf), self._hbuf.ctypes.data, len(self._hbuf),
+                                             ctypes.byref(k))
+            if st != HOUGH_OK:
+                raise HoughError(st, "hough_server_poll")
+            n = k.value
+            for r in self._rbuf[:n]:
+                c0, nc = int(r["cand_offset"]), int(r["n_candidates"])
+                h0, nh = int(r["hit_offset"]), int(r["n_hit_index"])
+                out.append(Served(r.copy(), self._cbuf[c0:c0 + nc].copy(), self._hbuf[h0:h0 + nh].copy()))
+            if n == 0 or len(out) >= max_results:
+                if n == 0 and self.stats()["results_waiting"] > 0 and not out:
+                    # the next result does not fit the buffers: grow them
+                    self._cbuf = np.zeros(2 * len(self._cbuf), cand_dtype)
+                    self._hbuf = np.zeros(2 * len(self._hbuf), np.int32)
+                    continue
+                return out
+            max_results -= n
+            if max_results <= 0:
+                return out
+
+    def poll_records(self, max_results: int = 65536):
+        """(records, candidates, hit indices) of up to max_results finished
+        requests as flat host arrays (offsets in the records)."""
+        if len(self._rbuf) < max_results:
+            self._rbuf = np.zeros(max_results, served_dtype)
+        while True:
+            k = ctypes.c_int32()
+            st = self._lib.hough_server_poll(self._h, max_results, self._rbuf.ctypes.data, self._cbuf.ctypes.data,
+                                             len(self._cbuf), self._hbuf.ctypes.data, len(self._hbuf),
+                                             ctypes.byref(k))
+            if st != HOUGH_OK:
+                raise HoughError(st, "hough_server_poll")
+            n = k.value
+            if n == 0 and self.stats()["results_waiting"] > 0:
+                self._cbuf = np.zeros(2 * len(self._cbuf), cand_dtype)
+                self._hbuf = np.zeros(2 * len(self._hbuf), np.int32)
+                continue
+            recs = self._rbuf[:n].copy()
+            nc = int(recs["cand_offset"][-1] + recs["n_candidates"][-1]) if n else 0
+            nh = int(recs["hit_offset"][-1] + recs["n_hit_index"][-1]) if n else 0
+            return recs, self._cbuf[:nc].copy(), self._hbuf[:nh].copy()
+
+    def drain(self, timeout: float = 60.0) -> None:
+        st = self._lib.hough_server_drain(self._h, timeout)
+        if st != HOUGH_OK:
+            raise HoughError(st, "hough_server_drain (timed out)")
+
+    def stats(self) -> dict:
+        a = np.zeros(16, np.int64)
+        st = self._lib.hough_server_get_stats(self._h, a.ctypes.data)
+        if st != HOUGH_OK:
+            raise HoughError(st, "hough_server_get_stats")
+        return dict(zip(SERVER_STAT_NAMES, (int(x) for x in a)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.hough_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -79,6 +79,52 @@ def test_null_and_bad_context_rejected():
         hough.HOUGH_ERR_INVALID_ARG
 
 
+def test_server_struct_layouts_match_header(tmp_path):
+    import subprocess
+    from paper_2511_02742_amd import hough
+    src = tmp_path / "slayout.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"hough_tf.h\"\n"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(hough_server_config),"
+        " offsetof(hough_server_config, max_batch_hits), offsetof(hough_server_config, queue_events),"
+        " sizeof(hough_served), offsetof(hough_served, cand_offset), offsetof(hough_served, t_done),"
+        " sizeof(hough_server_stats), offsetof(hough_server_stats, device_bytes),"
+        " offsetof(hough_server_stats, results_waiting)); return 0;}\n")
+    exe = tmp_path / "slayout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    sd = hough.served_dtype
+    want = [ctypes.sizeof(hough.ServerConfig), hough.ServerConfig.max_batch_hits.offset,
+            hough.ServerConfig.queue_events.offset, sd.itemsize, sd.fields["cand_offset"][1],
+            sd.fields["t_done"][1], 16 * 8, 8 * hough.SERVER_STAT_NAMES.index("device_bytes"),
+            8 * hough.SERVER_STAT_NAMES.index("results_waiting")]
+    assert got == want
+
+
+def test_server_rejects_bad_arguments_without_a_device():
+    """Argument checks that return before any device work."""
+    from paper_2511_02742_amd import hough
+    lib = hough.load_library()
+    cfg = hough.default_config()
+    h = ctypes.c_void_p()
+    bad = hough.ServerConfig()
+    bad.lanes = 9
+    assert lib.hough_server_create(ctypes.byref(cfg), 0, ctypes.byref(bad), ctypes.byref(h)) == \
+        hough.HOUGH_ERR_INVALID_ARG
+    bad = hough.ServerConfig()
+    bad.reserved[1] = 1
+    assert lib.hough_server_create(ctypes.byref(cfg), 0, ctypes.byref(bad), ctypes.byref(h)) == \
+        hough.HOUGH_ERR_INVALID_ARG
+    assert not h.value
+    assert lib.hough_server_destroy(None) == 0
+    n = ctypes.c_int32()
+    assert lib.hough_server_submit(None, 0, None, None, None, None, None, ctypes.byref(n)) == \
+        hough.HOUGH_ERR_INVALID_ARG
+    assert lib.hough_server_poll(None, 0, None, None, 0, None, 0, ctypes.byref(n)) == hough.HOUGH_ERR_INVALID_ARG
+    assert lib.hough_server_drain(None, 0.0) == hough.HOUGH_ERR_INVALID_ARG
+    assert lib.hough_server_clock(None) == -1.0
+
+
 def test_kernels_use_no_scratch():
     """The finder and sweep kernels must keep everything in registers and LDS:
     a scratch (private memory) spill costs far more than the kernel's own work.
