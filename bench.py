@@ -207,6 +207,7 @@ def serve_bench(args, finder, log):
     batching. Latency is the server's completion time minus the request's
     arrival time. A final burst (every request arriving at once) gives the
     most the served form sustains."""
+    import numpy as np
     import torch
     from paper_2511_02742_amd import eventgen
     from paper_2511_02742_amd.hough import HoughServer
@@ -278,7 +279,7 @@ def serve_bench(args, finder, log):
             log("served %s: %s" % ("burst" if rate == float("inf") else "%.0f/s" % rate, ent))
             res.append(ent)
         dev_bytes = srv.stats()["device_bytes"]
-    return {"workload": "mixed pileup {1,10,25,50,100} tracks + 1% noise, pool of %d seeded events "
+    return {"workload": "mixed pileup {1,10,25,50,100} tracks + 1%% noise, pool of %d seeded events "
                         "(seeds 2000000..), Poisson arrivals" % P,
             "lanes": args.serve_lanes, "device_bytes": dev_bytes, "mean_hits": round(float(lens.mean()), 1),
             "rates": res}

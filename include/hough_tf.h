@@ -329,6 +329,8 @@ hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, 
  * `results`, their candidates into `cand` and their hit indices into
  * `hit_index` (host arrays of the given capacities), stopping before the
  * first result that does not fit. *n_results receives the number moved.
+ * Returns HOUGH_ERR_CAPACITY (and moves nothing) when the oldest waiting
+ * result alone does not fit the arrays.
  */
 hough_status hough_server_poll(void *server, int32_t max_results, hough_served *results, hough_candidate *cand,
                                int64_t cand_capacity, int32_t *hit_index, int64_t hit_capacity,

@@ -481,6 +481,8 @@ hough_status hough_server_poll(void *server, int32_t max_results, hough_served *
         s->results.pop_front();
     }
     *n_results = k;
+    // the oldest result alone is larger than the caller's arrays
+    if (k == 0 && max_results > 0 && !s->results.empty()) return HOUGH_ERR_CAPACITY;
     return HOUGH_OK;
 }
 

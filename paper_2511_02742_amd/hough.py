@@ -418,6 +418,11 @@ class HoughServer:
         self._hbuf = np.zeros(1 << 20, np.int32)
         self._rbuf = np.zeros(4096, served_dtype)
 
+    def _grow(self) -> None:
+        # the oldest waiting result does not fit the result arrays
+        self._cbuf = np.zeros(2 * len(self._cbuf), cand_dtype)
+        self._hbuf = np.zeros(2 * len(self._hbuf), np.int32)
+
     def clock(self) -> float:
         return float(self._lib.hough_server_clock(self._h))
 
@@ -453,6 +458,9 @@ class HoughServer:
             st = self._lib.hough_server_poll(self._h, max_results, self._rbuf.ctypes.data, self._cbuf.ctypes.data,
                                              len(self._cbuf), self._hbuf.ctypes.data, len(self._hbuf),
                                              ctypes.byref(k))
+            if st == HOUGH_ERR_CAPACITY:
+                self._grow()
+                continue
             if st != HOUGH_OK:
                 raise HoughError(st, "hough_server_poll")
             n = k.value
@@ -461,11 +469,6 @@ class HoughServer:
                 h0, nh = int(r["hit_offset"]), int(r["n_hit_index"])
                 out.append(Served(r.copy(), self._cbuf[c0:c0 + nc].copy(), self._hbuf[h0:h0 + nh].copy()))
             if n == 0 or len(out) >= max_results:
-                if n == 0 and self.stats()["results_waiting"] > 0 and not out:
-                    # the next result does not fit the buffers: grow them
-                    self._cbuf = np.zeros(2 * len(self._cbuf), cand_dtype)
-                    self._hbuf = np.zeros(2 * len(self._hbuf), np.int32)
-                    continue
                 return out
             max_results -= n
             if max_results <= 0:
@@ -481,13 +484,12 @@ class HoughServer:
             st = self._lib.hough_server_poll(self._h, max_results, self._rbuf.ctypes.data, self._cbuf.ctypes.data,
                                              len(self._cbuf), self._hbuf.ctypes.data, len(self._hbuf),
                                              ctypes.byref(k))
+            if st == HOUGH_ERR_CAPACITY:
+                self._grow()
+                continue
             if st != HOUGH_OK:
                 raise HoughError(st, "hough_server_poll")
             n = k.value
-            if n == 0 and self.stats()["results_waiting"] > 0:
-                self._cbuf = np.zeros(2 * len(self._cbuf), cand_dtype)
-                self._hbuf = np.zeros(2 * len(self._hbuf), np.int32)
-                continue
             recs = self._rbuf[:n].copy()
             nc = int(recs["cand_offset"][-1] + recs["n_candidates"][-1]) if n else 0
             nh = int(recs["hit_offset"][-1] + recs["n_hit_index"][-1]) if n else 0

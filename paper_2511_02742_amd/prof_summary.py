@@ -58,6 +58,21 @@ def kernel_stats(trace_dir: str):
     return out
 
 
+def dispatches_by_grid(trace_dir: str, kernel: str = "k_find"):
+    """{(grid_x, workgroup_x): [durations in ns]} of one kernel's dispatches,
+    from the per-dispatch kernel trace."""
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no kernel_trace.csv under %s" % trace_dir)
+    out = defaultdict(list)
+    for r in csv.DictReader(open(files[0])):
+        if kernel not in r["Kernel_Name"]:
+            continue
+        key = (int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        out[key].append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    return out
+
+
 def counter_per_dispatch(pmc_dir: str, counter: str):
     files = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)
     if not files:
@@ -117,7 +132,16 @@ def main():
         lines.append("| %s | %d | %.2f | %.2f | %.2f | %.3f | %.1f |" % (
             r["name"], r["calls"], r["avg_ns"] / 1e3, r["min_ns"] / 1e3, r["max_ns"] / 1e3,
             r["total_ns"] / 1e6, r["pct"]))
+    grids = dispatches_by_grid(args.trace)
+    lines += ["", "k_find dispatches by launch size (the batched call is the largest grid):", "",
+              "| workgroups | threads/wg | dispatches | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for (gx, wx), d in sorted(grids.items(), key=lambda kv: -kv[0][0]):
+        lines.append("| %d | %d | %d | %.2f | %.2f | %.2f |" % (gx // wx, wx, len(d), statistics.mean(d) / 1e3,
+                                                              min(d) / 1e3, max(d) / 1e3))
     kv = {"kernel_sha256_16": h}
+    big = max(grids) if grids else None
+    if big:
+        kv["batched_k_find_avg_us"] = "%.2f" % (statistics.mean(grids[big]) / 1e3)
     if args.fetch and args.write and args.copy_mib:
         t = traffic(args.fetch, args.write, args.copy_mib)
         lines += ["", "HBM traffic of the batched k_find launch (median over %d dispatches), from "

@@ -143,3 +143,21 @@ def test_served_empty_requests(gpu_available):
         got = _collect(srv, 3)
     for t in range(3):
         assert got[t].status == 0 and len(got[t].cand) == 0 and len(got[t].hit_index) == 0
+
+
+def test_served_poll_reports_a_result_too_large(gpu_available):
+    import ctypes
+    from paper_2511_02742_amd.hough import HOUGH_ERR_CAPACITY, HoughServer, cand_dtype, served_dtype
+    ev = eventgen.pileup_event(11)
+    with HoughServer(0) as srv:
+        assert srv.submit(ev.z, ev.vane, np.array([0, ev.n_hits], np.int64)) == 1
+        srv.drain(60.0)
+        recs = np.zeros(1, served_dtype)
+        cand = np.zeros(1, cand_dtype)
+        hits = np.zeros(4, np.int32)
+        k = ctypes.c_int32(-1)
+        st = srv._lib.hough_server_poll(srv._h, 1, recs.ctypes.data, cand.ctypes.data, 1, hits.ctypes.data, 4,
+                                        ctypes.byref(k))
+        assert st == HOUGH_ERR_CAPACITY and k.value == 0
+        got = _collect(srv, 1)
+    assert got[0].status == 0 and len(got[0].cand) > 1
