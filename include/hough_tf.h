@@ -120,7 +120,9 @@ typedef struct {
 #define HOUGH_COUNT_HOT_SCANS 10   /* tiles scanned after a hot-list overflow */
 #define HOUGH_COUNT_HOTSET_FULL 11 /* row-stream sweeps whose hot set overflowed */
 #define HOUGH_COUNT_RECOUNTS 12    /* iterations served by a hot-set recount */
-/* entries 13..15 are written as 0 */
+#define HOUGH_COUNT_LARGE 13       /* iterations run in the large-event path
+                                      (hot set and peaks in device memory) */
+/* entries 14..15 are written as 0 */
 
 /* Largest hit count of one event. */
 #define HOUGH_MAX_EVENT_HITS 131072

@@ -125,7 +125,7 @@ hough_status choose_shape(Ctx &c, std::string &why) {
     // at every event size up to the largest
     int assoc_min = 0;
     for (int w = 1; w <= HOUGH_MAX_EVENT_HITS / 64; ++w)
-        assoc_min = std::max(assoc_min, hough::assoc_fixed_bytes(w, kPeakKeep + kHotCap) + hough::assoc_peak_bytes(w));
+        assoc_min = std::max(assoc_min, hough::assoc_fixed_bytes(w) + hough::assoc_peak_bytes(w));
     c.tile_bytes = std::max(row_bytes * (rows + 2 * halo), assoc_min);
     c.tile_bytes = (c.tile_bytes + 15) & ~15;
     c.lds_bytes = c.tile_bytes + hough::find_lds_extra(c.wg_threads, kHotCap, kPeakKeep);
@@ -133,6 +133,14 @@ hough_status choose_shape(Ctx &c, std::string &why) {
     if (hough::set_find_lds_limit(c.wg_threads, c.lds_bytes) != hipSuccess) {
         why = "hipFuncSetAttribute failed for the finder kernel";
         return HOUGH_ERR_DEVICE;
+    }
+    {
+        int per_cu = 0;
+        if (hough::find_blocks_per_cu(c.wg_threads, c.lds_bytes, &per_cu) != hipSuccess || per_cu < 1) {
+            why = "occupancy query failed for the finder kernel";
+            return HOUGH_ERR_DEVICE;
+        }
+        c.max_resident = per_cu * prop.multiProcessorCount;
     }
     // row-stream layout inside the tile: one row buffer per wave (reused by
     // the hash table of the window test: a power-of-two slot count of 8 B,
@@ -144,13 +152,26 @@ hough_status choose_shape(Ctx &c, std::string &why) {
         while (2 * slots * 8 <= rb) slots *= 2;
         int cap = std::min(4096, slots / 2);
         cap = std::min(cap, (c.tile_bytes - rb - sorted_bytes) / 8);
-        // the row-stream path (at most 512 alive hits, 8 words) runs the
-        // association inside the row buffers
-        const int assoc_stream = hough::assoc_fixed_bytes(8, kPeakKeep + kHotCap) + 2 * hough::assoc_peak_bytes(8);
-        c.stream_ok = cap >= 256 && rb >= assoc_stream ? 1 : 0;
+        // the row-stream path (up to 512 register-resident alive hits plus
+        // hs_cap more in LDS for a large event) runs the association inside
+        // the row buffers, two peaks per pass at least
+        int assoc_stream = 0;
+        for (int w = 1; w <= (512 + std::max(cap, 0) + 63) / 64; ++w)
+            assoc_stream = std::max(assoc_stream, hough::assoc_fixed_bytes(w) + 2 * hough::assoc_peak_bytes(w));
+        // a large event's count histogram and scatter cursors (one int each
+        // per possible count) also sit in the row buffers
+        const int count_sort = 8 * (512 + std::max(cap, 0) + 1);
+        c.stream_ok = cap >= 256 && rb >= assoc_stream && rb >= count_sort ? 1 : 0;
         c.hs_cap = std::max(cap, 0);
         c.hs_off = rb;
         c.sorted_off = rb + 8 * c.hs_cap;
+        // large events: device-memory hot set and hash table, and a peak
+        // list the row buffers can sort (a power of two of u64 keys)
+        c.big_hs = 65536;
+        c.big_ht = 131072;
+        c.big_pk = 32768;
+        c.big_sort = 1;
+        while (2 * c.big_sort * 8 <= rb) c.big_sort *= 2;
     }
     // |rho| <= r (1 + 2^-24)^3 for r = sqrt(phi^2 + z^2); a rho at least
     // delta inside [rho_min, rho_max] gives a bin in [0, n_rho) after the
@@ -209,6 +230,12 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     const size_t o_stats = take(8 * 16), o_err = take(8 * 4), o_offs = take(8 * 4);
     const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
     const size_t o_ghs = c.sweep_groups > 0 ? take(8 * (size_t)ne * (size_t)std::max(c.hs_cap, 1)) : 0;
+    // large-event slots: no more workgroups than events, nor than fit the
+    // device at once, hold one at a time
+    const int32_t slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ne, std::max(c.max_resident, 1)));
+    const int64_t slot_bytes = (int64_t)align256(8 * ((size_t)c.big_hs + (size_t)c.big_ht + (size_t)c.big_pk));
+    const size_t o_pflags = take(4 * (size_t)slots);
+    const size_t o_pool = take((size_t)slots * (size_t)slot_bytes);
     if (w.base) {
         if (hipStreamSynchronize(s) != hipSuccess) return HOUGH_ERR_DEVICE;
         free_workspace(w);
@@ -236,11 +263,16 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     w.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
     w.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
     w.g_hs = c.sweep_groups > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
+    w.pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
+    w.pool = reinterpret_cast<unsigned char *>(base + o_pool);
+    w.pool_slots = slots;
+    w.slot_bytes = slot_bytes;
     // statistics, error and split-sweep words start cleared; every call
     // leaves them so
     if (hough::launch_reset(w.stats, w.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     if (hough::launch_zero_i32(w.g_cnt, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     if (hough::launch_zero_i32(w.g_flag, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_zero_i32(w.pool_flags, slots, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     return HOUGH_OK;
 }
 
@@ -284,6 +316,14 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     a.g_cnt = w.g_cnt;
     a.g_flag = w.g_flag;
     a.g_hs = (c.sweep_groups > 0 && c.stream_ok) ? w.g_hs : nullptr;
+    a.pool = w.pool;
+    a.pool_flags = w.pool_flags;
+    a.pool_slots = w.pool_slots;
+    a.big_hs = c.big_hs;
+    a.big_ht = c.big_ht;
+    a.big_pk = c.big_pk;
+    a.big_sort = c.big_sort;
+    a.slot_bytes = w.slot_bytes;
     return a;
 }
 

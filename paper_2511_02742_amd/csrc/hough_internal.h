@@ -8,15 +8,15 @@
 
 namespace hough {
 
-// LDS scratch of one association pass over W 64-hit words and npk peaks:
-// a fixed part (per-peak (cos, sin), the claimed mask, and for W up to
-// kAssocRoundMaxW the per-hit table of the parallel claim rounds) plus a
-// per-peak part (match masks, word prefixes, three ints).
+// LDS scratch of one association pass over W 64-hit words: a fixed part
+// (the claimed mask and, for W up to kAssocRoundMaxW, the per-hit table of
+// the parallel claim rounds) plus a per-peak part (match masks, word
+// prefixes, (cos, sin), (theta bin, rho bin) and three ints).
 constexpr int kAssocRoundMaxW = 64;
-__host__ __device__ inline int assoc_fixed_bytes(int W, int npk) {
-    return ((8 * npk + 15) & ~15) + 8 * W + (W <= kAssocRoundMaxW ? 4 * 64 * W : 0);
+__host__ __device__ inline int assoc_fixed_bytes(int W) {
+    return 8 * W + (W <= kAssocRoundMaxW ? 4 * 64 * W : 0);
 }
-__host__ __device__ inline int assoc_peak_bytes(int W) { return 12 * W + 12; }
+__host__ __device__ inline int assoc_peak_bytes(int W) { return 12 * W + 28; }
 
 // Everything the finder kernel needs, passed by value.
 struct FindArgs {
@@ -60,6 +60,17 @@ struct FindArgs {
     int32_t hs_cap;      // hot-set capacity (entries)
     int32_t hs_off;      // LDS byte offsets of the hot set and of the sorted peak keys
     int32_t sorted_off;
+    // large events: a workgroup takes one slot of device memory for the
+    // event (hot set, hash table of the window test, peak list); alive hits
+    // beyond the register-resident 512 sit in LDS at hs_off (hs_cap of them)
+    unsigned char *pool;     // pool_slots * slot_bytes
+    int32_t *pool_flags;     // [pool_slots] 1 = taken (0 between calls)
+    int32_t pool_slots;
+    int32_t big_hs;          // hot-set entries per slot
+    int32_t big_ht;          // hash slots per slot (power of two)
+    int32_t big_pk;          // peak entries per slot (<= big_ht)
+    int32_t big_sort;        // longest run of equal counts the row buffers sort (power of two)
+    int64_t slot_bytes;
 };
 
 struct DumpArgs {
@@ -102,6 +113,8 @@ hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_dump(const DumpArgs &a, int lds_bytes, hipStream_t s);
 hipError_t launch_set_offsets(int64_t *offsets, int64_t n, hipStream_t s);
 hipError_t set_find_lds_limit(int wg_threads, int lds_bytes);
+// Finder workgroups one CU holds at once for this shape.
+hipError_t find_blocks_per_cu(int wg_threads, int lds_bytes, int *blocks);
 // LDS bytes of k_find beyond the tile (hot list, peak lists, dummies).
 int find_lds_extra(int wg_threads, int hcap, int pkeep);
 hipError_t set_dump_lds_limit(int lds_bytes);

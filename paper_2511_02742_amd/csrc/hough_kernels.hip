@@ -53,6 +53,13 @@ __device__ __forceinline__ int wave_id() {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // Number of set bits of m in lanes below this one.
+// A wave-uniform 64-bit value moved to scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int mbcnt64(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -129,25 +136,29 @@ struct Shared {
     int n_trunc;     // peak-list truncations (diagnostics)
     int n_hotscan;   // hot-list overflow scans (diagnostics)
     int rcnt[2];     // open peaks of the current and the next claim round
+    int clc[16];     // per-wave crossing-list fill of the large-event sweep
+    int big_ovf;     // a large-event sweep lost a crossing (list full)
+    int slot;        // device-memory slot of a large event, or -1
+    int nruns;       // runs of equal counts in a large event's peak list
 };
 
 // LDS layout of k_find (dynamic part):
 //   [0, tile_bytes)        tile rows, reused by the association phase
 //   hot[hcap]              u32, (tile row << 16) | k
 //   pbuf[pkeep + hcap]     u64 peak keys
-//   dec[pkeep + hcap]      int2 (theta bin, rho bin) of the sorted peaks
 //   dummy[threads]         u32, one word per lane for masked-off votes
 // Inside the tile region the row-stream path uses
 //   [0, NW * pitch * 4)    one row buffer per wave; later the hash table of
 //                          the window test and the association scratch
 //   hs[hs_cap]             u64 keys of every bin that reached T (the hot set;
-//                          0 marks a bin that fell below T)
+//                          0 marks a bin that fell below T); for a large
+//                          event, the alive hits beyond the first 512 as
+//                          float2 (phi, z) instead
 //   sorted[pkeep + hcap]   u64 peak keys in descending order
 struct Lds {
     uint32_t *tile;
     uint32_t *hot;
     unsigned long long *pbuf;
-    int2 *dec;
     uint32_t *dummy;
     unsigned long long *hs;
     unsigned long long *sorted;
@@ -230,7 +241,7 @@ __device__ __forceinline__ void test_bin(const FindArgs &A, const Lds &L, int tr
 // Keeps the pkeep largest keys when the peak list holds more; the largest
 // dropped key becomes the floor below which later keys are refused.
 template <int NT>
-__device__ void maybe_truncate(const FindArgs &A, const Lds &L, Shared &sh) {
+__device__ __forceinline__ void maybe_truncate(const FindArgs &A, const Lds &L, Shared &sh) {
     const int cnt = sh.pcnt;
     if (cnt <= A.pkeep) return;
     const int cap = A.pkeep + A.hcap;
@@ -390,7 +401,7 @@ __device__ __forceinline__ void stream_dispatch(const FindArgs &A, const float2 
 }
 
 template <int NT>
-__device__ void stream_sweep(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
+__device__ __forceinline__ void stream_sweep(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
                              int n_alive, Shared &sh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
@@ -402,12 +413,64 @@ __device__ __forceinline__ uint32_t hs_hash(uint32_t flat, int log2n) {
     return (flat * 2654435761u) >> (32 - log2n);
 }
 
+// Window test of one bin >= T against the hash table of the bins >= T
+// (htk: flat + 1, 0 = empty; htc: count): a neighbour absent from the table
+// is below T and cannot beat the bin.
+__device__ __forceinline__ bool window_peak(const FindArgs &A, const uint32_t *htk, const uint32_t *htc, int log2n,
+                                            unsigned long long key) {
+    const uint32_t c = (uint32_t)(key >> 32);
+    const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+    const int j = (int)(flat / (uint32_t)A.n_rho);
+    const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
+    const int w = A.nms_radius;
+    const uint32_t mask = (1u << log2n) - 1u;
+    bool peak = true;
+    for (int dr = -w; dr <= w; ++dr) {
+        const int jj = j + dr;
+        if (jj < 0 || jj >= A.n_theta) continue;
+        for (int dk = -w; dk <= w; ++dk) {
+            const int kk = k + dk;
+            if (kk < 0 || kk >= A.n_rho || (dr == 0 && dk == 0)) continue;
+            const uint32_t f2 = (uint32_t)(jj * A.n_rho + kk);
+            uint32_t slot = hs_hash(f2, log2n);
+            uint32_t c2 = 0u;
+            for (;;) {
+                const uint32_t kf = htk[slot];
+                if (kf == 0u) break;
+                if (kf == f2 + 1u) {
+                    c2 = htc[slot];
+                    break;
+                }
+                slot = (slot + 1u) & mask;
+            }
+            // a neighbour with a lower flat index wins ties
+            if (c2 > c || (c2 == c && f2 < flat)) peak = false;
+        }
+    }
+    return peak;
+}
+
+// Inserts the live keys of hot set hs[0, n_hs) into the hash table.
+template <int NT>
+__device__ __forceinline__ void hash_insert(const unsigned long long *hs, int n_hs, uint32_t *htk, uint32_t *htc,
+                                           int log2n) {
+    const uint32_t mask = (1u << log2n) - 1u;
+    for (int e = threadIdx.x; e < n_hs; e += NT) {
+        const unsigned long long key = hs[e];
+        if (key == 0ull) continue;
+        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+        uint32_t slot = hs_hash(flat, log2n);
+        while (atomicCAS(&htk[slot], 0u, flat + 1u) != 0u) slot = (slot + 1u) & mask;
+        htc[slot] = (uint32_t)(key >> 32);
+    }
+}
+
 // Peaks among the n_hs hot bins (keys in L.hs): the window test looks the
 // neighbours up in an LDS hash table keyed by flat index (bins below T are
 // absent and count as 0). Leaves the peak keys sorted in descending order in
 // L.hs and returns their number.
 template <int NT>
-__device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &sh) {
+__device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &sh) {
     if (A.peak_mode == 0) {
         if (threadIdx.x == 0) sh.best = 0ull;
         __syncthreads();
@@ -427,47 +490,12 @@ __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &s
     for (int i = threadIdx.x; i < ht; i += NT) htk[i] = 0u;
     if (threadIdx.x == 0) sh.pcnt = 0;
     __syncthreads();
-    for (int e = threadIdx.x; e < n_hs; e += NT) {
-        const unsigned long long key = L.hs[e];
-        if (key == 0ull) continue;
-        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
-        uint32_t slot = hs_hash(flat, log2n);
-        while (atomicCAS(&htk[slot], 0u, flat + 1u) != 0u) slot = (slot + 1u) & (uint32_t)(ht - 1);
-        htc[slot] = (uint32_t)(key >> 32);
-    }
+    hash_insert<NT>(L.hs, n_hs, htk, htc, log2n);
     __syncthreads();
-    const int w = A.nms_radius;
     for (int e = threadIdx.x; e < n_hs; e += NT) {
         const unsigned long long key = L.hs[e];
         if (key == 0ull) continue;
-        const uint32_t c = (uint32_t)(key >> 32);
-        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
-        const int j = (int)(flat / (uint32_t)A.n_rho);
-        const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
-        bool peak = true;
-        for (int dr = -w; dr <= w; ++dr) {
-            const int jj = j + dr;
-            if (jj < 0 || jj >= A.n_theta) continue;
-            for (int dk = -w; dk <= w; ++dk) {
-                const int kk = k + dk;
-                if (kk < 0 || kk >= A.n_rho || (dr == 0 && dk == 0)) continue;
-                const uint32_t f2 = (uint32_t)(jj * A.n_rho + kk);
-                uint32_t slot = hs_hash(f2, log2n);
-                uint32_t c2 = 0u;
-                for (;;) {
-                    const uint32_t kf = htk[slot];
-                    if (kf == 0u) break;
-                    if (kf == f2 + 1u) {
-                        c2 = htc[slot];
-                        break;
-                    }
-                    slot = (slot + 1u) & (uint32_t)(ht - 1);
-                }
-                // a neighbour with a lower flat index wins ties
-                if (c2 > c || (c2 == c && f2 < flat)) peak = false;
-            }
-        }
-        if (peak) {
+        if (window_peak(A, htk, htc, log2n, key)) {
             const int slot = atomicAdd(&sh.pcnt, 1);
             if (slot < A.pkeep + A.hcap) L.pbuf[slot] = key;
         }
@@ -499,8 +527,8 @@ __device__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &s
 // against the bin with Eq. (4) and ballots count the matches. Bins below T
 // are marked dead (key 0).
 template <int NT>
-__device__ void recount(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
-                        int n_alive, int n_hs) {
+__device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restrict__ cs, unsigned long long *hs, const HitRegs &h,
+                        const float2 *xh, int nx, int n_alive, int n_hs) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
@@ -508,7 +536,7 @@ __device__ void recount(const FindArgs &A, const float2 *__restrict__ cs, const 
         // 64 bins at once: lane l loads bin e0 + l and its (cos, sin), then
         // the wave counts the bins one after another
         const int e = e0 + lane;
-        const unsigned long long key = e < n_hs ? L.hs[e] : 0ull;
+        const unsigned long long key = e < n_hs ? hs[e] : 0ull;
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
         const int j = key != 0ull ? (int)(flat / (uint32_t)A.n_rho) : 0;
         const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
@@ -529,16 +557,274 @@ __device__ void recount(const FindArgs &A, const float2 *__restrict__ cs, const 
                     cnt += __popcll(__ballot(ch * kWave + lane < n_alive && kk == ki));
                 }
             }
+            for (int x = 0; x < nx; ++x) {
+                const int q = x * kWave + lane;
+                const float2 pz = xh[q];
+                const int kk = rho_bin(pz.x, pz.y, c, sn, A.rho_min, A.inv_w);
+                cnt += __popcll(__ballot(kChunks * kWave + q < n_alive && kk == ki));
+            }
             if (lane == i) out = (uint32_t)cnt >= A.min_votes ? bin_key((uint32_t)cnt, flat) : 0ull;
         }
-        if (key != 0ull) L.hs[e] = out;
+        if (key != 0ull) hs[e] = out;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Large events: more alive hits than the registers hold, or more bins at or
+// above T (or more peaks) than the LDS lists hold. The workgroup takes a slot
+// of device memory for the event; the alive hits beyond the first 512 sit in
+// LDS; the hot set, the hash table of the window test and the peak list live
+// in the slot; the peaks are sorted in the row buffers.
+// ---------------------------------------------------------------------------
+
+// Workgroup barrier that also orders the workgroup's device-memory writes
+// before its later reads (the slot arrays are written and read by different
+// waves; the acquire drops L1 lines an earlier event left behind).
+__device__ __forceinline__ void sync_global() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+struct Slot {
+    unsigned long long *hs;   // hot set, big_hs keys
+    uint32_t *htk, *htc;      // hash table, big_ht slots each
+    unsigned long long *pk;   // peak keys, big_pk
+};
+
+__device__ __forceinline__ Slot slot_ptrs(const FindArgs &A, int s) {
+    unsigned char *base = A.pool + (size_t)s * (size_t)A.slot_bytes;
+    Slot r;
+    r.hs = reinterpret_cast<unsigned long long *>(base);
+    r.htk = reinterpret_cast<uint32_t *>(r.hs + A.big_hs);
+    r.htc = r.htk + A.big_ht;
+    r.pk = reinterpret_cast<unsigned long long *>(r.htc + A.big_ht);
+    return r;
+}
+
+// A free slot for this workgroup, or -1. The host provides at least as many
+// slots as finder workgroups can be resident at once (or as events), so a
+// running workgroup finds one; the scan is bounded either way.
+__device__ __forceinline__ int acquire_slot(const FindArgs &A, Shared &sh) {
+    if (threadIdx.x == 0) {
+        int got = -1;
+        const int n = A.pool_slots;
+        for (int i = 0; i < 2 * n && got < 0; ++i) {
+            const int c = (int)((blockIdx.x + (unsigned)i) % (unsigned)n);
+            if (atomicCAS(&A.pool_flags[c], 0, 1) == 0) got = c;
+        }
+        sh.slot = got;
+    }
+    sync_global();
+    return sh.slot;
+}
+
+__device__ __forceinline__ void release_slot(const FindArgs &A, int s) {
+    if (s < 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(&A.pool_flags[s], 0);
+}
+
+// Loads the first 512 alive hits into registers and the rest into LDS at xh;
+// returns whether every alive hit votes inside [0, n_rho) in every row.
+template <int NT>
+__device__ __forceinline__ bool load_big(const FindArgs &A, int64_t b, int n_alive, HitRegs &h, float2 *xh) {
+    load_batch(A, b, n_alive, 0, h);
+    int ok = 1;
+    for (int q = kChunks * kWave + threadIdx.x; q < n_alive; q += NT) {
+        const float p = A.aphi[b + q], z = A.az[b + q];
+        xh[q - kChunks * kWave] = make_float2(p, z);
+        ok &= ((double)p * p + (double)z * z <= A.safe_r2) ? 1 : 0;
+    }
+    return __syncthreads_and(ok) != 0 && h.safe;
+}
+
+// Row-stream votes of a large event (every hit safe): the 8 register chunks
+// (masked per lane) and nx LDS chunks per row. A bin lifted to T is noted in
+// the wave's crossing list (cl, at most ncl per row) and its final count is
+// read back once every vote of the row is in; then the whole row is cleared.
+__device__ __forceinline__ void stream_rows_big(const FindArgs &A, const float2 *__restrict__ cs, uint32_t row_w, uint32_t dummy_w,
+                                const HitRegs &h, const float2 *xh, int nx, int n_alive, int row0, int rstride,
+                                unsigned long long *sink, int *sink_cnt, int sink_cap, uint32_t *cl, int *clc,
+                                int ncl, int *ovf) {
+    const int lane = lane_id();
+    const uint32_t tm1 = A.min_votes - 1u;
+    bool valid[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) valid[c] = c < h.nch && c * kWave + lane < n_alive;
+    uint4 *r4 = reinterpret_cast<uint4 *>(g_lds + row_w);
+    for (int x = lane; x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
+    if (lane == 0) *clc = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    for (int jb = row0; jb < A.n_theta; jb += rstride * kWave) {
+        const int nr = min(kWave, (A.n_theta - jb + rstride - 1) / rstride);
+        const float2 mine = lane < nr ? cs[jb + rstride * lane] : make_float2(0.0f, 0.0f);
+        for (int i = 0; i < nr; ++i) {
+            const int j = jb + rstride * i;
+            float2 t;
+            t.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
+            t.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+                const uint32_t a = valid[c] ? row_w + (uint32_t)k : dummy_w;
+                const uint32_t old = atomicAdd(&g_lds[a], 1u);
+                if (valid[c] && old == tm1) {
+                    const int slot = atomicAdd(clc, 1);
+                    if (slot < ncl) cl[slot] = (uint32_t)k;
+                }
+            }
+            for (int x = 0; x < nx; ++x) {
+                const int q = x * kWave + lane;
+                const bool v = kChunks * kWave + q < n_alive;
+                const float2 pz = xh[q];
+                const int k = rho_bin(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w);
+                const uint32_t a = v ? row_w + (uint32_t)k : dummy_w;
+                const uint32_t old = atomicAdd(&g_lds[a], 1u);
+                if (v && old == tm1) {
+                    const int slot = atomicAdd(clc, 1);
+                    if (slot < ncl) cl[slot] = (uint32_t)k;
+                }
+            }
+            // every vote of the row is in (a wave's LDS operations are
+            // performed in order): read the final counts of its new hot bins
+            const int ncr = *clc;
+            for (int x = lane; x < min(ncr, ncl); x += kWave) {
+                const uint32_t k = cl[x];
+                const uint32_t cnt = g_lds[row_w + k];
+                const int slot = atomicAdd(sink_cnt, 1);
+                if (slot < sink_cap) sink[slot] = bin_key(cnt, (uint32_t)(j * A.n_rho) + k);
+            }
+            if (ncr > ncl && lane == 0) *ovf = 1;
+            for (int x = lane; x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
+            if (lane == 0) *clc = 0;
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void sweep_big(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
+                          const float2 *xh, int nx, int n_alive, const Slot &S, Shared &sh) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int ncl = 2 * (A.pkeep + A.hcap) / NW;
+    // crossing lists in the peak-key buffer (unused by this path)
+    stream_rows_big(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(L.dummy - L.tile) + threadIdx.x, h, xh, nx,
+                    n_alive, wave, NW, S.hs, &sh.hs_cnt, A.big_hs,
+                    reinterpret_cast<uint32_t *>(L.pbuf) + wave * ncl, &sh.clc[wave], ncl, &sh.big_ovf);
+}
+
+// Peaks of a large event's hot set (in the slot): window test over a hash
+// table in the slot. The peak keys are then ordered by a counting sort on
+// the vote count (histogram, scan and scatter in LDS, into the hash table's
+// memory, free by then), and each count's run by flat index with a bitonic
+// sort in the row buffers (key order: count descending, flat ascending).
+// *keys receives the ordered keys; returns their number, or -1 when a table
+// or list would overflow.
+template <int NT>
+__device__ __forceinline__ int hotset_peaks_big(const FindArgs &A, const Lds &L, const Slot &S, int n_hs,
+                                                Shared &sh, const unsigned long long **keys) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    *keys = S.pk;
+    if (A.peak_mode == 0) {
+        if (threadIdx.x == 0) sh.best = 0ull;
+        __syncthreads();
+        for (int e = threadIdx.x; e < n_hs; e += NT) atomicMax(&sh.best, S.hs[e]);
+        __syncthreads();
+        const unsigned long long best = sh.best;
+        if (threadIdx.x == 0) S.pk[0] = best;
+        sync_global();
+        return best != 0ull ? 1 : 0;
+    }
+    int log2n = 6;
+    while ((1 << log2n) < 2 * n_hs) ++log2n;
+    const int ht = 1 << log2n;
+    if (ht > A.big_ht) return -1;
+    for (int i = threadIdx.x; i < ht; i += NT) S.htk[i] = 0u;
+    if (threadIdx.x == 0) sh.pcnt = 0;
+    sync_global();
+    hash_insert<NT>(S.hs, n_hs, S.htk, S.htc, log2n);
+    sync_global();
+    for (int e = threadIdx.x; e < n_hs; e += NT) {
+        const unsigned long long key = S.hs[e];
+        if (key == 0ull) continue;
+        if (window_peak(A, S.htk, S.htc, log2n, key)) {
+            const int slot = atomicAdd(&sh.pcnt, 1);
+            if (slot < A.big_pk) S.pk[slot] = key;
+        }
+    }
+    sync_global();
+    const int npk = sh.pcnt;
+    if (npk > A.big_pk) return -1;
+    if (npk <= 1) return npk;
+
+    // counting sort on the count (a count never exceeds the alive hits)
+    const int cmax = sh.nalive;
+    int *hist = reinterpret_cast<int *>(L.tile);   // [cmax + 1] counts, then run starts
+    int *cur = hist + (cmax + 1);                  // [cmax + 1] scatter cursors
+    uint32_t *runs = reinterpret_cast<uint32_t *>(L.pbuf);  // (start, length) of runs longer than 1
+    const int max_runs = A.pkeep + A.hcap;
+    for (int i = threadIdx.x; i <= cmax; i += NT) hist[i] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < npk; i += NT) atomicAdd(&hist[(uint32_t)(S.pk[i] >> 32)], 1);
+    __syncthreads();
+    if (wave == 0) {
+        // starts in descending count order
+        int run = 0, nr = 0;
+        for (int top = cmax; top >= 0; top -= kWave) {
+            const int c = top - lane;
+            const int v = c >= 0 ? hist[c] : 0;
+            const int incl = wave_incl_scan(v);
+            const int st = run + incl - v;
+            if (c >= 0) cur[c] = st;
+            const unsigned long long multi = __ballot(v > 1);
+            if (v > 1) {
+                const int r = nr + mbcnt64(multi);
+                if (r < max_runs) {
+                    runs[2 * r] = (uint32_t)st;
+                    runs[2 * r + 1] = (uint32_t)v;
+                }
+            }
+            nr += __popcll(multi);
+            run += __builtin_amdgcn_readlane(incl, kWave - 1);
+        }
+        if (lane == 0) sh.nruns = nr;
+    }
+    __syncthreads();
+    const int nruns = sh.nruns;
+    if (nruns > max_runs) return -1;
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(S.htk);
+    for (int i = threadIdx.x; i < npk; i += NT) {
+        const unsigned long long key = S.pk[i];
+        dst[atomicAdd(&cur[(uint32_t)(key >> 32)], 1)] = key;
+    }
+    sync_global();
+    // each run of equal counts by flat index, in the row buffers
+    unsigned long long *buf = reinterpret_cast<unsigned long long *>(L.tile);
+    for (int r = 0; r < nruns; ++r) {
+        const int st = (int)runs[2 * r];
+        const int len = (int)runs[2 * r + 1];
+        if (len > A.big_sort) return -1;
+        const int cap = next_pow2(len);
+        for (int i = threadIdx.x; i < cap; i += NT) buf[i] = i < len ? dst[st + i] : 0ull;
+        __syncthreads();
+        sort_desc<NT>(buf, cap);
+        for (int i = threadIdx.x; i < len; i += NT) dst[st + i] = buf[i];
+        __syncthreads();
+    }
+    sync_global();
+    (void)NW;
+    *keys = dst;
+    return npk;
 }
 
 // One pass of the histogram over all theta rows for the current alive list.
 // Leaves the peak keys with key <= ceil_key (and > sh.maxdrop) in pbuf.
 template <int NT>
-__device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t b, const Lds &L,
+__device__ __forceinline__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t b, const Lds &L,
                       HitRegs &h, int nbatch, unsigned long long ceil_key, Shared &sh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
@@ -629,7 +915,7 @@ __device__ void sweep(const FindArgs &A, const float2 *__restrict__ cs, int64_t 
 //   pst[p]: 0 open, -1 rejected, > 0 taken with that many hits (bit 24 set
 //   in the round it was taken).  M[p] becomes the taken peak's claimed set.
 template <int NT>
-__device__ void claim_rounds(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
+__device__ __forceinline__ void claim_rounds(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
                              int *owner, int W, int nb, Shared &sh) {
     constexpr int kFresh = 1 << 24;
     const int T = (int)A.min_votes;
@@ -698,7 +984,7 @@ __device__ void claim_rounds(const FindArgs &A, unsigned long long *icl, unsigne
 // The same claims, one peak after another by one wave (events too large for
 // the per-hit table of claim_rounds).  Lane l holds words l, l + 64, ...
 template <int NT>
-__device__ void claim_serial(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst, int W,
+__device__ __forceinline__ void claim_serial(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst, int W,
                              int nb) {
     if (wave_id() != 0) return;
     const int lane = lane_id();
@@ -721,7 +1007,7 @@ __device__ void claim_serial(const FindArgs &A, unsigned long long *icl, unsigne
 }
 
 template <int NT>
-__device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
+__device__ __forceinline__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
                           int npk, Shared &sh) {
     constexpr int NW = NT / kWave;
@@ -732,30 +1018,24 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
     const int64_t cbase = b / (int64_t)A.min_votes;
     const bool rounds = W <= kAssocRoundMaxW;
 
-    // union area: pcs[npk] float2 | icl[W] u64 | owner[64 W] (rounds only)
-    //             | M[pb*W] u64 | rp[pb*W] u32 | pbase[pb] | pst[pb] | elist[pb]
+    // union area: icl[W] u64 | owner[64 W] (rounds only) | per peak of a
+    // pass: M[pb*W] u64 | pcs[pb] float2 | dec[pb] int2 | rp[pb*W] u32
+    //       | pbase[pb] | pst[pb] | elist[pb]
     unsigned char *uni = reinterpret_cast<unsigned char *>(L.tile);
-    float2 *pcs = reinterpret_cast<float2 *>(uni);
-    const int pcs_bytes = (8 * npk + 15) & ~15;
-    unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni + pcs_bytes);
+    unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni);
     int *owner = reinterpret_cast<int *>(icl + W);
-    unsigned long long *M = reinterpret_cast<unsigned long long *>(owner + (rounds ? W * kWave : 0));
+    unsigned long long *M = reinterpret_cast<unsigned long long *>(uni + assoc_fixed_bytes(W));
     // at least one peak per pass: the host sizes uni_bytes for the largest W
-    int pb = (uni_bytes - assoc_fixed_bytes(W, npk)) / assoc_peak_bytes(W);
-    pb = min(pb, A.pkeep + A.hcap);
-    uint32_t *rp = reinterpret_cast<uint32_t *>(M + (size_t)pb * W);
+    int pb = (uni_bytes - assoc_fixed_bytes(W)) / assoc_peak_bytes(W);
+    pb = min(pb, npk);
+    float2 *pcs = reinterpret_cast<float2 *>(M + (size_t)pb * W);
+    int2 *dec = reinterpret_cast<int2 *>(pcs + pb);
+    uint32_t *rp = reinterpret_cast<uint32_t *>(dec + pb);
     int *pbase = reinterpret_cast<int *>(rp + (size_t)pb * W);
     int *pst = pbase + pb;
     int *elist = pst + pb;
 
-    // peak coordinates and their (cos, sin), and the hits claimed by an
-    // earlier pass of this iteration
-    for (int p = threadIdx.x; p < npk; p += NT) {
-        const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p] & 0xffffffffull);
-        const int j = (int)(flat / (uint32_t)A.n_rho);
-        L.dec[p] = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
-        pcs[p] = cs[j];
-    }
+    // the hits claimed by an earlier pass of this iteration
     for (int ch = wave; ch < W; ch += NW) {
         const int q = ch * kWave + lane;
         const bool taken = q < n_alive && A.state[b + A.aidx[b + q]] != -1;
@@ -766,13 +1046,21 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
 
     for (int p0 = 0; p0 < npk; p0 += pb) {
         const int nb = min(pb, npk - p0);
+        // coordinates and (cos, sin) of this pass's peaks
+        for (int p = threadIdx.x; p < nb; p += NT) {
+            const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p0 + p] & 0xffffffffull);
+            const int j = (int)(flat / (uint32_t)A.n_rho);
+            dec[p] = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
+            pcs[p] = cs[j];
+        }
+        __syncthreads();
         // A: match masks
         for (int bt = 0; bt < nbatch; ++bt) {
             if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
             const int qbase = bt * kChunks * kWave + lane;
             for (int p = wave; p < nb; p += NW) {
-                const int kp = L.dec[p0 + p].y;
-                const float2 t = pcs[p0 + p];
+                const int kp = dec[p].y;
+                const float2 t = pcs[p];
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
                     if (c < h.nch) {
@@ -821,7 +1109,7 @@ __device__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int 
         // candidate records and word prefixes of the claimed sets
         for (int ei = threadIdx.x; ei < nemit; ei += NT) {
             const int p = elist[ei];
-            const int2 jk = L.dec[p0 + p];
+            const int2 jk = dec[p];
             hough_candidate cd;
             cd.event = e;
             cd.iter = iter;
@@ -875,16 +1163,17 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     L.tile = reinterpret_cast<uint32_t *>(lds);
     L.hot = reinterpret_cast<uint32_t *>(lds + A.tile_bytes);
     L.pbuf = reinterpret_cast<unsigned long long *>(lds + A.tile_bytes + 4 * A.hcap);
-    L.dec = reinterpret_cast<int2 *>(L.pbuf + (A.pkeep + A.hcap));
-    L.dummy = reinterpret_cast<uint32_t *>(L.dec + (A.pkeep + A.hcap));
+    L.dummy = reinterpret_cast<uint32_t *>(L.pbuf + (A.pkeep + A.hcap));
     L.hs = reinterpret_cast<unsigned long long *>(lds + A.hs_off);
     L.sorted = reinterpret_cast<unsigned long long *>(lds + A.sorted_off);
 
     const int e = blockIdx.x;
     const int wave = wave_id();
     const int lane = lane_id();
-    const int64_t b = A.offsets[e];
-    const int64_t n64 = A.offsets[e + 1] - b;
+    // the event's bounds are uniform: keep them (and every address derived
+    // from them) in scalar registers
+    const int64_t b = uniform64(A.offsets[e]);
+    const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
 
     if (threadIdx.x == 0) {
         int bad = 0;
@@ -962,6 +1251,9 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     bool first = true;
     int n_hs = 0;          // entries of the hot set
     bool hs_valid = false; // the hot set holds every bin >= T of the current histogram
+    bool big = false;      // large event: hot set and peaks in a device-memory slot
+    int slot = -1;
+    int bigs = 0;          // iterations run in the large-event path
     HitRegs h;
     for (;;) {
         if (A.max_iters > 0 && iter >= A.max_iters) break;
@@ -997,45 +1289,105 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
 
         bool any = false;
         bool done = false;
-        if (nbatch == 1 && A.stream_ok && h.safe) {
-            if (first && A.g_hs != nullptr && A.g_flag[e] == 0 && A.g_cnt[e] <= A.hs_cap) {
-                // the first histogram was swept by the split sweep kernel
-                n_hs = A.g_cnt[e];
-                const unsigned long long *src = A.g_hs + (size_t)e * A.hs_cap;
-                for (int i = threadIdx.x; i < n_hs; i += NT) L.hs[i] = src[i];
-                hs_valid = true;
-                ++passes;
-                evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
-                __syncthreads();
-            } else if (hs_valid) {
-                // recount the previous hot set (no histogram sweep)
-                recount<NT>(A, cs, L, h, n_alive, n_hs);
-                ++recounts;
-                evals += (unsigned long long)n_hs * (unsigned long long)(h.nch * kWave);
-                __syncthreads();
+        // an event with more than one register batch of alive hits is large;
+        // it stays large (its hot set lives in its slot)
+        if (nbatch > 1) big = true;
+        // (the LDS-resident hits are read in whole 64-hit chunks)
+        if (A.stream_ok && n_alive <= kChunks * kWave + (A.hs_cap & ~(kWave - 1))) {
+            float2 *xh = reinterpret_cast<float2 *>(L.hs);
+            int nx = 0;
+            bool safe;
+            if (nbatch > 1) {
+                safe = load_big<NT>(A, b, n_alive, h, xh);
+                nx = (n_alive - kChunks * kWave + kWave - 1) / kWave;
             } else {
-                // row-stream sweep; falls back to the tiled sweep below when
-                // more bins reach T than the hot set holds
-                ++passes;
-                if (threadIdx.x == 0) sh.hs_cnt = 0;
-                __syncthreads();
-                stream_sweep<NT>(A, cs, L, h, n_alive, sh);
-                __syncthreads();
-                n_hs = sh.hs_cnt;
-                hs_valid = n_hs <= A.hs_cap;
-                hs_full += hs_valid ? 0 : 1;
-                evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                safe = h.safe;
             }
-            if (hs_valid) {
-                const int npk = hotset_peaks<NT>(A, L, n_hs, sh);
-                if (npk >= 0) {
-                    done = true;
-                    if (npk > 0) {
-                        any = true;
-                        associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh);
-                    }
+            if (safe && !big) {
+                if (first && A.g_hs != nullptr && A.g_flag[e] == 0 && A.g_cnt[e] <= A.hs_cap) {
+                    // the first histogram was swept by the split sweep kernel
+                    n_hs = A.g_cnt[e];
+                    const unsigned long long *src = A.g_hs + (size_t)e * A.hs_cap;
+                    for (int i = threadIdx.x; i < n_hs; i += NT) L.hs[i] = src[i];
+                    hs_valid = true;
+                    ++passes;
+                    evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                    __syncthreads();
+                } else if (hs_valid) {
+                    // recount the previous hot set (no histogram sweep)
+                    recount<NT>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs);
+                    ++recounts;
+                    evals += (unsigned long long)n_hs * (unsigned long long)(h.nch * kWave);
+                    __syncthreads();
                 } else {
+                    // row-stream sweep; a hot set larger than LDS holds
+                    // sends the event to the large-event path below
+                    ++passes;
+                    if (threadIdx.x == 0) sh.hs_cnt = 0;
+                    __syncthreads();
+                    stream_sweep<NT>(A, cs, L, h, n_alive, sh);
+                    __syncthreads();
+                    n_hs = sh.hs_cnt;
+                    hs_valid = n_hs <= A.hs_cap;
+                    hs_full += hs_valid ? 0 : 1;
+                    evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                }
+                if (hs_valid) {
+                    const int npk = hotset_peaks<NT>(A, L, n_hs, sh);
+                    if (npk >= 0) {
+                        done = true;
+                        if (npk > 0) {
+                            any = true;
+                            associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh);
+                        }
+                    }
+                }
+                if (!done) {
+                    // more bins at or above T, or more peaks, than LDS holds
+                    big = true;
                     hs_valid = false;
+                }
+            }
+            if (safe && big && !done) {
+                if (slot < 0) slot = acquire_slot(A, sh);
+                if (slot >= 0) {
+                    const Slot S = slot_ptrs(A, slot);
+                    ++bigs;
+                    if (hs_valid) {
+                        recount<NT>(A, cs, S.hs, h, xh, nx, n_alive, n_hs);
+                        ++recounts;
+                        evals += (unsigned long long)n_hs * (unsigned long long)((h.nch + nx) * kWave);
+                        sync_global();
+                    } else {
+                        ++passes;
+                        if (threadIdx.x == 0) {
+                            sh.hs_cnt = 0;
+                            sh.big_ovf = 0;
+                        }
+                        __syncthreads();
+                        sweep_big<NT>(A, cs, L, h, xh, nx, n_alive, S, sh);
+                        sync_global();
+                        n_hs = sh.hs_cnt;
+                        hs_valid = n_hs <= A.big_hs && sh.big_ovf == 0;
+                        hs_full += hs_valid ? 0 : 1;
+                        evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                    }
+                    if (hs_valid) {
+                        const unsigned long long *pkeys = nullptr;
+                        const int npk = hotset_peaks_big<NT>(A, L, S, n_hs, sh, &pkeys);
+                        if (npk >= 0) {
+                            done = true;
+                            if (npk > 0) {
+                                any = true;
+                                // reloaded here so that the hit registers are
+                                // free during the window test
+                                if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
+                                associate<NT>(A, cs, e, b, iter, L, pkeys, A.hs_off, h, nbatch, npk, sh);
+                            }
+                        } else {
+                            hs_valid = false;
+                        }
+                    }
                 }
             }
         }
@@ -1081,6 +1433,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         ++iter;
         if (sh.ncand == ncand0) break;
     }
+    release_slot(A, slot);
     if (A.g_cnt != nullptr && threadIdx.x == 0) {
         // leave the split-sweep words cleared for the next call
         A.g_cnt[e] = 0;
@@ -1104,7 +1457,8 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             A.counts[HOUGH_COUNT_HOT_SCANS] = sh.n_hotscan;
             A.counts[HOUGH_COUNT_HOTSET_FULL] = hs_full;
             A.counts[HOUGH_COUNT_RECOUNTS] = recounts;
-            for (int i = HOUGH_COUNT_RECOUNTS + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+            A.counts[HOUGH_COUNT_LARGE] = bigs;
+            for (int i = HOUGH_COUNT_LARGE + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
         }
         return;
     }
@@ -1120,6 +1474,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         atomicAdd(&A.stats[6], (unsigned long long)sh.n_hotscan);
         atomicAdd(&A.stats[7], (unsigned long long)hs_full);
         atomicAdd(&A.stats[8], (unsigned long long)recounts);
+        atomicAdd(&A.stats[9], (unsigned long long)bigs);
     }
 }
 
@@ -1244,7 +1599,8 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         A.counts[HOUGH_COUNT_HOT_SCANS] = (long long)A.stats[6];
         A.counts[HOUGH_COUNT_HOTSET_FULL] = (long long)A.stats[7];
         A.counts[HOUGH_COUNT_RECOUNTS] = (long long)A.stats[8];
-        for (int i = HOUGH_COUNT_RECOUNTS + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+        A.counts[HOUGH_COUNT_LARGE] = (long long)A.stats[9];
+        for (int i = HOUGH_COUNT_LARGE + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
         // leave the statistics and error words cleared for the next call
         for (int i = 0; i < kStats; ++i) A.stats[i] = 0ull;
         A.err[0] = 0;
@@ -1313,8 +1669,9 @@ __global__ __launch_bounds__(1024) void k_dump(DumpArgs A, const float2 *__restr
 }  // namespace
 
 int find_lds_extra(int wg_threads, int hcap, int pkeep) {
-    // hot list, peak keys, decoded peaks, one dummy word per thread
-    return 4 * hcap + 8 * (pkeep + hcap) + 8 * (pkeep + hcap) + 4 * wg_threads;
+    // hot list (the large-event sweep's crossing lists), peak keys, one
+    // dummy word per thread
+    return 4 * hcap + 8 * (pkeep + hcap) + 4 * wg_threads;
 }
 
 hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s) {
@@ -1375,6 +1732,19 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
 hipError_t launch_set_offsets(int64_t *offsets, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_set_offsets, dim3(1), dim3(1), 0, s, offsets, n);
     return hipGetLastError();
+}
+
+hipError_t find_blocks_per_cu(int wg_threads, int lds_bytes, int *blocks) {
+    switch (wg_threads) {
+    case 256:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_find<256>, 256, lds_bytes);
+    case 512:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_find<512>, 512, lds_bytes);
+    case 1024:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_find<1024>, 1024, lds_bytes);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t set_find_lds_limit(int wg_threads, int lds_bytes) {

@@ -32,6 +32,11 @@ struct Workspace {
     int64_t *tmp_offsets = nullptr;
     unsigned long long *g_hs = nullptr;
     int32_t *g_cnt = nullptr, *g_flag = nullptr;
+    // large events: one slot per resident finder workgroup
+    unsigned char *pool = nullptr;
+    int32_t *pool_flags = nullptr;
+    int32_t pool_slots = 0;
+    int64_t slot_bytes = 0;
 };
 
 struct Ctx {
@@ -48,6 +53,9 @@ struct Ctx {
     int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
     int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
     int stream_ok = 0, hs_off = 0, sorted_off = 0;
+    int big_hs = 0, big_ht = 0, big_pk = 0;  // per-slot capacities of large events
+    int big_sort = 0;                         // longest equal-count run sorted in LDS
+    int max_resident = 0;                     // finder workgroups resident at once on the device
     double safe_r2 = -1.0;
     int dump_rows = 0, dump_lds = 0;
     Workspace ws;

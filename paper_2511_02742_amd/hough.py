@@ -26,7 +26,7 @@ HOUGH_ERR_DATA = -6
 
 HOUGH_COUNTS = 16
 COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_iters", "passes",
-               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "r13", "r14", "r15")
+               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "r14", "r15")
 
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",

