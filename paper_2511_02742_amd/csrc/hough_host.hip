@@ -167,11 +167,15 @@ hough_status choose_shape(Ctx &c, std::string &why) {
         c.sorted_off = rb + 8 * c.hs_cap;
         // large events: device-memory hot set and hash table, and a peak
         // list the row buffers can sort (a power of two of u64 keys)
-        c.big_hs = 65536;
-        c.big_ht = 131072;
         c.big_pk = 32768;
         c.big_sort = 1;
         while (2 * c.big_sort * 8 <= rb) c.big_sort *= 2;
+        // the banded sweep's row lists (2 w + 1 per wave) after the sorted
+        // peak keys, at least 32 entries each
+        c.roll_off = c.sorted_off;
+        c.roll_bytes = c.tile_bytes - c.roll_off;
+        const int nl = 2 * g.nms_radius + 1;
+        c.big_ok = c.stream_ok && c.roll_bytes >= 4 * nl * (c.wg_threads / 64) * 32 ? 1 : 0;
     }
     // |rho| <= r (1 + 2^-24)^3 for r = sqrt(phi^2 + z^2); a rho at least
     // delta inside [rho_min, rho_max] gives a bin in [0, n_rho) after the
@@ -233,7 +237,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     // large-event slots: no more workgroups than events, nor than fit the
     // device at once, hold one at a time
     const int32_t slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ne, std::max(c.max_resident, 1)));
-    const int64_t slot_bytes = (int64_t)align256(8 * ((size_t)c.big_hs + (size_t)c.big_ht + (size_t)c.big_pk));
+    const int64_t slot_bytes = (int64_t)align256(8 * 2 * (size_t)c.big_pk);
     const size_t o_pflags = take(4 * (size_t)slots);
     const size_t o_pool = take((size_t)slots * (size_t)slot_bytes);
     if (w.base) {
@@ -319,10 +323,11 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     a.pool = w.pool;
     a.pool_flags = w.pool_flags;
     a.pool_slots = w.pool_slots;
-    a.big_hs = c.big_hs;
-    a.big_ht = c.big_ht;
     a.big_pk = c.big_pk;
     a.big_sort = c.big_sort;
+    a.big_ok = c.big_ok;
+    a.roll_off = c.roll_off;
+    a.roll_bytes = c.roll_bytes;
     a.slot_bytes = w.slot_bytes;
     return a;
 }

@@ -61,16 +61,17 @@ struct FindArgs {
     int32_t hs_off;      // LDS byte offsets of the hot set and of the sorted peak keys
     int32_t sorted_off;
     // large events: a workgroup takes one slot of device memory for the
-    // event (hot set, hash table of the window test, peak list); alive hits
-    // beyond the register-resident 512 sit in LDS at hs_off (hs_cap of them)
+    // event (its peak lists); alive hits beyond the register-resident 512 sit
+    // in LDS at hs_off (hs_cap of them)
     unsigned char *pool;     // pool_slots * slot_bytes
     int32_t *pool_flags;     // [pool_slots] 1 = taken (0 between calls)
     int32_t pool_slots;
-    int32_t big_hs;          // hot-set entries per slot
-    int32_t big_ht;          // hash slots per slot (power of two)
-    int32_t big_pk;          // peak entries per slot (<= big_ht)
+    int32_t big_pk;          // peak entries per slot (two lists: found, ordered)
     int32_t big_sort;        // longest run of equal counts the row buffers sort (power of two)
     int64_t slot_bytes;
+    int32_t big_ok;          // the banded large-event sweep fits this shape
+    int32_t roll_off;        // LDS byte offset and size of its per-wave row lists
+    int32_t roll_bytes;
 };
 
 struct DumpArgs {

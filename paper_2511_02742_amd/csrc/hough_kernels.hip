@@ -44,6 +44,7 @@ constexpr int kWave = 64;
 // indexing it keeps LDS addresses 32-bit.
 extern __shared__ __align__(16) uint32_t g_lds[];
 constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
+constexpr int kMaxLists = 5;  // row lists of the banded sweep: 2 w + 1 for w <= 2
 constexpr int kStats = 16;  // workspace statistics words (see k_scan)
 
 __device__ __forceinline__ int wave_id() {
@@ -136,10 +137,10 @@ struct Shared {
     int n_trunc;     // peak-list truncations (diagnostics)
     int n_hotscan;   // hot-list overflow scans (diagnostics)
     int rcnt[2];     // open peaks of the current and the next claim round
-    int clc[16];     // per-wave crossing-list fill of the large-event sweep
-    int big_ovf;     // a large-event sweep lost a crossing (list full)
+    int big_ovf;     // a large-event sweep lost a bin >= T (row list full)
     int slot;        // device-memory slot of a large event, or -1
     int nruns;       // runs of equal counts in a large event's peak list
+    int rollc[16 * kMaxLists];  // fill of each wave's row lists (banded sweep)
 };
 
 // LDS layout of k_find (dynamic part):
@@ -587,18 +588,15 @@ __device__ __forceinline__ void sync_global() {
 }
 
 struct Slot {
-    unsigned long long *hs;   // hot set, big_hs keys
-    uint32_t *htk, *htc;      // hash table, big_ht slots each
-    unsigned long long *pk;   // peak keys, big_pk
+    unsigned long long *pk;   // peak keys in the order found, big_pk
+    unsigned long long *srt;  // the same keys ordered, big_pk
 };
 
 __device__ __forceinline__ Slot slot_ptrs(const FindArgs &A, int s) {
     unsigned char *base = A.pool + (size_t)s * (size_t)A.slot_bytes;
     Slot r;
-    r.hs = reinterpret_cast<unsigned long long *>(base);
-    r.htk = reinterpret_cast<uint32_t *>(r.hs + A.big_hs);
-    r.htc = r.htk + A.big_ht;
-    r.pk = reinterpret_cast<unsigned long long *>(r.htc + A.big_ht);
+    r.pk = reinterpret_cast<unsigned long long *>(base);
+    r.srt = r.pk + A.big_pk;
     return r;
 }
 
@@ -640,130 +638,185 @@ __device__ __forceinline__ bool load_big(const FindArgs &A, int64_t b, int n_ali
     return __syncthreads_and(ok) != 0 && h.safe;
 }
 
-// Row-stream votes of a large event (every hit safe): the 8 register chunks
-// (masked per lane) and nx LDS chunks per row. A bin lifted to T is noted in
-// the wave's crossing list (cl, at most ncl per row) and its final count is
-// read back once every vote of the row is in; then the whole row is cleared.
-__device__ __forceinline__ void stream_rows_big(const FindArgs &A, const float2 *__restrict__ cs, uint32_t row_w, uint32_t dummy_w,
-                                const HitRegs &h, const float2 *xh, int nx, int n_alive, int row0, int rstride,
-                                unsigned long long *sink, int *sink_cnt, int sink_cap, uint32_t *cl, int *clc,
-                                int ncl, int *ovf) {
+// Window test of the bins >= T of row jt against the lists (k << 16 | count)
+// of the bins >= T of rows jt - w .. jt + w (list of row r: roll[r mod nl]).
+// A neighbour below T cannot beat a bin at or above T, so the lists decide.
+__device__ __forceinline__ void band_test(const FindArgs &A, const uint32_t *roll, const int *rc, int nl, int cap,
+                                          int jt, unsigned long long *pk, Shared &sh) {
+    const int lane = lane_id();
+    const int w = A.nms_radius;
+    const int cur = jt % nl;
+    const int nc = min(rc[cur], cap);
+    for (int x0 = 0; x0 < nc; x0 += kWave) {
+        // one bin of row jt per lane; the neighbour lists are read as LDS
+        // broadcasts with uniform trip counts
+        const int x = x0 + lane;
+        const bool act = x < nc;
+        const uint32_t e = act ? roll[cur * cap + x] : 0u;
+        const int k = (int)(e >> 16);
+        const uint32_t c = e & 0xffffu;
+        bool peak = act;
+        for (int dr = -w; dr <= w; ++dr) {
+            const int r = jt + dr;
+            if (r < 0 || r >= A.n_theta) continue;
+            const int li = r % nl;
+            const int n2 = min(rc[li], cap);
+            const uint32_t *l2 = roll + li * cap;
+#pragma unroll 4
+            for (int y = 0; y < n2; ++y) {
+                const uint32_t e2 = l2[y];
+                const int d = (int)(e2 >> 16) - k;
+                const uint32_t c2 = e2 & 0xffffu;
+                const bool near = d >= -w && d <= w && !(dr == 0 && d == 0);
+                // a neighbour with a lower flat index (earlier row, or same
+                // row to the left) wins ties
+                const bool earlier = dr < 0 || (dr == 0 && d < 0);
+                peak = peak && !(near && (c2 > c || (c2 == c && earlier)));
+            }
+        }
+        if (peak) {
+            const int slot = atomicAdd(&sh.pcnt, 1);
+            if (slot < A.big_pk) pk[slot] = bin_key(c, (uint32_t)(jt * A.n_rho + k));
+        }
+    }
+}
+
+// Banded row-stream sweep of a large event with the window test built in.
+// Wave w streams its band of rows [r0, r1) plus w_nms rows on either side
+// (only for their bins >= T). After a row's votes (register chunks and nx
+// LDS chunks, every hit safe) its bins that reached T get their final counts
+// and form the row's list; once row j + w_nms is in, row j is tested against
+// the lists of rows j - w_nms .. j + w_nms. Peak keys go to pk (argmax mode:
+// the largest key to sh.best). Overflowing lists set sh.big_ovf.
+template <int NT>
+__device__ __forceinline__ void band_big(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L,
+                                         const HitRegs &h, const float2 *xh, int nx, int n_alive,
+                                         unsigned long long *pk, Shared &sh) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
     const int lane = lane_id();
     const uint32_t tm1 = A.min_votes - 1u;
+    const int w = A.nms_radius;
+    const int nl = 2 * w + 1;
+    const int cap = A.roll_bytes / (4 * nl * NW);
+    uint32_t *roll = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.tile) + A.roll_off) +
+                     wave * nl * cap;
+    int *rc = &sh.rollc[wave * kMaxLists];
+    const uint32_t row_w = (uint32_t)(wave * A.pitch);
+    const uint32_t dummy_w = (uint32_t)(L.dummy - L.tile) + threadIdx.x;
     bool valid[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) valid[c] = c < h.nch && c * kWave + lane < n_alive;
     uint4 *r4 = reinterpret_cast<uint4 *>(g_lds + row_w);
     for (int x = lane; x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
-    if (lane == 0) *clc = 0;
+    const int bw = (A.n_theta + NW - 1) / NW;
+    const int r0 = wave * bw;
+    const int r1 = min(A.n_theta, r0 + bw);
+    if (r0 >= r1) return;   // more waves than bands (nx <= 56: hot flags fit 64 bits)
+    const int jlo = max(r0 - w, 0);
+    const int jhi = min(r1 + w, A.n_theta);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    for (int jb = row0; jb < A.n_theta; jb += rstride * kWave) {
-        const int nr = min(kWave, (A.n_theta - jb + rstride - 1) / rstride);
-        const float2 mine = lane < nr ? cs[jb + rstride * lane] : make_float2(0.0f, 0.0f);
+    for (int jb = jlo; jb < jhi; jb += kWave) {
+        const int nr = min(kWave, jhi - jb);
+        const float2 mine = lane < nr ? cs[jb + lane] : make_float2(0.0f, 0.0f);
         for (int i = 0; i < nr; ++i) {
-            const int j = jb + rstride * i;
+            const int j = jb + i;
+            uint32_t *lst = roll + (j % nl) * cap;
+            int *lc = &rc[j % nl];
+            if (lane == 0) *lc = 0;
             float2 t;
             t.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
             t.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
+            // the votes of a row stay in flight together: the bins they lift
+            // to T are only flagged here (bit c: register chunk c, bit 8 + x:
+            // LDS chunk x) and collected once the row is done
+            unsigned long long hot = 0ull;
+            {
+                uint32_t olds[kChunks];
 #pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                const uint32_t a = valid[c] ? row_w + (uint32_t)k : dummy_w;
-                const uint32_t old = atomicAdd(&g_lds[a], 1u);
-                if (valid[c] && old == tm1) {
-                    const int slot = atomicAdd(clc, 1);
-                    if (slot < ncl) cl[slot] = (uint32_t)k;
+                for (int c = 0; c < kChunks; ++c) {
+                    const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+                    olds[c] = atomicAdd(&g_lds[valid[c] ? row_w + (uint32_t)k : dummy_w], 1u);
+                }
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) hot |= (unsigned long long)(valid[c] && olds[c] == tm1) << c;
+            }
+            for (int xb = 0; xb < nx; xb += kChunks) {
+                // eight LDS chunks at a time: loads, then votes
+                float2 pz[kChunks];
+                uint32_t olds[kChunks];
+#pragma unroll
+                for (int u = 0; u < kChunks; ++u)
+                    pz[u] = xb + u < nx ? xh[(xb + u) * kWave + lane] : make_float2(0.0f, 0.0f);
+#pragma unroll
+                for (int u = 0; u < kChunks; ++u) {
+                    const bool v = xb + u < nx && kChunks * kWave + (xb + u) * kWave + lane < n_alive;
+                    const int k = rho_bin(pz[u].x, pz[u].y, t.x, t.y, A.rho_min, A.inv_w);
+                    olds[u] = atomicAdd(&g_lds[v ? row_w + (uint32_t)k : dummy_w], 1u);
+                }
+#pragma unroll
+                for (int u = 0; u < kChunks; ++u) {
+                    const bool v = xb + u < nx && kChunks * kWave + (xb + u) * kWave + lane < n_alive;
+                    hot |= (unsigned long long)(v && olds[u] == tm1) << (kChunks + xb + u);
                 }
             }
-            for (int x = 0; x < nx; ++x) {
-                const int q = x * kWave + lane;
-                const bool v = kChunks * kWave + q < n_alive;
-                const float2 pz = xh[q];
-                const int k = rho_bin(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w);
-                const uint32_t a = v ? row_w + (uint32_t)k : dummy_w;
-                const uint32_t old = atomicAdd(&g_lds[a], 1u);
-                if (v && old == tm1) {
-                    const int slot = atomicAdd(clc, 1);
-                    if (slot < ncl) cl[slot] = (uint32_t)k;
+            if (__ballot(hot != 0ull) != 0ull) {
+                while (hot != 0ull) {
+                    const int bit = __ffsll((long long)hot) - 1;
+                    hot &= hot - 1ull;
+                    float ph = 0.0f, zz = 0.0f;
+                    if (bit < kChunks) {
+#pragma unroll
+                        for (int c = 0; c < kChunks; ++c)
+                            if (bit == c) {
+                                ph = h.phi[c];
+                                zz = h.z[c];
+                            }
+                    } else {
+                        const float2 pz = xh[(bit - kChunks) * kWave + lane];
+                        ph = pz.x;
+                        zz = pz.y;
+                    }
+                    const uint32_t k = (uint32_t)rho_bin(ph, zz, t.x, t.y, A.rho_min, A.inv_w);
+                    const int s = atomicAdd(lc, 1);
+                    if (s < cap) lst[s] = k;
                 }
             }
             // every vote of the row is in (a wave's LDS operations are
-            // performed in order): read the final counts of its new hot bins
-            const int ncr = *clc;
-            for (int x = lane; x < min(ncr, ncl); x += kWave) {
-                const uint32_t k = cl[x];
+            // performed in order): final counts of the row's bins >= T
+            const int n = *lc;
+            if (n > cap && lane == 0) sh.big_ovf = 1;
+            for (int x = lane; x < min(n, cap); x += kWave) {
+                const uint32_t k = lst[x];
                 const uint32_t cnt = g_lds[row_w + k];
-                const int slot = atomicAdd(sink_cnt, 1);
-                if (slot < sink_cap) sink[slot] = bin_key(cnt, (uint32_t)(j * A.n_rho) + k);
+                lst[x] = (k << 16) | cnt;
+                if (A.peak_mode == 0) atomicMax(&sh.best, bin_key(cnt, (uint32_t)(j * A.n_rho) + k));
             }
-            if (ncr > ncl && lane == 0) *ovf = 1;
             for (int x = lane; x < A.pitch / 4; x += kWave) r4[x] = make_uint4(0u, 0u, 0u, 0u);
-            if (lane == 0) *clc = 0;
+            const int jt = j - w;
+            if (A.peak_mode == 1 && jt >= r0 && jt < r1) band_test(A, roll, rc, nl, cap, jt, pk, sh);
         }
     }
+    // rows whose window reaches past the last row of the grid
+    if (A.peak_mode == 1)
+        for (int jt = max(r0, jhi - w); jt < r1; ++jt) band_test(A, roll, rc, nl, cap, jt, pk, sh);
 }
 
+// Orders a large event's npk peak keys (in S.pk) by key: a counting sort on
+// the vote count (histogram, scan and scatter in LDS) into S.srt, then each
+// run of equal counts by flat index with a bitonic sort in the row buffers.
+// Returns npk, or -1 when a run is longer than the row buffers sort.
 template <int NT>
-__device__ __forceinline__ void sweep_big(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L, const HitRegs &h,
-                          const float2 *xh, int nx, int n_alive, const Slot &S, Shared &sh) {
-    constexpr int NW = NT / kWave;
-    const int wave = wave_id();
-    const int ncl = 2 * (A.pkeep + A.hcap) / NW;
-    // crossing lists in the peak-key buffer (unused by this path)
-    stream_rows_big(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(L.dummy - L.tile) + threadIdx.x, h, xh, nx,
-                    n_alive, wave, NW, S.hs, &sh.hs_cnt, A.big_hs,
-                    reinterpret_cast<uint32_t *>(L.pbuf) + wave * ncl, &sh.clc[wave], ncl, &sh.big_ovf);
-}
-
-// Peaks of a large event's hot set (in the slot): window test over a hash
-// table in the slot. The peak keys are then ordered by a counting sort on
-// the vote count (histogram, scan and scatter in LDS, into the hash table's
-// memory, free by then), and each count's run by flat index with a bitonic
-// sort in the row buffers (key order: count descending, flat ascending).
-// *keys receives the ordered keys; returns their number, or -1 when a table
-// or list would overflow.
-template <int NT>
-__device__ __forceinline__ int hotset_peaks_big(const FindArgs &A, const Lds &L, const Slot &S, int n_hs,
-                                                Shared &sh, const unsigned long long **keys) {
-    constexpr int NW = NT / kWave;
+__device__ __forceinline__ int order_peaks(const FindArgs &A, const Lds &L, const Slot &S, int npk, Shared &sh) {
     const int wave = wave_id();
     const int lane = lane_id();
-    *keys = S.pk;
-    if (A.peak_mode == 0) {
-        if (threadIdx.x == 0) sh.best = 0ull;
-        __syncthreads();
-        for (int e = threadIdx.x; e < n_hs; e += NT) atomicMax(&sh.best, S.hs[e]);
-        __syncthreads();
-        const unsigned long long best = sh.best;
-        if (threadIdx.x == 0) S.pk[0] = best;
+    if (npk <= 1) {
+        if (npk == 1 && threadIdx.x == 0) S.srt[0] = S.pk[0];
         sync_global();
-        return best != 0ull ? 1 : 0;
+        return npk;
     }
-    int log2n = 6;
-    while ((1 << log2n) < 2 * n_hs) ++log2n;
-    const int ht = 1 << log2n;
-    if (ht > A.big_ht) return -1;
-    for (int i = threadIdx.x; i < ht; i += NT) S.htk[i] = 0u;
-    if (threadIdx.x == 0) sh.pcnt = 0;
-    sync_global();
-    hash_insert<NT>(S.hs, n_hs, S.htk, S.htc, log2n);
-    sync_global();
-    for (int e = threadIdx.x; e < n_hs; e += NT) {
-        const unsigned long long key = S.hs[e];
-        if (key == 0ull) continue;
-        if (window_peak(A, S.htk, S.htc, log2n, key)) {
-            const int slot = atomicAdd(&sh.pcnt, 1);
-            if (slot < A.big_pk) S.pk[slot] = key;
-        }
-    }
-    sync_global();
-    const int npk = sh.pcnt;
-    if (npk > A.big_pk) return -1;
-    if (npk <= 1) return npk;
-
-    // counting sort on the count (a count never exceeds the alive hits)
-    const int cmax = sh.nalive;
-    int *hist = reinterpret_cast<int *>(L.tile);   // [cmax + 1] counts, then run starts
+    const int cmax = sh.nalive;                    // a count never exceeds the alive hits
+    int *hist = reinterpret_cast<int *>(L.tile);   // [cmax + 1]
     int *cur = hist + (cmax + 1);                  // [cmax + 1] scatter cursors
     uint32_t *runs = reinterpret_cast<uint32_t *>(L.pbuf);  // (start, length) of runs longer than 1
     const int max_runs = A.pkeep + A.hcap;
@@ -772,7 +825,7 @@ __device__ __forceinline__ int hotset_peaks_big(const FindArgs &A, const Lds &L,
     for (int i = threadIdx.x; i < npk; i += NT) atomicAdd(&hist[(uint32_t)(S.pk[i] >> 32)], 1);
     __syncthreads();
     if (wave == 0) {
-        // starts in descending count order
+        // run starts in descending count order
         int run = 0, nr = 0;
         for (int top = cmax; top >= 0; top -= kWave) {
             const int c = top - lane;
@@ -796,28 +849,24 @@ __device__ __forceinline__ int hotset_peaks_big(const FindArgs &A, const Lds &L,
     __syncthreads();
     const int nruns = sh.nruns;
     if (nruns > max_runs) return -1;
-    unsigned long long *dst = reinterpret_cast<unsigned long long *>(S.htk);
     for (int i = threadIdx.x; i < npk; i += NT) {
         const unsigned long long key = S.pk[i];
-        dst[atomicAdd(&cur[(uint32_t)(key >> 32)], 1)] = key;
+        S.srt[atomicAdd(&cur[(uint32_t)(key >> 32)], 1)] = key;
     }
     sync_global();
-    // each run of equal counts by flat index, in the row buffers
     unsigned long long *buf = reinterpret_cast<unsigned long long *>(L.tile);
     for (int r = 0; r < nruns; ++r) {
         const int st = (int)runs[2 * r];
         const int len = (int)runs[2 * r + 1];
         if (len > A.big_sort) return -1;
-        const int cap = next_pow2(len);
-        for (int i = threadIdx.x; i < cap; i += NT) buf[i] = i < len ? dst[st + i] : 0ull;
+        const int c2 = next_pow2(len);
+        for (int i = threadIdx.x; i < c2; i += NT) buf[i] = i < len ? S.srt[st + i] : 0ull;
         __syncthreads();
-        sort_desc<NT>(buf, cap);
-        for (int i = threadIdx.x; i < len; i += NT) dst[st + i] = buf[i];
+        sort_desc<NT>(buf, c2);
+        for (int i = threadIdx.x; i < len; i += NT) S.srt[st + i] = buf[i];
         __syncthreads();
     }
     sync_global();
-    (void)NW;
-    *keys = dst;
     return npk;
 }
 
@@ -1009,7 +1058,7 @@ __device__ __forceinline__ void claim_serial(const FindArgs &A, unsigned long lo
 template <int NT>
 __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
-                          int npk, Shared &sh) {
+                          int npk, Shared &sh, const float2 *xh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
@@ -1055,7 +1104,39 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         }
         __syncthreads();
         // A: match masks
-        for (int bt = 0; bt < nbatch; ++bt) {
+        if (xh != nullptr && nbatch > 1) {
+            // the first 512 alive hits in registers, the rest in LDS at xh
+            for (int p = wave; p < nb; p += NW) {
+                const int kp = dec[p].y;
+                const float2 t = pcs[p];
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
+                    const int d = k - kp;
+                    const unsigned long long m = __ballot((d < 0 ? -d : d) <= A.assoc_window);
+                    if (lane == 0) M[(size_t)p * W + c] = m;
+                }
+                for (int xb = 0; xb + kChunks < W; xb += kChunks) {
+                    // eight LDS chunks at a time: loads first
+                    float2 pz[kChunks];
+#pragma unroll
+                    for (int u = 0; u < kChunks; ++u)
+                        pz[u] = xb + u + kChunks < W ? xh[(xb + u) * kWave + lane] : make_float2(0.0f, 0.0f);
+#pragma unroll
+                    for (int u = 0; u < kChunks; ++u) {
+                        if (xb + u + kChunks < W) {
+                            const int k = rho_bin(pz[u].x, pz[u].y, t.x, t.y, A.rho_min, A.inv_w);
+                            const int d = k - kp;
+                            const bool hit = kChunks * kWave + (xb + u) * kWave + lane < n_alive &&
+                                             (d < 0 ? -d : d) <= A.assoc_window;
+                            const unsigned long long m = __ballot(hit);
+                            if (lane == 0) M[(size_t)p * W + kChunks + xb + u] = m;
+                        }
+                    }
+                }
+            }
+        }
+        for (int bt = 0; bt < nbatch && (xh == nullptr || nbatch == 1); ++bt) {
             if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
             const int qbase = bt * kChunks * kWave + lane;
             for (int p = wave; p < nb; p += NW) {
@@ -1292,8 +1373,9 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         // an event with more than one register batch of alive hits is large;
         // it stays large (its hot set lives in its slot)
         if (nbatch > 1) big = true;
-        // (the LDS-resident hits are read in whole 64-hit chunks)
-        if (A.stream_ok && n_alive <= kChunks * kWave + (A.hs_cap & ~(kWave - 1))) {
+        // (the LDS-resident hits are read in whole 64-hit chunks, at most
+        // 56 of them: the banded sweep flags hot votes in 64 bits)
+        if (A.stream_ok && n_alive <= kChunks * kWave + min(A.hs_cap & ~(kWave - 1), 56 * kWave)) {
             float2 *xh = reinterpret_cast<float2 *>(L.hs);
             int nx = 0;
             bool safe;
@@ -1338,7 +1420,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                         done = true;
                         if (npk > 0) {
                             any = true;
-                            associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh);
+                            associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh, nullptr);
                         }
                     }
                 }
@@ -1348,45 +1430,46 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                     hs_valid = false;
                 }
             }
-            if (safe && big && !done) {
+            if (safe && big && !done && A.big_ok && 2 * A.nms_radius + 1 <= kMaxLists) {
                 if (slot < 0) slot = acquire_slot(A, sh);
                 if (slot >= 0) {
+                    // a fresh banded sweep every iteration: with thousands
+                    // of bins >= T, recounting them costs more than a sweep
                     const Slot S = slot_ptrs(A, slot);
                     ++bigs;
-                    if (hs_valid) {
-                        recount<NT>(A, cs, S.hs, h, xh, nx, n_alive, n_hs);
-                        ++recounts;
-                        evals += (unsigned long long)n_hs * (unsigned long long)((h.nch + nx) * kWave);
-                        sync_global();
-                    } else {
-                        ++passes;
-                        if (threadIdx.x == 0) {
-                            sh.hs_cnt = 0;
-                            sh.big_ovf = 0;
-                        }
-                        __syncthreads();
-                        sweep_big<NT>(A, cs, L, h, xh, nx, n_alive, S, sh);
-                        sync_global();
-                        n_hs = sh.hs_cnt;
-                        hs_valid = n_hs <= A.big_hs && sh.big_ovf == 0;
-                        hs_full += hs_valid ? 0 : 1;
-                        evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                    ++passes;
+                    hs_valid = false;
+                    if (threadIdx.x == 0) {
+                        sh.pcnt = 0;
+                        sh.big_ovf = 0;
+                        sh.best = 0ull;
                     }
-                    if (hs_valid) {
-                        const unsigned long long *pkeys = nullptr;
-                        const int npk = hotset_peaks_big<NT>(A, L, S, n_hs, sh, &pkeys);
-                        if (npk >= 0) {
-                            done = true;
-                            if (npk > 0) {
-                                any = true;
-                                // reloaded here so that the hit registers are
-                                // free during the window test
-                                if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
-                                associate<NT>(A, cs, e, b, iter, L, pkeys, A.hs_off, h, nbatch, npk, sh);
-                            }
-                        } else {
-                            hs_valid = false;
+                    __syncthreads();
+                    band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
+                    sync_global();
+                    evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                    int npk = -1;
+                    if (sh.big_ovf == 0) {
+                        if (A.peak_mode == 0) {
+                            const unsigned long long best = sh.best;
+                            if (threadIdx.x == 0) S.srt[0] = best;
+                            sync_global();
+                            npk = best != 0ull ? 1 : 0;
+                        } else if (sh.pcnt <= A.big_pk) {
+                            npk = order_peaks<NT>(A, L, S, sh.pcnt, sh);
                         }
+                    }
+                    if (npk >= 0) {
+                        done = true;
+                        if (npk > 0) {
+                            any = true;
+                            // batch 0 back in registers (the peak ordering
+                            // borrowed them), the rest still in LDS
+                            load_batch(A, b, n_alive, 0, h);
+                            associate<NT>(A, cs, e, b, iter, L, S.srt, A.hs_off, h, nbatch, npk, sh, xh);
+                        }
+                    } else {
+                        ++hs_full;
                     }
                 }
             }
@@ -1424,7 +1507,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             if (npk == 0) break;
             any = true;
             const unsigned long long drop = sh.maxdrop;
-            associate<NT>(A, cs, e, b, iter, L, L.pbuf, A.tile_bytes, h, nbatch, npk, sh);
+            associate<NT>(A, cs, e, b, iter, L, L.pbuf, A.tile_bytes, h, nbatch, npk, sh, nullptr);
             if (drop == 0ull) break;
             ceil_key = drop;
         }

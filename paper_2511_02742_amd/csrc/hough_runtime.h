@@ -53,8 +53,9 @@ struct Ctx {
     int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
     int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
     int stream_ok = 0, hs_off = 0, sorted_off = 0;
-    int big_hs = 0, big_ht = 0, big_pk = 0;  // per-slot capacities of large events
+    int big_pk = 0;                           // peak entries per large-event slot
     int big_sort = 0;                         // longest equal-count run sorted in LDS
+    int big_ok = 0, roll_off = 0, roll_bytes = 0;  // banded large-event sweep
     int max_resident = 0;                     // finder workgroups resident at once on the device
     double safe_r2 = -1.0;
     int dump_rows = 0, dump_lds = 0;
