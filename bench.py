@@ -46,6 +46,10 @@ def main():
     ap.add_argument("--serve-rates", default="20000,50000,100000")
     ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=4096)
+    ap.add_argument("--refit-events", type=int, default=4096,
+                    help="events of the Poisson(20) batch whose candidates the refit leg fits (0: skip it)")
+    ap.add_argument("--refit-oracle", type=int, default=30,
+                    help="pure candidates also fitted by the float64 oracle for the parameter error")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first, as the reference kernel for "
                          "FETCH_SIZE / WRITE_SIZE counter scaling")
@@ -176,6 +180,7 @@ def main():
         log("cpu oracle: %.1f events/s over %d events" % (n_done / tc, n_done))
 
     served = serve_bench(args, f, log) if args.serve_events > 0 else None
+    refit = refit_bench(args, f, log) if args.refit_events > 0 else None
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
@@ -196,6 +201,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "served": served,
+        "refit": refit,
     }
     print(json.dumps(rec), flush=True)
 
@@ -283,6 +289,82 @@ def serve_bench(args, finder, log):
                         "(seeds 2000000..), Poisson arrivals" % P,
             "lanes": args.serve_lanes, "device_bytes": dev_bytes, "mean_hits": round(float(lens.mean()), 1),
             "rates": res}
+
+
+def refit_bench(args, finder, log):
+    """Helix refit of the candidates the finder returns for the uneven batch
+    (Poisson(20) tracks per event, seeds 1000000..): gather, initial fit and
+    20 Gauss-Newton steps on the GPU (timed with HIP events), the parameter
+    error against the float64 oracle on a sample of candidates whose hits all
+    come from one generated track, and the momentum resolution against the
+    generator truth."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2511_02742_amd import eventgen
+    from paper_2511_02742_amd.hough import (REFIT_STEPS, momentum_mev, refit_gather, refit_gauss_newton,
+                                            refit_init)
+
+    b = eventgen.poisson_batch(args.refit_events)
+    dev = torch.device("cuda", 0)
+    t = {k: torch.from_numpy(getattr(b, k)).to(dev) for k in ("r", "z", "vane", "offsets")}
+    out = finder.find(t["z"], t["vane"], t["offsets"])
+    cand, hit_index, info = out.to_host()
+    assert info["status"] == 0
+    hits = refit_gather(out, t["offsets"], t["r"], t["z"], t["vane"])
+    stream = torch.cuda.current_stream(dev)
+    times = []
+    for rep in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        p = refit_init(hits).contiguous()
+        chi2 = refit_gauss_newton(hits, p)
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        if rep > 0:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    status = hits.status.cpu().numpy()
+    P = p.cpu().numpy().astype(np.float64)
+    mom = momentum_mev(p.double()).cpu().numpy()
+    n_cand = len(cand)
+    # purity and truth momentum of each candidate
+    pure = np.zeros(n_cand, bool)
+    ptrue = np.zeros(n_cand)
+    for c, cd in enumerate(cand):
+        ev = b.events[cd["event"]]
+        tr = ev.track[hit_index[cd["hit_offset"]:cd["hit_offset"] + cd["n_hits"]]]
+        if tr[0] >= 0 and np.all(tr == tr[0]):
+            pure[c] = True
+            ptrue[c] = ev.p[tr[0]]
+    fit = (status == 0)
+    sel = fit & pure
+    ratio = mom[sel] / ptrue[sel] - 1.0
+    res = {"workload": "candidates of %d events, Poisson(20) tracks + 1%% noise (seeds 1000000..)" % args.refit_events,
+           "candidates": n_cand, "fitted": int(fit.sum()), "pure_fitted": int(sel.sum()),
+           "steps": REFIT_STEPS, "ms": round(ms, 4), "candidates_per_s": round(n_cand / (ms * 1e-3), 1),
+           "momentum_bias": round(float(np.median(ratio)), 5),
+           "momentum_resolution_68": round(float(np.quantile(np.abs(ratio - np.median(ratio)), 0.68)), 5)}
+    if args.refit_oracle > 0 and not args.no_cpu_baseline:
+        from oracle.refit_oracle import refit_gn, refit_init as o_init
+        floors = np.array([1e-4, 1.0, 1.0, 1.0, 0.01])
+        worst = np.zeros(5)
+        done = 0
+        r_np, z_np, v_np = b.r, b.z, b.vane
+        for c in np.nonzero(sel)[0][:args.refit_oracle]:
+            cd = cand[c]
+            idx = b.offsets[cd["event"]] + hit_index[cd["hit_offset"]:cd["hit_offset"] + cd["n_hits"]]
+            p0, s0, a0 = o_init(r_np[idx], z_np[idx], v_np[idx])
+            po = refit_gn(p0, r_np[idx], z_np[idx], v_np[idx], s0, a0)
+            e = np.abs(P[c] - po) / np.maximum(np.abs(po), floors)
+            e[1] = abs(math.remainder(P[c][1] - po[1], 2 * math.pi))
+            worst = np.maximum(worst, e)
+            done += 1
+        res["oracle_sample"] = done
+        res["max_param_error_vs_f64"] = {k: float("%.3g" % v) for k, v in
+                                         zip(("kappa", "phi0", "d0", "z0", "tan_lambda"), worst)}
+    log("refit: %s" % res)
+    return res
 
 
 if __name__ == "__main__":

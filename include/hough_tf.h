@@ -342,6 +342,61 @@ hough_status hough_server_poll(void *server, int32_t max_results, hough_served *
 hough_status hough_server_drain(void *server, double timeout_s);
 hough_status hough_server_get_stats(const void *server, hough_server_stats *stats);
 
+/*
+ * Helix refit of track candidates (a continuous fit of each candidate's hits;
+ * the paper fits its seeds with a Kalman filter, Sec. 3, and names a GPU fit
+ * as future work). Stateless calls on the caller's stream; every pointer is
+ * device memory; outputs are valid once the stream has been synchronised.
+ *
+ * Hits of candidate c: [hit_offsets[c], hit_offsets[c+1]) of r, z (mm) and
+ * vane (the radial plane at azimuth 2 pi vane / n_vanes). Parameters: float
+ * [n_cand][5] = (kappa, phi0, d0, z0, tan_lambda) in the perigee form: signed
+ * radius 1 / kappa (kappa > 0 turns clockwise seen from +z), centre
+ * (d0 + 1/kappa) (sin phi0, -cos phi0), z = z0 + a tan_lambda / |kappa| at
+ * turning angle a past the perigee (the circle's point nearest the z axis).
+ * Hit i is predicted at the crossing of the circle with its vane's ray (root
+ * hit_sign[i] = +-1) and at the z of that crossing's turning angle, unwrapped
+ * against hit_aref[i]; chi^2 = sum ((r - r_hat)^2 + (z - z_hat)^2) / sigma^2.
+ *
+ * hough_refit_gather: hit arrays of the candidates a find call returned
+ * (cand, hit_index of that call, its event_offsets and hit arrays r, z, vane of
+ * the batch): writes hit_offsets[n_cand + 1] and r_out, z_out, vane_out (one
+ * entry per hit index, in the order of hit_index).
+ * hough_refit_init: initial parameters (float64 arithmetic: an algebraic circle
+ * fit with kappa > 0; turning angles unwrapped along the track, in z order when
+ * the hits' z spread is 1 mm or more, else between the two sides of the largest
+ * angular gap; a straight-line fit of z against the arc length) and each hit's
+ * root (the one nearest its r) and reference turning angle. status[c]: 0 ok,
+ * 1 fewer than 3 hits, 2 more than 128 hits, 3 no helix (hits on fewer than
+ * 3 distinct vanes, or an initial circle of radius above 1e4 mm: a line).
+ * hough_refit_chi2: chi2[c] at params (float32).
+ * hough_refit_grad: grad_params[c] = grad_chi2[c] * d chi2_c / d params_c
+ * (the adjoint; grad_chi2 NULL means 1).
+ * hough_refit_gauss_newton: `steps` Gauss-Newton steps in place: with J the
+ * Jacobian of the residual vector e, H = J^T J, g = J^T e, D = diag(H):
+ * params += -D^-1/2 (D^-1/2 H D^-1/2 + damping I)^-1 D^-1/2 g; candidates with
+ * status != 0 (status may be NULL) are left as they are; chi2 (may be NULL)
+ * receives the final chi^2.
+ * All return HOUGH_ERR_INVALID_ARG for null pointers or bad sizes.
+ */
+hough_status hough_refit_gather(void *stream, int32_t n_cand, const hough_candidate *cand, const int32_t *hit_index,
+                                const int64_t *event_offsets, const float *r, const float *z, const int16_t *vane,
+                                int64_t *hit_offsets, float *r_out, float *z_out, int16_t *vane_out);
+hough_status hough_refit_init(void *stream, int32_t n_cand, const int64_t *hit_offsets, const float *r,
+                              const float *z, const int16_t *vane, int32_t n_vanes, float *params, float *hit_sign,
+                              float *hit_aref, int32_t *status);
+hough_status hough_refit_chi2(void *stream, int32_t n_cand, const int64_t *hit_offsets, const float *r,
+                              const float *z, const int16_t *vane, int32_t n_vanes, const float *hit_sign,
+                              const float *hit_aref, const float *params, float sigma, float *chi2);
+hough_status hough_refit_grad(void *stream, int32_t n_cand, const int64_t *hit_offsets, const float *r,
+                              const float *z, const int16_t *vane, int32_t n_vanes, const float *hit_sign,
+                              const float *hit_aref, const float *params, const float *grad_chi2, float sigma,
+                              float *grad_params);
+hough_status hough_refit_gauss_newton(void *stream, int32_t n_cand, const int64_t *hit_offsets, const float *r,
+                                      const float *z, const int16_t *vane, int32_t n_vanes, const float *hit_sign,
+                                      const float *hit_aref, const int32_t *status, float *params, int32_t steps,
+                                      float damping, float sigma, float *chi2);
+
 const char *hough_status_string(hough_status st);
 /* Detail of the last failing call on ctx (empty string if none). */
 const char *hough_last_error(const void *ctx);

@@ -51,6 +51,7 @@ MEV_PER_T_MM = 0.299792458      # pT[MeV/c] = 0.299792458 * B[T] * R[mm]
 GN_STEPS = 20
 GN_DAMPING = 1e-3
 Z_ORDER_MM = 1.0                 # z spread above which the hits are unwrapped in z order
+R_MAX_MM = 1.0e4                 # larger initial circles are lines, not helices (p > 9 GeV/c at 3 T)
 
 
 def vane_dirs(vane, n_vanes: int = N_VANES):
@@ -88,7 +89,11 @@ def unwrap_turning(alpha, z):
 
 def refit_init(r, z, vane, n_vanes: int = N_VANES):
     """(params (5,), root sign s (n,), reference turning angle a_ref (n,))
-    from the measured hits of one candidate, in float64."""
+    from the measured hits of one candidate, in float64; params is None for a
+    candidate no helix is fitted to (fewer than 3 hits or 3 distinct vanes,
+    or a circle of radius above R_MAX_MM: hits along a line, not a helix)."""
+    if len(r) < 3 or len(set(np.asarray(vane).tolist())) < 3:
+        return None, np.ones(len(r)), np.zeros(len(r))
     r = np.asarray(r, np.float64)
     z = np.asarray(z, np.float64)
     ux, uy = vane_dirs(vane, n_vanes)
@@ -102,9 +107,12 @@ def refit_init(r, z, vane, n_vanes: int = N_VANES):
     rhs = -np.array([np.dot(u, w), np.dot(v, w), w.sum()])
     D, E, F = np.linalg.solve(A, rhs)
     cx, cy = xm - D / 2.0, ym - E / 2.0
-    R = math.sqrt(D * D / 4.0 + E * E / 4.0 - F)
-    kappa = 1.0 / R
+    R2 = D * D / 4.0 + E * E / 4.0 - F
     cn = math.hypot(cx, cy)
+    if not (R2 > 0.0) or not (cn > 0.0) or math.sqrt(R2) > R_MAX_MM:
+        return None, np.ones(len(r)), np.zeros(len(r))
+    R = math.sqrt(R2)
+    kappa = 1.0 / R
     nx, ny = cx / cn, cy / cn
     d0 = cn - R
     phi0 = math.atan2(nx, -ny)
@@ -179,13 +187,19 @@ def refit_gn(p0, r, z, vane, sign, aref, steps: int = GN_STEPS, mu: float = GN_D
         d = np.where(d > 0.0, d, 1.0)
         Hs = H / np.outer(d, d) + mu * np.eye(5)
         y = np.linalg.solve(Hs, -g / d)
-        p = p + y / d
+        q = p + y / d
+        if not np.all(np.isfinite(q)):
+            break
+        p = q
     return p
 
 
 def refit_candidate(r, z, vane, steps: int = GN_STEPS):
-    """(initial params, fitted params, sign, aref) of one candidate."""
+    """(initial params, fitted params, sign, aref) of one candidate (params
+    None when no helix is fitted)."""
     p0, sign, aref = refit_init(r, z, vane)
+    if p0 is None:
+        return None, None, sign, aref
     return p0, refit_gn(p0, r, z, vane, sign, aref, steps), sign, aref
 
 

@@ -33,7 +33,8 @@ EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_outpu
            "hough_timing", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
            "hough_autotune", "hough_server_create", "hough_server_destroy", "hough_server_clock",
            "hough_server_submit", "hough_server_poll", "hough_server_drain", "hough_server_get_stats",
-           "hough_status_string", "hough_last_error")
+           "hough_refit_gather", "hough_refit_init", "hough_refit_chi2", "hough_refit_grad",
+           "hough_refit_gauss_newton", "hough_status_string", "hough_last_error")
 
 cand_dtype = np.dtype([("event", "<i4"), ("iter", "<i4"), ("theta_bin", "<i4"), ("rho_bin", "<i4"),
                        ("peak_votes", "<u4"), ("n_hits", "<u4"), ("hit_offset", "<i8"),
@@ -137,6 +138,17 @@ def load_library(path: str = LIB_PATH):
     lib.hough_server_drain.restype = st
     lib.hough_server_get_stats.argtypes = [P, P]
     lib.hough_server_get_stats.restype = st
+    F = ctypes.c_float
+    lib.hough_refit_gather.argtypes = [P, I32, P, P, P, P, P, P, P, P, P, P]
+    lib.hough_refit_gather.restype = st
+    lib.hough_refit_init.argtypes = [P, I32, P, P, P, P, I32, P, P, P, P]
+    lib.hough_refit_init.restype = st
+    lib.hough_refit_chi2.argtypes = [P, I32, P, P, P, P, I32, P, P, P, F, P]
+    lib.hough_refit_chi2.restype = st
+    lib.hough_refit_grad.argtypes = [P, I32, P, P, P, P, I32, P, P, P, P, F, P]
+    lib.hough_refit_grad.restype = st
+    lib.hough_refit_gauss_newton.argtypes = [P, I32, P, P, P, P, I32, P, P, P, P, I32, F, F, P]
+    lib.hough_refit_gauss_newton.restype = st
     lib.hough_status_string.argtypes = [ctypes.c_int]
     lib.hough_status_string.restype = ctypes.c_char_p
     lib.hough_last_error.argtypes = [P]
@@ -523,3 +535,158 @@ class HoughServer:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Helix refit (hough_refit_* in the C ABI)
+# ---------------------------------------------------------------------------
+
+REFIT_SIGMA_MM = 0.055
+REFIT_STEPS = 20
+REFIT_DAMPING = 1e-3
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(st, what):
+    if st != HOUGH_OK:
+        raise HoughError(st, what)
+
+
+@dataclasses.dataclass
+class RefitHits:
+    """Device arrays of the candidates' hits (CSR) and the per-hit state the
+    initial fit sets (root sign and reference turning angle)."""
+    offsets: "object"     # int64 [n_cand + 1]
+    r: "object"           # float32 [n_hits]
+    z: "object"
+    vane: "object"        # int16
+    n_vanes: int = 40
+    sign: "object" = None
+    aref: "object" = None
+    status: "object" = None
+
+    @property
+    def n_cand(self) -> int:
+        return int(self.offsets.numel()) - 1
+
+
+def refit_gather(out: "FindOutput", offsets, r, z, vane, stream=None, n_vanes: int = 40) -> RefitHits:
+    """The hits of the candidates in a find call's output (device tensors of
+    the same batch) as a RefitHits."""
+    import torch
+    lib = load_library()
+    cnt = out.counts.cpu().numpy()
+    n_cand, n_hit = int(cnt[0]), int(cnt[1])
+    dev = z.device
+    off = torch.empty(n_cand + 1, dtype=torch.int64, device=dev)
+    ro = torch.empty(max(n_hit, 1), dtype=torch.float32, device=dev)
+    zo = torch.empty_like(ro)
+    vo = torch.empty(max(n_hit, 1), dtype=torch.int16, device=dev)
+    s = _stream_ptr(stream, dev)
+    _check(lib.hough_refit_gather(s, n_cand, _ptr(out.cand), _ptr(out.hit_index), _ptr(offsets), _ptr(r), _ptr(z),
+                                  _ptr(vane), _ptr(off), _ptr(ro), _ptr(zo), _ptr(vo)), "hough_refit_gather")
+    return RefitHits(off, ro[:n_hit], zo[:n_hit], vo[:n_hit], n_vanes)
+
+
+def _stream_ptr(stream, dev):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def refit_init(h: RefitHits, stream=None):
+    """Initial parameters (float32 [n_cand, 5]); sets h.sign, h.aref, h.status."""
+    import torch
+    lib = load_library()
+    dev = h.r.device
+    n = h.n_cand
+    params = torch.zeros((max(n, 1), 5), dtype=torch.float32, device=dev)
+    h.sign = torch.empty(max(h.r.numel(), 1), dtype=torch.float32, device=dev)
+    h.aref = torch.empty_like(h.sign)
+    h.status = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    _check(lib.hough_refit_init(_stream_ptr(stream, dev), n, _ptr(h.offsets), _ptr(h.r), _ptr(h.z), _ptr(h.vane),
+                                h.n_vanes, _ptr(params), _ptr(h.sign), _ptr(h.aref), _ptr(h.status)),
+           "hough_refit_init")
+    return params[:n]
+
+
+def refit_chi2(h: RefitHits, params, sigma: float = REFIT_SIGMA_MM, stream=None):
+    import torch
+    lib = load_library()
+    params = params.contiguous()
+    chi2 = torch.empty(max(h.n_cand, 1), dtype=torch.float32, device=params.device)
+    _check(lib.hough_refit_chi2(_stream_ptr(stream, params.device), h.n_cand, _ptr(h.offsets), _ptr(h.r), _ptr(h.z),
+                                _ptr(h.vane), h.n_vanes, _ptr(h.sign), _ptr(h.aref), _ptr(params), sigma,
+                                _ptr(chi2)), "hough_refit_chi2")
+    return chi2[:h.n_cand]
+
+
+def refit_grad(h: RefitHits, params, grad_chi2=None, sigma: float = REFIT_SIGMA_MM, stream=None):
+    import torch
+    lib = load_library()
+    params = params.contiguous()
+    g = torch.empty_like(params)
+    if grad_chi2 is not None:
+        grad_chi2 = grad_chi2.contiguous().to(torch.float32)
+    _check(lib.hough_refit_grad(_stream_ptr(stream, params.device), h.n_cand, _ptr(h.offsets), _ptr(h.r), _ptr(h.z),
+                                _ptr(h.vane), h.n_vanes, _ptr(h.sign), _ptr(h.aref), _ptr(params),
+                                _ptr(grad_chi2), sigma, _ptr(g)), "hough_refit_grad")
+    return g
+
+
+def refit_gauss_newton(h: RefitHits, params, steps: int = REFIT_STEPS, damping: float = REFIT_DAMPING,
+                       sigma: float = REFIT_SIGMA_MM, stream=None):
+    """Gauss-Newton steps on params in place; returns the final chi^2."""
+    import torch
+    lib = load_library()
+    assert params.is_contiguous() and params.dtype == torch.float32
+    chi2 = torch.empty(max(h.n_cand, 1), dtype=torch.float32, device=params.device)
+    _check(lib.hough_refit_gauss_newton(_stream_ptr(stream, params.device), h.n_cand, _ptr(h.offsets), _ptr(h.r),
+                                        _ptr(h.z), _ptr(h.vane), h.n_vanes, _ptr(h.sign), _ptr(h.aref),
+                                        _ptr(h.status), _ptr(params), steps, damping, sigma, _ptr(chi2)),
+           "hough_refit_gauss_newton")
+    return chi2[:h.n_cand]
+
+
+def _autograd_function():
+    import torch
+
+    class HelixChi2(torch.autograd.Function):
+        """chi^2 per candidate as a differentiable function of the helix
+        parameters: forward by the chi^2 kernel, backward by the hand-written
+        adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, params, hits: RefitHits, sigma: float = REFIT_SIGMA_MM):
+            params = params.detach().contiguous()
+            ctx.hits = hits
+            ctx.sigma = sigma
+            ctx.save_for_backward(params)
+            return refit_chi2(hits, params, sigma)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (params,) = ctx.saved_tensors
+            return refit_grad(ctx.hits, params, grad_out, ctx.sigma), None, None
+
+    return HelixChi2
+
+
+_HELIX_CHI2 = None
+
+
+def helix_chi2(params, hits: RefitHits, sigma: float = REFIT_SIGMA_MM):
+    """Differentiable chi^2 per candidate (torch.autograd.Function)."""
+    global _HELIX_CHI2
+    if _HELIX_CHI2 is None:
+        _HELIX_CHI2 = _autograd_function()
+    return _HELIX_CHI2.apply(params, hits, sigma)
+
+
+def momentum_mev(params, b_tesla: float = 3.0):
+    """|p| in MeV/c from fitted parameters (tensor [n, 5])."""
+    pt = 0.299792458 * b_tesla / params[:, 0].abs()
+    return pt * (1.0 + params[:, 4] * params[:, 4]).sqrt()

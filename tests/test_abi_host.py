@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "hough_tf.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hough_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hough_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -176,3 +176,18 @@ def test_kernels_keep_scratch_out_of_their_loops(tmp_path):
                 assert depth <= 1, (m.group(1), line.strip(), depth)
         assert deepest >= 3, (m.group(1), deepest)   # the vote loops were seen
     assert kernels == 3
+
+
+def test_refit_calls_reject_bad_arguments_without_a_device():
+    from paper_2511_02742_amd import hough
+    lib = hough.load_library()
+    E = hough.HOUGH_ERR_INVALID_ARG
+    assert lib.hough_refit_init(None, -1, None, None, None, None, 40, None, None, None, None) == E
+    assert lib.hough_refit_init(None, 1, None, None, None, None, 40, None, None, None, None) == E
+    assert lib.hough_refit_chi2(None, 0, None, None, None, None, 40, None, None, None, 0.0, None) == E
+    assert lib.hough_refit_grad(None, 2, None, None, None, None, 0, None, None, None, None, 0.055, None) == E
+    assert lib.hough_refit_gauss_newton(None, 0, None, None, None, None, 40, None, None, None, None, -1, 1e-3,
+                                        0.055, None) == E
+    assert lib.hough_refit_gather(None, 1, None, None, None, None, None, None, None, None, None, None) == E
+    # nothing to do is not an error
+    assert lib.hough_refit_chi2(None, 0, None, None, None, None, 40, None, None, None, 0.055, None) == 0
