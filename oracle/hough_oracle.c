@@ -41,6 +41,18 @@
  *   - an event stops when no peak reaches T, when an iteration emits
  *     nothing, or after max_iters iterations (0 = no cap).
  *
+ * Coarse-to-fine mode (peak_mode 2; Sec. 6 and Fig. 2: the paper fills an
+ * 18 x 100 coarse histogram and then a 10 x 10 fine one inside the most
+ * likely coarse region, to fit GPU shared memory):
+ *   - the coarse grid has n_theta / coarse_theta x n_rho / coarse_rho bins
+ *     over the same ranges; a hit votes at the coarse theta bin centres
+ *     with the same bin formula (its own cos/sin and inv_w);
+ *   - the fine histogram is the full n_theta x n_rho histogram restricted
+ *     to the coarse_theta x coarse_rho block under the coarse bin with the
+ *     largest key; its largest key is the iteration's one peak, kept when it
+ *     reaches T (otherwise the event stops); association and removal as in
+ *     argmax mode. This peak need not be the full histogram's maximum.
+ *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no -ffast-math, no OpenMP).
  */
 #include <math.h>
@@ -63,10 +75,12 @@ typedef struct {
     int32_t n_vanes;
     int32_t phi_unit;       /* 0 = degrees, 1 = radians */
     uint32_t min_votes;     /* T */
-    int32_t peak_mode;      /* 0 = argmax, 1 = nms */
+    int32_t peak_mode;      /* 0 = argmax, 1 = nms, 2 = coarse-to-fine */
     int32_t nms_radius;     /* w */
     int32_t assoc_window;   /* a */
     int32_t max_iters;      /* 0 = unlimited */
+    int32_t coarse_theta;   /* peak_mode 2: fine theta bins per coarse bin */
+    int32_t coarse_rho;     /* peak_mode 2: fine rho bins per coarse bin */
 } orc_config;
 
 typedef struct {            /* 40 bytes */
@@ -89,7 +103,11 @@ static int orc_check_config(const orc_config *c)
     if (c->n_vanes < 1 || c->n_vanes > 32767) return ORC_ERR_ARG;
     if (c->phi_unit != 0 && c->phi_unit != 1) return ORC_ERR_ARG;
     if (c->min_votes < 1) return ORC_ERR_ARG;
-    if (c->peak_mode != 0 && c->peak_mode != 1) return ORC_ERR_ARG;
+    if (c->peak_mode < 0 || c->peak_mode > 2) return ORC_ERR_ARG;
+    if (c->peak_mode == 2) {
+        if (c->coarse_theta < 1 || c->coarse_rho < 1) return ORC_ERR_ARG;
+        if (c->n_theta % c->coarse_theta || c->n_rho % c->coarse_rho) return ORC_ERR_ARG;
+    }
     if (c->nms_radius < 0 || c->nms_radius > 16) return ORC_ERR_ARG;
     if (c->assoc_window < 0) return ORC_ERR_ARG;
     if (c->max_iters < 0) return ORC_ERR_ARG;
@@ -265,6 +283,84 @@ int64_t orc_peaks(const orc_config *c, const uint32_t *acc, uint64_t *keys, int6
     return np;
 }
 
+/* Coarse grid of the coarse-to-fine mode: theta sampled at the coarse bin
+ * centres, its own inv_w. */
+typedef struct {
+    float *cos_t, *sin_t;
+    float inv_w;
+    int32_t n_theta, n_rho;
+} orc_ctabs;
+
+static int orc_ctabs_make(const orc_config *c, orc_ctabs *t)
+{
+    const double pi = 3.14159265358979323846;
+    t->n_theta = c->n_theta / c->coarse_theta;
+    t->n_rho = c->n_rho / c->coarse_rho;
+    t->cos_t = malloc(sizeof(float) * t->n_theta);
+    t->sin_t = malloc(sizeof(float) * t->n_theta);
+    if (!t->cos_t || !t->sin_t) return ORC_ERR_OOM;
+    for (int j = 0; j < t->n_theta; ++j) {
+        double th = (j + 0.5) * pi / (double)t->n_theta;
+        t->cos_t[j] = (float)cos(th);
+        t->sin_t[j] = (float)sin(th);
+    }
+    t->inv_w = (float)((double)t->n_rho / ((double)c->rho_max - (double)c->rho_min));
+    return ORC_OK;
+}
+
+static void orc_ctabs_free(orc_ctabs *t)
+{
+    free(t->cos_t); free(t->sin_t);
+}
+
+/* One coarse-to-fine peak of the alive hits: the coarse histogram (in acc),
+ * its largest key, the fine histogram of the block under it, and that
+ * block's largest key (in keys[0]) if it reaches T. Returns 1 or 0. */
+static int64_t orc_coarse_fine_peak(const orc_config *c, const orc_tabs *t, const orc_ctabs *ct, int64_t n,
+                                    const float *z, const int16_t *vane, const uint8_t *alive, uint32_t *acc,
+                                    uint64_t *keys)
+{
+    const int64_t ncb = (int64_t)ct->n_theta * ct->n_rho;
+    memset(acc, 0, sizeof(uint32_t) * (size_t)ncb);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!alive[i]) continue;
+        float phi = t->phi_v[vane[i]];
+        for (int32_t J = 0; J < ct->n_theta; ++J) {
+            int32_t K = orc_bin(phi, z[i], ct->cos_t[J], ct->sin_t[J], c->rho_min, ct->inv_w);
+            if (K >= 0 && K < ct->n_rho) acc[(int64_t)J * ct->n_rho + K] += 1;
+        }
+    }
+    uint64_t best = 0;
+    for (int64_t b = 0; b < ncb; ++b) {
+        uint64_t key = orc_key(acc[b], (uint32_t)b);
+        if (key > best) best = key;
+    }
+    uint32_t bflat = 0xffffffffu - (uint32_t)(best & 0xffffffffu);
+    int32_t J = (int32_t)(bflat / (uint32_t)ct->n_rho), K = (int32_t)(bflat % (uint32_t)ct->n_rho);
+    int32_t j0 = J * c->coarse_theta, k0 = K * c->coarse_rho;
+    /* fine histogram of the block (rows j0.., bins k0..) */
+    uint32_t *fine = acc;
+    memset(fine, 0, sizeof(uint32_t) * (size_t)c->coarse_theta * c->coarse_rho);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!alive[i]) continue;
+        float phi = t->phi_v[vane[i]];
+        for (int32_t j = j0; j < j0 + c->coarse_theta; ++j) {
+            int32_t k = orc_bin(phi, z[i], t->cos_t[j], t->sin_t[j], c->rho_min, t->inv_w);
+            if (k >= k0 && k < k0 + c->coarse_rho) fine[(int64_t)(j - j0) * c->coarse_rho + (k - k0)] += 1;
+        }
+    }
+    uint64_t peak = 0;
+    for (int32_t dj = 0; dj < c->coarse_theta; ++dj)
+        for (int32_t dk = 0; dk < c->coarse_rho; ++dk) {
+            uint64_t key = orc_key(fine[(int64_t)dj * c->coarse_rho + dk],
+                                   (uint32_t)((j0 + dj) * c->n_rho + (k0 + dk)));
+            if (key > peak) peak = key;
+        }
+    if ((uint32_t)(peak >> 32) < c->min_votes) return 0;
+    keys[0] = peak;
+    return 1;
+}
+
 /* The full find-and-remove loop on one event.
  *   cand / hit_index receive the candidates (emission order) and their hits
  *   (ascending event-local indices); claim (optional, n entries) receives
@@ -282,13 +378,18 @@ int orc_find(const orc_config *c, int32_t event_id, int64_t n, const float *z, c
     orc_tabs t;
     st = orc_tabs_make(c, &t);
     if (st) { orc_tabs_free(&t); return st; }
+    orc_ctabs ct = {0};
+    if (c->peak_mode == 2) {
+        st = orc_ctabs_make(c, &ct);
+        if (st) { orc_ctabs_free(&ct); orc_tabs_free(&t); return st; }
+    }
     const int64_t nbins = (int64_t)c->n_theta * c->n_rho;
     uint32_t *acc = malloc(sizeof(uint32_t) * (size_t)nbins);
     uint8_t *alive = malloc((size_t)(n > 0 ? n : 1));
     int32_t *owner = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     uint64_t *keys = malloc(sizeof(uint64_t) * (size_t)nbins);
     if (!acc || !alive || !owner || !keys) {
-        free(acc); free(alive); free(owner); free(keys); orc_tabs_free(&t);
+        free(acc); free(alive); free(owner); free(keys); orc_ctabs_free(&ct); orc_tabs_free(&t);
         return ORC_ERR_OOM;
     }
     for (int64_t i = 0; i < n; ++i) { alive[i] = 1; owner[i] = -1; }
@@ -301,10 +402,15 @@ int orc_find(const orc_config *c, int32_t event_id, int64_t n, const float *z, c
         for (int64_t i = 0; i < n; ++i) n_alive += alive[i];
         /* no bin can reach T with fewer than T hits: the fill is skipped */
         if (n_alive < (int64_t)c->min_votes) break;
-        votes += n_alive * c->n_theta;
-        /* rebuild the histogram from the hits still in the pool */
+        if (c->peak_mode == 2) {
+            votes += n_alive * (c->n_theta / c->coarse_theta + c->coarse_theta);
+        } else {
+            votes += n_alive * c->n_theta;
+        }
+        /* rebuild the histogram from the hits still in the pool (the
+         * coarse-to-fine mode fills its own two histograms) */
         memset(acc, 0, sizeof(uint32_t) * (size_t)nbins);
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t i = 0; i < n && c->peak_mode != 2; ++i) {
             if (!alive[i]) continue;
             float phi = t.phi_v[vane[i]];
             for (int32_t j = 0; j < c->n_theta; ++j) {
@@ -312,7 +418,12 @@ int orc_find(const orc_config *c, int32_t event_id, int64_t n, const float *z, c
                 if (k >= 0 && k < c->n_rho) acc[(int64_t)j * c->n_rho + k] += 1;
             }
         }
-        int64_t np = orc_peaks(c, acc, keys, nbins);
+        int64_t np;
+        if (c->peak_mode == 2) {
+            np = orc_coarse_fine_peak(c, &t, &ct, n, z, vane, alive, acc, keys);
+        } else {
+            np = orc_peaks(c, acc, keys, nbins);
+        }
         if (np < 0) { st = (int)np; break; }
         if (np == 0) break;
         int emitted = 0;
@@ -369,6 +480,7 @@ int orc_find(const orc_config *c, int32_t event_id, int64_t n, const float *z, c
     if (claim)
         for (int64_t i = 0; i < n; ++i) claim[i] = owner[i];
     free(acc); free(alive); free(owner); free(keys);
+    orc_ctabs_free(&ct);
     orc_tabs_free(&t);
     return st;
 }

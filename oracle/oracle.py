@@ -31,7 +31,8 @@ class _CConfig(ctypes.Structure):
                 ("n_vanes", ctypes.c_int32), ("phi_unit", ctypes.c_int32),
                 ("min_votes", ctypes.c_uint32), ("peak_mode", ctypes.c_int32),
                 ("nms_radius", ctypes.c_int32), ("assoc_window", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32)]
+                ("max_iters", ctypes.c_int32), ("coarse_theta", ctypes.c_int32),
+                ("coarse_rho", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
@@ -43,15 +44,17 @@ class OracleConfig:
     n_vanes: int = 40
     phi_unit: int = 0          # 0 degrees, 1 radians
     min_votes: int = 6
-    peak_mode: int = 1         # 0 argmax, 1 nms
+    peak_mode: int = 1         # 0 argmax, 1 nms, 2 coarse-to-fine
     nms_radius: int = 1
     assoc_window: int = 0
     max_iters: int = 0
+    coarse_theta: int = 10     # peak_mode 2: fine bins per coarse bin
+    coarse_rho: int = 10
 
     def c(self) -> _CConfig:
         return _CConfig(self.n_theta, self.n_rho, self.rho_min, self.rho_max, self.n_vanes,
                         self.phi_unit, self.min_votes, self.peak_mode, self.nms_radius,
-                        self.assoc_window, self.max_iters)
+                        self.assoc_window, self.max_iters, self.coarse_theta, self.coarse_rho)
 
 
 def build_oracle(force: bool = True) -> str:
