@@ -64,6 +64,23 @@ typedef enum {
  *
  * Bins are ordered by the 64-bit key (count << 32) | (2^32 - 1 - flat),
  * flat = j * n_rho + k: higher count first, then lower flat index.
+ *
+ * Coarse-to-fine mode (peak_mode 2; Sec. 6 and Fig. 2: an 18 x 100 coarse
+ * histogram, then a 10 x 10 fine one inside its most likely region). Per
+ * iteration the alive hits fill a coarse histogram of
+ * (n_theta / coarse_theta) x (n_rho / coarse_rho) bins over the same ranges,
+ * theta sampled at the coarse bin centres (tables built the same way, with
+ * inv_w = float(coarse n_rho / (rho_max - rho_min))); the coarse bin J, K
+ * with the largest key selects the block of full-grid bins j in
+ * [J coarse_theta, (J+1) coarse_theta), k in [K coarse_rho, (K+1) coarse_rho);
+ * the alive hits fill that block with the full-grid bin formula and its
+ * largest key (full-grid flat index) is the iteration's one peak, kept if its
+ * count reaches T (else the event stops). Association and removal are those
+ * of argmax mode. The peak need not be the full histogram's maximum.
+ * coarse_theta and coarse_rho must divide n_theta and n_rho (0 selects 10);
+ * both histograms together must fit 16384 counts (64 KiB of LDS). In modes 0
+ * and 1 both fields must be 0. Mode 2 ignores nms_radius, tile_rows and the
+ * split sweep; wg_threads sets its workgroup (0 = 256).
  */
 typedef struct {
     int32_t  n_theta;        /* theta bins, 1..65536                         */
@@ -74,7 +91,8 @@ typedef struct {
     int32_t  phi_unit;       /* 0 = degrees, 1 = radians                     */
     uint32_t min_votes;      /* T: smallest peak count and candidate size    */
     int32_t  peak_mode;      /* 0 = argmax (one global maximum per pass),
-                                1 = nms (every local maximum)                */
+                                1 = nms (every local maximum),
+                                2 = coarse-to-fine (see below)               */
     int32_t  nms_radius;     /* w: window half-width for nms, 0..16          */
     int32_t  assoc_window;   /* a: a hit joins peak (j,k) if |k_i(j)-k| <= a */
     int32_t  max_iters;      /* iteration cap per event, 0 = none            */
@@ -85,7 +103,8 @@ typedef struct {
                                 sweep, run as a separate kernel; 0 = the
                                 finder's own workgroup sweeps               */
     int32_t  sweep_threads;  /* threads per sweep workgroup (256/512/1024)  */
-    int32_t  reserved[2];    /* must be 0                                    */
+    int32_t  coarse_theta;   /* peak_mode 2: fine theta bins per coarse bin  */
+    int32_t  coarse_rho;     /* peak_mode 2: fine rho bins per coarse bin    */
 } hough_config;
 
 /*
@@ -121,7 +140,9 @@ typedef struct {
 #define HOUGH_COUNT_HOTSET_FULL 11 /* row-stream sweeps whose hot set overflowed */
 #define HOUGH_COUNT_RECOUNTS 12    /* iterations served by a hot-set recount */
 #define HOUGH_COUNT_LARGE 13       /* iterations run in the large-event path
-                                      (hot set and peaks in device memory) */
+                                      (hot set and peaks in device memory;
+                                      mode 2: hits of events beyond 1024
+                                      hits read from device memory)       */
 /* entries 14..15 are written as 0 */
 
 /* Largest hit count of one event. */

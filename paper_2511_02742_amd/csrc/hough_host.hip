@@ -54,7 +54,21 @@ hough_status check_config(const hough_config *c, std::string &why) {
     if (c->n_vanes < 1 || c->n_vanes > 32767) { why = "n_vanes must be in 1..32767"; return HOUGH_ERR_INVALID_ARG; }
     if (c->phi_unit != 0 && c->phi_unit != 1) { why = "phi_unit must be 0 or 1"; return HOUGH_ERR_INVALID_ARG; }
     if (c->min_votes < 1) { why = "min_votes must be >= 1"; return HOUGH_ERR_INVALID_ARG; }
-    if (c->peak_mode != 0 && c->peak_mode != 1) { why = "peak_mode must be 0 or 1"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->peak_mode < 0 || c->peak_mode > 2) { why = "peak_mode must be 0, 1 or 2"; return HOUGH_ERR_INVALID_ARG; }
+    if (c->peak_mode == 2) {
+        const int ct = c->coarse_theta ? c->coarse_theta : 10, cr = c->coarse_rho ? c->coarse_rho : 10;
+        if (ct < 1 || cr < 1 || c->n_theta % ct || c->n_rho % cr) {
+            why = "coarse_theta and coarse_rho must be >= 1 and divide n_theta and n_rho";
+            return HOUGH_ERR_INVALID_ARG;
+        }
+        if ((int64_t)(c->n_theta / ct) * (c->n_rho / cr) + (int64_t)ct * cr > hough::kCfMaxBins) {
+            why = "the coarse and fine histograms must fit 16384 bins together";
+            return HOUGH_ERR_INVALID_ARG;
+        }
+    } else if (c->coarse_theta != 0 || c->coarse_rho != 0) {
+        why = "coarse_theta and coarse_rho must be 0 unless peak_mode is 2";
+        return HOUGH_ERR_INVALID_ARG;
+    }
     if (c->nms_radius < 0 || c->nms_radius > 16) { why = "nms_radius must be in 0..16"; return HOUGH_ERR_INVALID_ARG; }
     if (c->assoc_window < 0) { why = "assoc_window must be >= 0"; return HOUGH_ERR_INVALID_ARG; }
     if (c->max_iters < 0) { why = "max_iters must be >= 0"; return HOUGH_ERR_INVALID_ARG; }
@@ -68,8 +82,6 @@ hough_status check_config(const hough_config *c, std::string &why) {
         why = "wg_threads must be 0, 256, 512 or 1024";
         return HOUGH_ERR_INVALID_ARG;
     }
-    for (int r : c->reserved)
-        if (r != 0) { why = "reserved fields must be 0"; return HOUGH_ERR_INVALID_ARG; }
     return HOUGH_OK;
 }
 
@@ -92,6 +104,24 @@ void build_tables(Ctx &c) {
     c.inv_w = (float)((double)g.n_rho / width);
     c.rho_c.resize(g.n_rho);
     for (int k = 0; k < g.n_rho; ++k) c.rho_c[k] = (float)((double)g.rho_min + (k + 0.5) * width / (double)g.n_rho);
+    // coarse grid of the coarse-to-fine mode: the same construction on
+    // n_theta / coarse_theta rows and n_rho / coarse_rho bins
+    c.ccos_t.clear();
+    c.csin_t.clear();
+    if (g.peak_mode == 2) {
+        c.f_theta = g.coarse_theta ? g.coarse_theta : 10;
+        c.f_rho = g.coarse_rho ? g.coarse_rho : 10;
+        c.c_theta = g.n_theta / c.f_theta;
+        c.c_rho = g.n_rho / c.f_rho;
+        c.ccos_t.resize(c.c_theta);
+        c.csin_t.resize(c.c_theta);
+        for (int j = 0; j < c.c_theta; ++j) {
+            const double th = (j + 0.5) * pi / (double)c.c_theta;
+            c.ccos_t[j] = (float)std::cos(th);
+            c.csin_t[j] = (float)std::sin(th);
+        }
+        c.inv_wc = (float)((double)c.c_rho / width);
+    }
 }
 
 // Picks the LDS tile: the own theta rows plus the 2w halo rows make a
@@ -203,6 +233,18 @@ hough_status choose_shape(Ctx &c, std::string &why) {
     if (hough::set_dump_lds_limit(c.dump_lds) != hipSuccess) {
         why = "hipFuncSetAttribute failed for the dump kernel";
         return HOUGH_ERR_DEVICE;
+    }
+    // the coarse-to-fine mode runs its own kernel (the tile above still
+    // serves the debug histogram)
+    if (g.peak_mode == 2) {
+        c.wg_threads = g.wg_threads > 0 ? g.wg_threads : 256;
+        c.lds_bytes = hough::cf_lds_bytes(c.c_theta * c.c_rho, c.f_theta * c.f_rho);
+        c.sweep_groups = 0;
+        if (c.lds_bytes + kStaticLds > lds_max) { why = "LDS budget exceeded"; return HOUGH_ERR_INVALID_ARG; }
+        if (hough::set_cf_lds_limit(c.wg_threads, c.lds_bytes) != hipSuccess) {
+            why = "hipFuncSetAttribute failed for the coarse-to-fine kernel";
+            return HOUGH_ERR_DEVICE;
+        }
     }
     return HOUGH_OK;
 }
@@ -329,6 +371,12 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     a.roll_off = c.roll_off;
     a.roll_bytes = c.roll_bytes;
     a.slot_bytes = w.slot_bytes;
+    a.ccs = c.d_ccs;
+    a.inv_wc = c.inv_wc;
+    a.c_theta = c.c_theta;
+    a.c_rho = c.c_rho;
+    a.f_theta = c.f_theta;
+    a.f_rho = c.f_rho;
     return a;
 }
 
@@ -362,7 +410,8 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
             return fail(&c, HOUGH_ERR_DEVICE, "hipEventCreate failed");
         (void)hipEventRecord(e0, s);
     }
-    hipError_t st = hough::launch_find(a, c.wg_threads, c.lds_bytes, s);
+    hipError_t st = c.cfg.peak_mode == 2 ? hough::launch_find_cf(a, c.wg_threads, c.lds_bytes, s)
+                                         : hough::launch_find(a, c.wg_threads, c.lds_bytes, s);
     if (st != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("finder launch failed: ") + hipGetErrorString(st));
     if (e0) {
         (void)hipEventRecord(e1, s);
@@ -429,7 +478,9 @@ hough_status make_context(const hough_config *cfg, int device, Ctx **out) {
         delete c;
         return fail(nullptr, st, why);
     }
-    const size_t nf = 2 * (size_t)cfg->n_theta + cfg->n_vanes + cfg->n_theta + cfg->n_rho;
+    // the coarse (cos, sin) pairs start at an even float offset (8-byte aligned)
+    const size_t o_ccs = (3 * (size_t)cfg->n_theta + cfg->n_vanes + cfg->n_rho + 1) & ~(size_t)1;
+    const size_t nf = o_ccs + 2 * (size_t)c->c_theta;
     if (hipMalloc(&c->d_tables, nf * sizeof(float)) != hipSuccess) {
         delete c;
         return fail(nullptr, HOUGH_ERR_OOM, "table allocation failed");
@@ -438,6 +489,7 @@ hough_status make_context(const hough_config *cfg, int device, Ctx **out) {
     c->d_phi = c->d_tables + 2 * cfg->n_theta;
     c->d_thc = c->d_phi + cfg->n_vanes;
     c->d_rhoc = c->d_thc + cfg->n_theta;
+    c->d_ccs = c->c_theta > 0 ? reinterpret_cast<float2 *>(c->d_tables + o_ccs) : nullptr;
     std::vector<float> host(nf);
     float *h = host.data();
     for (int j = 0; j < cfg->n_theta; ++j) {
@@ -447,6 +499,10 @@ hough_status make_context(const hough_config *cfg, int device, Ctx **out) {
     std::copy(c->phi_v.begin(), c->phi_v.end(), h + 2 * cfg->n_theta);
     std::copy(c->theta_c.begin(), c->theta_c.end(), h + 2 * cfg->n_theta + cfg->n_vanes);
     std::copy(c->rho_c.begin(), c->rho_c.end(), h + 3 * cfg->n_theta + cfg->n_vanes);
+    for (int j = 0; j < c->c_theta; ++j) {
+        h[o_ccs + 2 * j] = c->ccos_t[j];
+        h[o_ccs + 2 * j + 1] = c->csin_t[j];
+    }
     if (hipMemcpy(c->d_tables, h, nf * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(c->d_tables);
         delete c;

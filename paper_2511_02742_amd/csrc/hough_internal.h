@@ -72,6 +72,12 @@ struct FindArgs {
     int32_t big_ok;          // the banded large-event sweep fits this shape
     int32_t roll_off;        // LDS byte offset and size of its per-wave row lists
     int32_t roll_bytes;
+    // coarse-to-fine mode (peak_mode 2): the coarse grid (c_theta x c_rho
+    // bins, theta sampled at the coarse bin centres, ccs[J] = (cos, sin)) and
+    // the fine block of f_theta x f_rho full-grid bins under one coarse bin
+    const float2 *ccs;
+    float inv_wc;
+    int32_t c_theta, c_rho, f_theta, f_rho;
 };
 
 struct DumpArgs {
@@ -119,5 +125,13 @@ hipError_t find_blocks_per_cu(int wg_threads, int lds_bytes, int *blocks);
 // LDS bytes of k_find beyond the tile (hot list, peak lists, dummies).
 int find_lds_extra(int wg_threads, int hcap, int pkeep);
 hipError_t set_dump_lds_limit(int lds_bytes);
+
+// Coarse-to-fine finder (hough_cf.hip): one workgroup per event; events of
+// at most kCfStage hits keep their hits and pool flags in LDS.
+constexpr int kCfStage = 1024;
+constexpr int kCfMaxBins = 16384;  // coarse plus fine histogram words in LDS
+int cf_lds_bytes(int c_bins, int f_bins);
+hipError_t set_cf_lds_limit(int wg_threads, int lds_bytes);
+hipError_t launch_find_cf(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 
 }  // namespace hough

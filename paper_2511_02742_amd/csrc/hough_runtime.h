@@ -49,6 +49,11 @@ struct Ctx {
     float *d_tables = nullptr;
     float2 *d_cs = nullptr;
     float *d_phi = nullptr, *d_thc = nullptr, *d_rhoc = nullptr;
+    // coarse-to-fine mode: coarse grid tables, grid and block sizes
+    std::vector<float> ccos_t, csin_t;
+    float inv_wc = 0.f;
+    float2 *d_ccs = nullptr;
+    int c_theta = 0, c_rho = 0, f_theta = 0, f_rho = 0;
     // launch shape
     int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
     int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;

@@ -50,7 +50,8 @@ class HoughConfig(ctypes.Structure):
                 ("nms_radius", ctypes.c_int32), ("assoc_window", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("wg_threads", ctypes.c_int32), ("sweep_groups", ctypes.c_int32),
-                ("sweep_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("sweep_threads", ctypes.c_int32), ("coarse_theta", ctypes.c_int32),
+                ("coarse_rho", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):

@@ -45,28 +45,35 @@ def test_struct_layouts_match_header(tmp_path):
     src.write_text(
         "#include <stdio.h>\n#include <stddef.h>\n#include \"hough_tf.h\"\n"
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(hough_config),"
-        " offsetof(hough_config, min_votes), offsetof(hough_config, reserved), sizeof(hough_candidate),"
+        " offsetof(hough_config, min_votes), offsetof(hough_config, coarse_rho), sizeof(hough_candidate),"
         " offsetof(hough_candidate, hit_offset), offsetof(hough_candidate, rho)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(hough.HoughConfig), hough.HoughConfig.min_votes.offset,
-            hough.HoughConfig.reserved.offset, hough.cand_dtype.itemsize,
+            hough.HoughConfig.coarse_rho.offset, hough.cand_dtype.itemsize,
             hough.cand_dtype.fields["hit_offset"][1], hough.cand_dtype.fields["rho"][1]]
     assert got == want
 
 
-@pytest.mark.parametrize("field,value", [("n_theta", 0), ("min_votes", 0), ("peak_mode", 2),
-                                         ("rho_max", -600.0), ("wg_threads", 128), ("nms_radius", 17)])
-def test_create_rejects_bad_config(field, value):
+@pytest.mark.parametrize("kw,why", [
+    ({"n_theta": 0}, "n_theta"), ({"min_votes": 0}, "min_votes"), ({"peak_mode": 3}, "peak_mode"),
+    ({"rho_max": -600.0}, "rho_max"), ({"wg_threads": 128}, "wg_threads"), ({"nms_radius": 17}, "nms_radius"),
+    # coarse-to-fine: the factors must divide the grid (10 does not divide
+    # 1024), be 0 outside mode 2, and both histograms must fit LDS
+    ({"peak_mode": 2}, "coarse"), ({"coarse_theta": 10}, "coarse"),
+    ({"peak_mode": 2, "n_theta": 180, "n_rho": 1000, "coarse_theta": 7}, "coarse"),
+    ({"peak_mode": 2, "n_theta": 180, "n_rho": 1000, "coarse_rho": -1}, "coarse"),
+    ({"peak_mode": 2, "n_theta": 180, "n_rho": 1000, "coarse_theta": 1, "coarse_rho": 1}, "16384")])
+def test_create_rejects_bad_config(kw, why):
     from paper_2511_02742_amd import hough
-    cfg = hough.default_config(**{field: value})
+    cfg = hough.default_config(**kw)
     lib = hough.load_library()
     h = ctypes.c_void_p()
     st = lib.hough_create(ctypes.byref(cfg), 0, ctypes.byref(h))
     assert st == hough.HOUGH_ERR_INVALID_ARG
     assert not h.value
-    assert lib.hough_last_error(None)
+    assert why in lib.hough_last_error(None).decode()
 
 
 def test_null_and_bad_context_rejected():

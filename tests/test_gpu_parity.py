@@ -19,7 +19,8 @@ def _ocfg(hcfg) -> OracleConfig:
     return OracleConfig(n_theta=hcfg.n_theta, n_rho=hcfg.n_rho, rho_min=hcfg.rho_min, rho_max=hcfg.rho_max,
                         n_vanes=hcfg.n_vanes, phi_unit=hcfg.phi_unit, min_votes=hcfg.min_votes,
                         peak_mode=hcfg.peak_mode, nms_radius=hcfg.nms_radius,
-                        assoc_window=hcfg.assoc_window, max_iters=hcfg.max_iters)
+                        assoc_window=hcfg.assoc_window, max_iters=hcfg.max_iters,
+                        coarse_theta=hcfg.coarse_theta or 10, coarse_rho=hcfg.coarse_rho or 10)
 
 
 _finders = {}
