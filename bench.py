@@ -50,6 +50,8 @@ def main():
                     help="events of the Poisson(20) batch whose candidates the refit leg fits (0: skip it)")
     ap.add_argument("--refit-oracle", type=int, default=30,
                     help="pure candidates also fitted by the float64 oracle for the parameter error")
+    ap.add_argument("--no-coarse-fine", action="store_true",
+                    help="skip the coarse-to-fine leg (the paper's 18 x 100 -> 10 x 10 histograms)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first, as the reference kernel for "
                          "FETCH_SIZE / WRITE_SIZE counter scaling")
@@ -139,19 +141,7 @@ def main():
 
     # ---- HBM traffic of the finder kernel from the committed counter summary
     # (reported only while the kernel source still matches the one profiled)
-    traffic = None
-    try:
-        from paper_2511_02742_amd.prof_summary import kernel_source_hash
-        kv = {}
-        with open(os.path.join(ROOT, "profiles", "k_find_pileup50.txt")) as fh:
-            for line in fh:
-                if ":" in line:
-                    k, v = line.split(":", 1)
-                    kv[k.strip()] = v.strip()
-        if kv.get("kernel_sha256_16") == kernel_source_hash() and "fetch_bytes_per_launch" in kv:
-            traffic = float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
-    except (OSError, ValueError):
-        traffic = None
+    traffic = profiled_traffic("k_find_pileup50", "hough_kernels.hip")
 
     # ---- roofline of the finder kernel ------------------------------------
     flops = FLOPS_PER_VOTE * info["evals"]
@@ -181,6 +171,7 @@ def main():
 
     served = serve_bench(args, f, log) if args.serve_events > 0 else None
     refit = refit_bench(args, f, log) if args.refit_events > 0 else None
+    coarse_fine = None if args.no_coarse_fine else coarse_fine_bench(args, batch, z, vane, offs, log)
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
@@ -202,6 +193,7 @@ def main():
         "cpu_baseline": cpu,
         "served": served,
         "refit": refit,
+        "coarse_fine": coarse_fine,
     }
     print(json.dumps(rec), flush=True)
 
@@ -364,6 +356,98 @@ def refit_bench(args, finder, log):
         res["max_param_error_vs_f64"] = {k: float("%.3g" % v) for k, v in
                                          zip(("kappa", "phi0", "d0", "z0", "tan_lambda"), worst)}
     log("refit: %s" % res)
+    return res
+
+
+def profiled_traffic(name, source):
+    """HBM bytes per launch (read + written) from the committed counter
+    summary profiles/<name>.txt, or None when it is missing or was taken from
+    another version of the kernel source."""
+    try:
+        from paper_2511_02742_amd.prof_summary import kernel_source_hash
+        kv = {}
+        with open(os.path.join(ROOT, "profiles", name + ".txt")) as fh:
+            for line in fh:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_sha256_16") == kernel_source_hash(source) and "fetch_bytes_per_launch" in kv:
+            return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def seeded_fraction(batch, cand, hit_index, min_hits):
+    """Share of the generated tracks with at least min_hits hits that some
+    candidate seeds: at least min_hits of the candidate's hits, and more than
+    half of them, come from that track."""
+    import numpy as np
+    seeded = set()
+    for cd in cand:
+        ev = batch.events[cd["event"]]
+        tr = ev.track[hit_index[cd["hit_offset"]:cd["hit_offset"] + cd["n_hits"]]]
+        tr = tr[tr >= 0]
+        if len(tr) == 0:
+            continue
+        t, k = np.unique(tr, return_counts=True)
+        i = int(np.argmax(k))
+        if k[i] >= min_hits and 2 * k[i] > cd["n_hits"]:
+            seeded.add((int(cd["event"]), int(t[i])))
+    findable = 0
+    hit = 0
+    for e, ev in enumerate(batch.events):
+        t, k = np.unique(ev.track[ev.track >= 0], return_counts=True)
+        for tt in t[k >= min_hits]:
+            findable += 1
+            hit += (e, int(tt)) in seeded
+    return hit / max(findable, 1), findable
+
+
+def coarse_fine_bench(args, batch, z, vane, offs, log):
+    """The paper's two-stage histogram (18 x 100 coarse, 10 x 10 fine, on the
+    180 x 1000 grid) on the same pileup-50 batch, against full-grid argmax and
+    nms on the same grid: events/s, finder kernel time, Eq. (4) evaluations,
+    candidates and the share of findable generated tracks each one seeds."""
+    import numpy as np
+    import torch
+    from paper_2511_02742_amd.hough import HoughFinder
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    res = {"workload": "the same %d pileup-50 events, 180 x 1000 grid, T=6, a=0" % N_EVENTS}
+    for name, kw in (("coarse_fine", {"peak_mode": 2}), ("argmax", {"peak_mode": 0}), ("nms", {"peak_mode": 1})):
+        f = HoughFinder(0, n_theta=180, n_rho=1000, **kw)
+        out = f.alloc_outputs(N_EVENTS, batch.n_hits)
+        for _ in range(args.warmup):
+            f.find(z, vane, offs, out=out, stream=stream)
+        torch.cuda.synchronize(dev)
+        f.set_timing(True)
+        f.timing(reset=True)
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            f.find(z, vane, offs, out=out, stream=stream)
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t1
+        f.set_timing(False)
+        kern_ms, launches = f.timing(reset=True)
+        cand, hits, info = out.to_host()
+        assert info["status"] == 0, info
+        frac, findable = seeded_fraction(batch, cand, hits, 6)
+        kavg = kern_ms / max(launches, 1)
+        res[name] = {"events_per_s": round(N_EVENTS * args.steps / wall, 1),
+                     "ms_per_step": round(1e3 * wall / args.steps, 4), "kernel_avg_ms": round(kavg, 4),
+                     "kernel": "k_find_cf" if name == "coarse_fine" else "k_find",
+                     "evals": info["evals"], "evals_per_s": round(info["evals"] / (kavg * 1e-3), 1),
+                     "candidates": info["candidates"], "iters": info["iters"],
+                     "seeded_track_fraction": round(frac, 4)}
+        res["findable_tracks"] = findable
+        log("coarse-fine leg, %s: %s" % (name, res[name]))
+    cf = res["coarse_fine"]
+    flops = FLOPS_PER_VOTE * cf["evals"]
+    achieved = flops / (cf["kernel_avg_ms"] * 1e-3) / 1e12
+    cf["roofline"] = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TFLOPS, 2),
+                      "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                      "traffic": profiled_traffic("k_find_cf_pileup50", "hough_cf.hip")}
     return res
 
 

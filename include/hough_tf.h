@@ -130,7 +130,10 @@ typedef struct {
 #define HOUGH_COUNT_STATUS 2       /* 0, or a negative hough_status         */
 #define HOUGH_COUNT_DETAIL 3       /* first invalid global hit index, or -1 */
 #define HOUGH_COUNT_EVALS 4        /* Eq. (4) bin evaluations performed for
-                                      histograms and hot-bin recounts      */
+                                      histograms and hot-bin recounts (mode
+                                      2: the first coarse fill, each fine
+                                      block, and the coarse votes taken out
+                                      for removed hits)                    */
 #define HOUGH_COUNT_ITERS 5        /* iterations summed over events         */
 #define HOUGH_COUNT_MAX_ITERS 6    /* largest iteration count of an event   */
 #define HOUGH_COUNT_PASSES 7       /* full histogram sweeps                 */

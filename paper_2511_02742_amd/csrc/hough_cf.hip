@@ -5,22 +5,23 @@
 // range, then a 10 x 10 fine histogram inside the most likely coarse bin,
 // whose maximum is the line. Here one workgroup owns one event for the whole
 // loop, and per iteration
-//   1. every alive hit votes once per coarse theta row (Eq. (4) at the coarse
-//      row's theta, the coarse bin width) into the coarse histogram in LDS.
-//      Each vote is an LDS atomic add that returns the old count, and the
-//      thread keeps the largest key (count, -flat) its votes produced: the
-//      largest of those over the workgroup is the histogram's largest key,
-//      so the histogram is never scanned;
+//   1. the coarse histogram of the alive hits (Eq. (4) at each coarse row's
+//      theta, the coarse bin width) is in LDS: every hit votes once per
+//      coarse row in the first iteration, by LDS atomic adds that return
+//      nothing (no wave waits on them), and each later iteration finds it
+//      with the removed hits' votes subtracted. Each thread takes the largest
+//      key (count, -flat) of its share of the bins and an LDS atomic max
+//      gives the workgroup's;
 //   2. every alive hit votes in the fine rows (the full-resolution theta rows
-//      under the coarse bin) into the fine block, keeping the largest key the
-//      same way; its count must reach T, else the event is done;
+//      under the coarse bin) into the fine block, whose largest key is found
+//      the same way; its count must reach T, else the event is done;
 //   3. the hits on the peak's line (|k_i(j*) - k*| <= a) are claimed in
 //      ascending index order through ballots and a prefix over 64-hit words,
-//      written out and removed from the pool.
+//      written out, removed from the pool and their coarse votes subtracted.
 // Hits vote in lanes (64 per chunk), theta rows are dealt to the waves. An
 // event of at most kCfStage hits keeps (phi, z) and its pool bitmask in LDS;
 // a larger one reads its staged (phi, z) and the pool state from device
-// memory. Four workgroup barriers per iteration.
+// memory. Five workgroup barriers per iteration after the first.
 //
 // The bin expression is the finder's: separately rounded float operations
 // (built with -ffp-contract=off) on host-built float tables.
@@ -50,7 +51,7 @@ struct CfLds {
     float2 *pz;                     // staged events: (phi, z) per hit
     unsigned long long *pool;       // staged events: bit i = hit i still in the pool
     unsigned long long *mm;         // match masks of one association segment
-    unsigned long long *red;        // per-wave maxima: [0, NW) coarse, [NW, 2 NW) fine
+    unsigned long long *red;        // largest coarse [0] and fine [1] key
 };
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
@@ -87,10 +88,29 @@ __device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsig
     return a > b ? a : b;
 }
 
+// One DPP step of the wave maximum: v and the value `ctrl` moves into this
+// lane (lanes the move does not reach keep their own).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long v) {
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, ROW_MASK, 0xf, false);
+    return umax64(v, ((unsigned long long)ohi << 32) | olo);
+}
+
+// Largest value over the wave (every lane active), in registers: row_shr
+// 1, 2, 4, 8 leave each row's maximum in its lane 15, row_bcast 15 and 31
+// carry them up to lane 63.
 __device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = umax64(v, __shfl_xor(v, o));
-    return v;
+    v = dpp_max_step<0x111, 0xf>(v);
+    v = dpp_max_step<0x112, 0xf>(v);
+    v = dpp_max_step<0x114, 0xf>(v);
+    v = dpp_max_step<0x118, 0xf>(v);
+    v = dpp_max_step<0x142, 0xa>(v);
+    v = dpp_max_step<0x143, 0xc>(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Hit i of the event if it is still in the pool: its (phi, z).
@@ -118,13 +138,47 @@ struct CfStats {
     int iter, passes, unstaged;
 };
 
-template <int NT, bool STAGED>
-__device__ __forceinline__ void cf_loop(const FindArgs &A, const CfLds &L, CfShared &sh, int e, int64_t b, int n,
-                                        CfStats &st) {
+// Votes of every alive hit into `rows` rows of a histogram in LDS, U rows
+// per wave at a time (rows wave + NW u): row r's bin is
+// d = rho_bin(hit, tab[r], inv_w) - koff, counted in hist[r * width + d]
+// when 0 <= d < width. The atomics return nothing, so a wave never waits on
+// them; the maximum is found by a scan afterwards.
+template <int NT, int U, bool STAGED>
+__device__ __forceinline__ void fill(const FindArgs &A, const CfLds &L, const float2 *__restrict__ tab, int rows,
+                                     uint32_t *hist, int width, int koff, float inv_w, int64_t b, int n) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = threadIdx.x & (kWave - 1);
     const int nchunks = (n + kWave - 1) / kWave;
+    for (int g = wave; g < rows; g += U * NW) {
+        float cc[U], ss[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float2 t = tab[g + u * NW < rows ? g + u * NW : g];
+            cc[u] = t.x;
+            ss[u] = t.y;
+        }
+        for (int ch = 0; ch < nchunks; ++ch) {
+            float phi, z;
+            if (!fetch<STAGED>(A, L, b, n, ch * kWave + lane, phi, z)) continue;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int d = rho_bin(phi, z, cc[u], ss[u], A.rho_min, inv_w) - koff;
+                if (g + u * NW < rows && (unsigned)d < (unsigned)width) atomicAdd(&hist[(g + u * NW) * width + d], 1u);
+            }
+        }
+    }
+}
+
+// The (cos, sin) tables come in as separate restrict pointers: nothing the
+// kernel stores can alias them, so their uniform loads are scalar loads.
+template <int NT, bool STAGED>
+__device__ __forceinline__ void cf_loop(const FindArgs &A, const float2 *__restrict__ ccs,
+                                        const float2 *__restrict__ cs, const CfLds &L, CfShared &sh, int e,
+                                        int64_t b, int n, CfStats &st) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = threadIdx.x & (kWave - 1);
     const int cbins = A.c_theta * A.c_rho;
     const int fbins = A.f_theta * A.f_rho;
     const int64_t cbase = b / (int64_t)A.min_votes;
@@ -133,67 +187,61 @@ __device__ __forceinline__ void cf_loop(const FindArgs &A, const CfLds &L, CfSha
         const int n_alive = n - nhit0;
         // no bin can reach T with fewer than T hits
         if (n_alive < (int)A.min_votes) break;
-        st.evals += (unsigned long long)n_alive * (unsigned long long)(A.c_theta + A.f_theta);
+        st.evals += (unsigned long long)n_alive * (unsigned long long)A.f_theta;
+        // 1. coarse histogram: filled from every hit in the first iteration;
+        // later iterations find it with the votes of the hits removed since
+        // subtracted (step 3), which is the histogram of the hits left. Each
+        // thread takes the largest key of its share of the bins, and the
+        // workgroup's largest comes from one LDS atomic max per thread.
+        if (st.passes == 0) {
+            st.evals += (unsigned long long)n * (unsigned long long)A.c_theta;
+            fill<NT, 5, STAGED>(A, L, ccs, A.c_theta, L.coarse, A.c_rho, 0, A.inv_wc, b, n);
+            __syncthreads();
+        }
         ++st.passes;
         if (!STAGED) ++st.unstaged;
-
-        // 1. coarse histogram; each vote's new key kept per thread
         unsigned long long best = 0ull;
-        for (int ch = 0; ch < nchunks; ++ch) {
-            float phi, z;
-            if (!fetch<STAGED>(A, L, b, n, ch * kWave + lane, phi, z)) continue;
-            for (int J = wave; J < A.c_theta; J += NW) {
-                const float2 cs = A.ccs[J];
-                const int K = rho_bin(phi, z, cs.x, cs.y, A.rho_min, A.inv_wc);
-                if ((unsigned)K < (unsigned)A.c_rho) {
-                    const uint32_t flat = (uint32_t)(J * A.c_rho + K);
-                    const uint32_t old = atomicAdd(&L.coarse[flat], 1u);
-                    best = umax64(best, bin_key(old + 1u, flat));
-                }
-            }
+#pragma unroll 4
+        for (int i = threadIdx.x; i < cbins; i += NT) {
+            const uint32_t c = L.coarse[i];
+            if (c) best = umax64(best, bin_key(c, (uint32_t)i));
         }
         best = wave_max64(best);
-        if (lane == 0) L.red[wave] = best;
+        if (lane == 0 && best) atomicMax(&L.red[0], best);
         __syncthreads();
         // with every coarse bin empty, the largest key is that of bin 0
-        best = 0xffffffffull;
-        for (int w = 0; w < NW; ++w) best = umax64(best, L.red[w]);
+        best = umax64(L.red[0], 0xffffffffull);
         const uint32_t cflat = 0xffffffffu - (uint32_t)best;
         const int J = (int)(cflat / (uint32_t)A.c_rho);
         const int j0 = J * A.f_theta;
         const int k0 = (int)(cflat - (uint32_t)J * (uint32_t)A.c_rho) * A.f_rho;
-        // every coarse vote has returned: clear the histogram for the next
-        // iteration
-        for (int i = threadIdx.x; i < cbins; i += NT) L.coarse[i] = 0u;
 
-        // 2. fine block under the coarse bin
+        // 2. fine block under the coarse bin, the same way
+        fill<NT, 3, STAGED>(A, L, cs + j0, A.f_theta, L.fine, A.f_rho, k0, A.inv_w, b, n);
+        __syncthreads();
         unsigned long long peak = 0ull;
-        for (int ch = 0; ch < nchunks; ++ch) {
-            float phi, z;
-            if (!fetch<STAGED>(A, L, b, n, ch * kWave + lane, phi, z)) continue;
-            for (int r = wave; r < A.f_theta; r += NW) {
-                const int j = j0 + r;
-                const float2 cs = A.cs[j];
-                const int d = rho_bin(phi, z, cs.x, cs.y, A.rho_min, A.inv_w) - k0;
-                if ((unsigned)d < (unsigned)A.f_rho) {
-                    const uint32_t old = atomicAdd(&L.fine[r * A.f_rho + d], 1u);
-                    peak = umax64(peak, bin_key(old + 1u, (uint32_t)(j * A.n_rho + k0 + d)));
-                }
-            }
+        for (int i = threadIdx.x; i < fbins; i += NT) {
+            const uint32_t c = L.fine[i];
+            L.fine[i] = 0u;
+            const int r = i / A.f_rho;
+            const uint32_t flat = (uint32_t)((j0 + r) * A.n_rho + k0 + (i - r * A.f_rho));
+            if (c) peak = umax64(peak, bin_key(c, flat));
         }
         peak = wave_max64(peak);
-        if (lane == 0) L.red[NW + wave] = peak;
+        if (lane == 0 && peak) atomicMax(&L.red[1], peak);
         __syncthreads();
-        peak = 0ull;
-        for (int w = 0; w < NW; ++w) peak = umax64(peak, L.red[NW + w]);
-        for (int i = threadIdx.x; i < fbins; i += NT) L.fine[i] = 0u;
+        peak = L.red[1];
         const uint32_t cnt = (uint32_t)(peak >> 32);
         if (cnt < A.min_votes) break;
         const uint32_t flat = 0xffffffffu - (uint32_t)peak;
         const int jp = (int)(flat / (uint32_t)A.n_rho);
         const int kp = (int)(flat - (uint32_t)jp * (uint32_t)A.n_rho);
-        const float2 csp = A.cs[jp];
+        const float2 csp = cs[jp];
         const int cid = sh.ncand;
+        // the candidate's bin centres, loaded now so the association hides
+        // their latency
+        const float theta_c = A.theta_c[jp];
+        const float rho_c = A.rho_c[kp];
 
         // 3. association, in segments of kCfStage hits: match masks, then
         // positions from the word prefix. Every hit that voted into the peak
@@ -214,10 +262,16 @@ __device__ __forceinline__ void cf_loop(const FindArgs &A, const CfLds &L, CfSha
                 if (lane == 0) L.mm[w] = mask;
             }
             __syncthreads();
+            // match counts of the segment's words in lanes 0..15 (one DPP
+            // row), their inclusive prefix by row_shr 1, 2, 4, 8
+            int incl = lane < words ? __popcll(L.mm[lane]) : 0;
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);
+            incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xf, false);
             for (int w = wave; w < words; w += NW) {
                 const unsigned long long mask = L.mm[w];
-                int before = 0;
-                for (int v = 0; v < w; ++v) before += __popcll(L.mm[v]);
+                const int before = w > 0 ? __builtin_amdgcn_readlane(incl, w - 1) : 0;
                 if ((mask >> lane) & 1ull) {
                     const int i = s0 + w * kWave + lane;
                     A.hits_ws[b + nhit0 + taken + before + mbcnt64(mask)] = i;
@@ -227,9 +281,32 @@ __device__ __forceinline__ void cf_loop(const FindArgs &A, const CfLds &L, CfSha
                     if (lane == 0) L.pool[(s0 >> 6) + w] &= ~mask;
                 }
             }
-            int seg = 0;
-            for (int v = 0; v < words; ++v) seg += __popcll(L.mm[v]);
+            // take the claimed hits' votes out of the coarse histogram (unless
+            // no iteration follows): every wave walks the segment's words,
+            // its own coarse rows
+            const bool last = A.max_iters != 0 && st.iter + 1 >= A.max_iters;
+            for (int w = 0; w < words && !last; ++w) {
+                const unsigned long long mask = L.mm[w];
+                if (!((mask >> lane) & 1ull)) continue;
+                const int i = s0 + w * kWave + lane;
+                float phi, z;
+                if constexpr (STAGED) {
+                    const float2 p = L.pz[i];
+                    phi = p.x;
+                    z = p.y;
+                } else {
+                    phi = A.aphi[b + i];
+                    z = A.az[b + i];
+                }
+                for (int J = wave; J < A.c_theta; J += NW) {
+                    const float2 c = ccs[J];
+                    const int K = rho_bin(phi, z, c.x, c.y, A.rho_min, A.inv_wc);
+                    if ((unsigned)K < (unsigned)A.c_rho) atomicSub(&L.coarse[J * A.c_rho + K], 1u);
+                }
+            }
+            const int seg = __builtin_amdgcn_readlane(incl, kSegWords - 1);
             taken += seg;
+            if (!last) st.evals += (unsigned long long)seg * (unsigned long long)A.c_theta;
             // the masks are rewritten by the next segment
             if (s0 + kCfStage < n) __syncthreads();
         }
@@ -242,15 +319,29 @@ __device__ __forceinline__ void cf_loop(const FindArgs &A, const CfLds &L, CfSha
             cd.peak_votes = cnt;
             cd.n_hits = (uint32_t)taken;
             cd.hit_offset = nhit0;
-            cd.theta = A.theta_c[jp];
-            cd.rho = A.rho_c[kp];
+            cd.theta = theta_c;
+            cd.rho = rho_c;
             A.cand_ws[cbase + cid] = cd;
             sh.ncand = cid + 1;
             sh.nhit = nhit0 + taken;
+            // both maxima were read before the association's barrier
+            L.red[0] = 0ull;
+            L.red[1] = 0ull;
         }
         ++st.iter;
         __syncthreads();
     }
+}
+
+// The event's statistics words (multi-event calls; the scan kernel sums them).
+__device__ void put_ev_stats(const FindArgs &A, int e, const CfStats &st) {
+    unsigned long long *p = A.ev_stats + e;
+    const size_t ne = (size_t)A.n_events;
+    for (int k = 0; k < kEvStats; ++k) p[k * ne] = 0ull;
+    p[kEvEvals * ne] = st.evals;
+    p[kEvIters * ne] = (unsigned long long)st.iter;
+    p[kEvPasses * ne] = (unsigned long long)st.passes;
+    p[kEvLarge * ne] = (unsigned long long)st.unstaged;
 }
 
 __device__ void write_error_counts(int64_t *counts, long long status, long long detail) {
@@ -262,8 +353,8 @@ __device__ void write_error_counts(int64_t *counts, long long status, long long 
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_find_cf(FindArgs A) {
-    constexpr int NW = NT / kWave;
+__global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__restrict__ ccs,
+                                                const float2 *__restrict__ cs) {
     __shared__ CfShared sh;
     unsigned char *const lds = reinterpret_cast<unsigned char *>(cf_lds);
     const int cb = (4 * A.c_theta * A.c_rho + 15) & ~15;
@@ -298,7 +389,10 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A) {
         if (threadIdx.x == 0) {
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
-            if (A.counts != nullptr) write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
+            if (A.counts != nullptr)
+                write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
+            else
+                put_ev_stats(A, e, CfStats{0ull, 0, 0, 0});
         }
         return;
     }
@@ -332,11 +426,13 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A) {
     }
     for (int i = threadIdx.x; i < A.c_theta * A.c_rho; i += NT) L.coarse[i] = 0u;
     for (int i = threadIdx.x; i < A.f_theta * A.f_rho; i += NT) L.fine[i] = 0u;
+    if (threadIdx.x < 2) L.red[threadIdx.x] = 0ull;
     if (__syncthreads_or(badhit)) {
         if (threadIdx.x == 0) {
             atomicMin(&A.err[0], (long long)HOUGH_ERR_DATA);
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
+            if (A.counts == nullptr) put_ev_stats(A, e, CfStats{0ull, 0, 0, 0});
         }
         if (A.counts != nullptr) {
             // first invalid hit of the event (the only event of the call)
@@ -353,10 +449,9 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A) {
 
     CfStats st{0ull, 0, 0, 0};
     if (staged)
-        cf_loop<NT, true>(A, L, sh, e, b, n, st);
+        cf_loop<NT, true>(A, ccs, cs, L, sh, e, b, n, st);
     else
-        cf_loop<NT, false>(A, L, sh, e, b, n, st);
-    (void)NW;
+        cf_loop<NT, false>(A, ccs, cs, L, sh, e, b, n, st);
 
     if (A.counts != nullptr) {
         if (threadIdx.x == 0) {
@@ -376,20 +471,16 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A) {
     if (threadIdx.x == 0) {
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
-        atomicAdd(&A.stats[0], st.evals);
-        atomicAdd(&A.stats[1], (unsigned long long)st.iter);
-        atomicMax(&A.stats[2], (unsigned long long)st.iter);
-        atomicAdd(&A.stats[3], (unsigned long long)st.passes);
-        atomicAdd(&A.stats[9], (unsigned long long)st.unstaged);
+        put_ev_stats(A, e, st);
     }
 }
 
 }  // namespace
 
-int cf_lds_bytes(int c_bins, int f_bins) {
-    // histograms, staged (phi, z), pool and match words, per-wave maxima
-    // (two per wave of the largest workgroup)
-    return ((4 * c_bins + 15) & ~15) + ((4 * f_bins + 15) & ~15) + 8 * kCfStage + 16 * kSegWords + 16 * 16;
+int cf_lds_bytes(int c_bins, int f_bins, int wg_threads) {
+    // histograms, staged (phi, z), pool and match words, the two maxima
+    (void)wg_threads;
+    return ((4 * c_bins + 15) & ~15) + ((4 * f_bins + 15) & ~15) + 8 * kCfStage + 16 * kSegWords + 16;
 }
 
 hipError_t set_cf_lds_limit(int wg_threads, int lds_bytes) {
@@ -413,13 +504,13 @@ hipError_t launch_find_cf(const FindArgs &a, int wg_threads, int lds_bytes, hipS
     const dim3 grid(a.n_events);
     switch (wg_threads) {
     case 256:
-        hipLaunchKernelGGL(k_find_cf<256>, grid, dim3(256), lds_bytes, s, a);
+        hipLaunchKernelGGL(k_find_cf<256>, grid, dim3(256), lds_bytes, s, a, a.ccs, a.cs);
         break;
     case 512:
-        hipLaunchKernelGGL(k_find_cf<512>, grid, dim3(512), lds_bytes, s, a);
+        hipLaunchKernelGGL(k_find_cf<512>, grid, dim3(512), lds_bytes, s, a, a.ccs, a.cs);
         break;
     case 1024:
-        hipLaunchKernelGGL(k_find_cf<1024>, grid, dim3(1024), lds_bytes, s, a);
+        hipLaunchKernelGGL(k_find_cf<1024>, grid, dim3(1024), lds_bytes, s, a, a.ccs, a.cs);
         break;
     default:
         return hipErrorInvalidValue;

@@ -238,7 +238,7 @@ hough_status choose_shape(Ctx &c, std::string &why) {
     // serves the debug histogram)
     if (g.peak_mode == 2) {
         c.wg_threads = g.wg_threads > 0 ? g.wg_threads : 256;
-        c.lds_bytes = hough::cf_lds_bytes(c.c_theta * c.c_rho, c.f_theta * c.f_rho);
+        c.lds_bytes = hough::cf_lds_bytes(c.c_theta * c.c_rho, c.f_theta * c.f_rho, c.wg_threads);
         c.sweep_groups = 0;
         if (c.lds_bytes + kStaticLds > lds_max) { why = "LDS budget exceeded"; return HOUGH_ERR_INVALID_ARG; }
         if (hough::set_cf_lds_limit(c.wg_threads, c.lds_bytes) != hipSuccess) {
@@ -273,7 +273,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     const size_t o_state = take(4 * nh), o_aidx = take(4 * nh), o_aphi = take(4 * nh), o_az = take(4 * nh);
     const size_t o_hits = take(4 * nh), o_cand = take(sizeof(hough_candidate) * ncand);
     const size_t o_enc = take(4 * ne), o_enh = take(4 * ne), o_eco = take(8 * ne), o_eho = take(8 * ne);
-    const size_t o_stats = take(8 * 16), o_err = take(8 * 4), o_offs = take(8 * 4);
+    const size_t o_evst = take(8 * (size_t)hough::kEvStats * ne), o_err = take(8 * 4), o_offs = take(8 * 4);
     const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
     const size_t o_ghs = c.sweep_groups > 0 ? take(8 * (size_t)ne * (size_t)std::max(c.hs_cap, 1)) : 0;
     // large-event slots: no more workgroups than events, nor than fit the
@@ -303,7 +303,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     w.ev_nhits = reinterpret_cast<int32_t *>(base + o_enh);
     w.ev_cout = reinterpret_cast<long long *>(base + o_eco);
     w.ev_hout = reinterpret_cast<long long *>(base + o_eho);
-    w.stats = reinterpret_cast<unsigned long long *>(base + o_stats);
+    w.ev_stats = reinterpret_cast<unsigned long long *>(base + o_evst);
     w.err = reinterpret_cast<long long *>(base + o_err);
     w.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
     w.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
@@ -313,9 +313,9 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     w.pool = reinterpret_cast<unsigned char *>(base + o_pool);
     w.pool_slots = slots;
     w.slot_bytes = slot_bytes;
-    // statistics, error and split-sweep words start cleared; every call
+    // error and split-sweep words start cleared; every call
     // leaves them so
-    if (hough::launch_reset(w.stats, w.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_reset(w.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     if (hough::launch_zero_i32(w.g_cnt, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     if (hough::launch_zero_i32(w.g_flag, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
     if (hough::launch_zero_i32(w.pool_flags, slots, s) != hipSuccess) return HOUGH_ERR_DEVICE;
@@ -347,7 +347,7 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     a.hits_ws = w.hits_ws;
     a.ev_ncand = w.ev_ncand;
     a.ev_nhits = w.ev_nhits;
-    a.stats = w.stats;
+    a.ev_stats = w.ev_stats;
     a.err = w.err;
     a.tile_rows = c.tile_rows;
     a.pitch = c.pitch;
@@ -429,7 +429,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     ca.ev_nhits = w.ev_nhits;
     ca.ev_cout = w.ev_cout;
     ca.ev_hout = w.ev_hout;
-    ca.stats = w.stats;
+    ca.ev_stats = w.ev_stats;
     ca.err = w.err;
     ca.cand = cand;
     ca.hit_index = hit_index;

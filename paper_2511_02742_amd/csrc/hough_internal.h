@@ -18,6 +18,20 @@ __host__ __device__ inline int assoc_fixed_bytes(int W) {
 }
 __host__ __device__ inline int assoc_peak_bytes(int W) { return 12 * W + 28; }
 
+// Per-event statistics words written by the finder kernels.
+enum EvStat {
+    kEvEvals = 0,     // Eq. (4) bin evaluations
+    kEvIters,         // iterations
+    kEvPasses,        // histogram sweeps
+    kEvTiled,         // sweeps through the tiled fallback
+    kEvTrunc,         // peak-list truncations
+    kEvHotScans,      // tiles scanned after a hot-list overflow
+    kEvHotsetFull,    // row-stream sweeps whose hot set overflowed
+    kEvRecounts,      // iterations served by a hot-set recount
+    kEvLarge,         // iterations in the large-event path
+    kEvStats
+};
+
 // Everything the finder kernel needs, passed by value.
 struct FindArgs {
     // configuration
@@ -41,8 +55,9 @@ struct FindArgs {
     hough_candidate *cand_ws;  // candidate slots, event e starts at floor(off_e / T)
     int32_t *hits_ws;    // hit-list slots, event e starts at off_e
     int32_t *ev_ncand, *ev_nhits;
-    unsigned long long *stats;  // [evals, iters, max_iters, passes, tiled, truncations,
-                                //  hot scans, hot-set overflows, recounts, ...] (16 words)
+    // per-event statistics, [kEvStats][n_events] (see EvStat); summed by the
+    // scan kernel, so no two workgroups update one word
+    unsigned long long *ev_stats;
     long long *err;             // [status (min), first bad global hit index (min)]
     // launch shape
     int32_t tile_rows;   // own theta rows per LDS tile
@@ -102,7 +117,7 @@ struct CompactArgs {
     const int32_t *hits_ws;
     const int32_t *ev_ncand, *ev_nhits;
     long long *ev_cout, *ev_hout;  // exclusive prefix sums
-    unsigned long long *stats;  // read, then cleared for the next call
+    const unsigned long long *ev_stats;  // [kEvStats][n_events]
     long long *err;
     hough_candidate *cand;
     int32_t *hit_index;
@@ -110,7 +125,7 @@ struct CompactArgs {
 };
 
 // Kernel launchers (hough_kernels.hip). Each returns the launch status.
-hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s);  // used once per workspace
+hipError_t launch_reset(long long *err, hipStream_t s);  // used once per workspace
 hipError_t launch_find(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t s);
 hipError_t set_sweep_lds_limit(int threads, int lds_bytes);
@@ -130,7 +145,7 @@ hipError_t set_dump_lds_limit(int lds_bytes);
 // at most kCfStage hits keep their hits and pool flags in LDS.
 constexpr int kCfStage = 1024;
 constexpr int kCfMaxBins = 16384;  // coarse plus fine histogram words in LDS
-int cf_lds_bytes(int c_bins, int f_bins);
+int cf_lds_bytes(int c_bins, int f_bins, int wg_threads);
 hipError_t set_cf_lds_limit(int wg_threads, int lds_bytes);
 hipError_t launch_find_cf(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 

@@ -45,7 +45,6 @@ constexpr int kWave = 64;
 extern __shared__ __align__(16) uint32_t g_lds[];
 constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
 constexpr int kMaxLists = 5;  // row lists of the banded sweep: 2 w + 1 for w <= 2
-constexpr int kStats = 16;  // workspace statistics words (see k_scan)
 
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1235,6 +1234,22 @@ __device__ void write_error_counts(int64_t *counts, long long status, long long 
     for (int i = HOUGH_COUNT_EVALS; i < HOUGH_COUNTS; ++i) counts[i] = 0;
 }
 
+// The event's statistics words (multi-event calls; the scan kernel sums them).
+__device__ void put_ev_stats(const FindArgs &A, int e, unsigned long long evals, int iter, int passes, int tiled,
+                             int trunc, int hotscan, int hs_full, int recounts, int bigs) {
+    unsigned long long *p = A.ev_stats + e;
+    const size_t ne = (size_t)A.n_events;
+    p[kEvEvals * ne] = evals;
+    p[kEvIters * ne] = (unsigned long long)iter;
+    p[kEvPasses * ne] = (unsigned long long)passes;
+    p[kEvTiled * ne] = (unsigned long long)tiled;
+    p[kEvTrunc * ne] = (unsigned long long)trunc;
+    p[kEvHotScans * ne] = (unsigned long long)hotscan;
+    p[kEvHotsetFull * ne] = (unsigned long long)hs_full;
+    p[kEvRecounts * ne] = (unsigned long long)recounts;
+    p[kEvLarge * ne] = (unsigned long long)bigs;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restrict__ cs) {
     constexpr int NW = NT / kWave;
@@ -1285,7 +1300,10 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             }
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
-            if (A.counts != nullptr) write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
+            if (A.counts != nullptr)
+                write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
+            else
+                put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0);
         }
         return;
     }
@@ -1311,6 +1329,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             atomicMin(&A.err[0], (long long)HOUGH_ERR_DATA);
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
+            if (A.counts == nullptr) put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0);
         }
         if (A.counts != nullptr) {
             // first invalid hit of the event (the only event of the call)
@@ -1548,16 +1567,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     if (threadIdx.x == 0) {
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
-        atomicAdd(&A.stats[0], evals);
-        atomicAdd(&A.stats[1], (unsigned long long)iter);
-        atomicMax(&A.stats[2], (unsigned long long)iter);
-        atomicAdd(&A.stats[3], (unsigned long long)passes);
-        atomicAdd(&A.stats[4], (unsigned long long)tiled);
-        atomicAdd(&A.stats[5], (unsigned long long)sh.n_trunc);
-        atomicAdd(&A.stats[6], (unsigned long long)sh.n_hotscan);
-        atomicAdd(&A.stats[7], (unsigned long long)hs_full);
-        atomicAdd(&A.stats[8], (unsigned long long)recounts);
-        atomicAdd(&A.stats[9], (unsigned long long)bigs);
+        put_ev_stats(A, e, evals, iter, passes, tiled, sh.n_trunc, sh.n_hotscan, hs_full, recounts, bigs);
     }
 }
 
@@ -1613,8 +1623,7 @@ __global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restri
                     g * NW + wave, groups * NW, A.g_hs + (size_t)e * A.hs_cap, A.g_cnt + e, A.hs_cap);
 }
 
-__global__ void k_reset(unsigned long long *stats, long long *err) {
-    if (threadIdx.x < kStats) stats[threadIdx.x] = 0ull;
+__global__ void k_reset(long long *err) {
     if (threadIdx.x == 0) {
         err[0] = 0;
         err[1] = 0x7fffffffffffffffll;
@@ -1631,11 +1640,20 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
     constexpr int NT = 1024;
     constexpr int NW = NT / kWave;
     __shared__ long long wc[NW], wh[NW];
+    __shared__ unsigned long long ws[NW][kEvStats + 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     long long carry_c = 0, carry_h = 0;
+    // per-event statistics: sums, and the largest iteration count
+    unsigned long long sum[kEvStats], max_it = 0ull;
+    for (int k = 0; k < kEvStats; ++k) sum[k] = 0ull;
     for (int base = 0; base < A.n_events; base += NT) {
         const int e = base + threadIdx.x;
+        if (e < A.n_events) {
+            for (int k = 0; k < kEvStats; ++k) sum[k] += A.ev_stats[(size_t)k * A.n_events + e];
+            const unsigned long long it = A.ev_stats[(size_t)kEvIters * A.n_events + e];
+            max_it = it > max_it ? it : max_it;
+        }
         const long long c = e < A.n_events ? A.ev_ncand[e] : 0;
         const long long h = e < A.n_events ? A.ev_nhits[e] : 0;
         long long ic = c, ih = h;
@@ -1667,25 +1685,39 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         carry_h += th;
         __syncthreads();
     }
+    for (int k = 0; k <= kEvStats; ++k) {
+        unsigned long long v = k < kEvStats ? sum[k] : max_it;
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const unsigned long long t = __shfl_xor(v, o, kWave);
+            v = k < kEvStats ? v + t : (t > v ? t : v);
+        }
+        if (lane == 0) ws[wave][k] = v;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        unsigned long long tot[kEvStats + 1];
+        for (int k = 0; k <= kEvStats; ++k) {
+            tot[k] = 0ull;
+            for (int u = 0; u < NW; ++u)
+                tot[k] = k < kEvStats ? tot[k] + ws[u][k] : (ws[u][k] > tot[k] ? ws[u][k] : tot[k]);
+        }
         const long long st = A.err[0];
         A.counts[HOUGH_COUNT_CANDIDATES] = st ? 0 : carry_c;
         A.counts[HOUGH_COUNT_HITS] = st ? 0 : carry_h;
         A.counts[HOUGH_COUNT_STATUS] = st;
         A.counts[HOUGH_COUNT_DETAIL] = A.err[1] == 0x7fffffffffffffffll ? -1 : A.err[1];
-        A.counts[HOUGH_COUNT_EVALS] = (long long)A.stats[0];
-        A.counts[HOUGH_COUNT_ITERS] = (long long)A.stats[1];
-        A.counts[HOUGH_COUNT_MAX_ITERS] = (long long)A.stats[2];
-        A.counts[HOUGH_COUNT_PASSES] = (long long)A.stats[3];
-        A.counts[HOUGH_COUNT_TILED] = (long long)A.stats[4];
-        A.counts[HOUGH_COUNT_TRUNCATIONS] = (long long)A.stats[5];
-        A.counts[HOUGH_COUNT_HOT_SCANS] = (long long)A.stats[6];
-        A.counts[HOUGH_COUNT_HOTSET_FULL] = (long long)A.stats[7];
-        A.counts[HOUGH_COUNT_RECOUNTS] = (long long)A.stats[8];
-        A.counts[HOUGH_COUNT_LARGE] = (long long)A.stats[9];
+        A.counts[HOUGH_COUNT_EVALS] = (long long)tot[kEvEvals];
+        A.counts[HOUGH_COUNT_ITERS] = (long long)tot[kEvIters];
+        A.counts[HOUGH_COUNT_MAX_ITERS] = (long long)tot[kEvStats];
+        A.counts[HOUGH_COUNT_PASSES] = (long long)tot[kEvPasses];
+        A.counts[HOUGH_COUNT_TILED] = (long long)tot[kEvTiled];
+        A.counts[HOUGH_COUNT_TRUNCATIONS] = (long long)tot[kEvTrunc];
+        A.counts[HOUGH_COUNT_HOT_SCANS] = (long long)tot[kEvHotScans];
+        A.counts[HOUGH_COUNT_HOTSET_FULL] = (long long)tot[kEvHotsetFull];
+        A.counts[HOUGH_COUNT_RECOUNTS] = (long long)tot[kEvRecounts];
+        A.counts[HOUGH_COUNT_LARGE] = (long long)tot[kEvLarge];
         for (int i = HOUGH_COUNT_LARGE + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
-        // leave the statistics and error words cleared for the next call
-        for (int i = 0; i < kStats; ++i) A.stats[i] = 0ull;
+        // leave the error words cleared for the next call
         A.err[0] = 0;
         A.err[1] = 0x7fffffffffffffffll;
     }
@@ -1757,8 +1789,8 @@ int find_lds_extra(int wg_threads, int hcap, int pkeep) {
     return 4 * hcap + 8 * (pkeep + hcap) + 4 * wg_threads;
 }
 
-hipError_t launch_reset(unsigned long long *stats, long long *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, stats, err);
+hipError_t launch_reset(long long *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, err);
     return hipGetLastError();
 }
 

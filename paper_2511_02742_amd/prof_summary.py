@@ -14,7 +14,7 @@ traffic figures; a key/value file next to it carries the figures the
 benchmark reports, with the hash of the kernel source they were taken from.
 
 python -m paper_2511_02742_amd.prof_summary --trace DIR [--fetch DIR --write DIR --copy-mib M]
-        --name NAME --command "..." [--command "..."]
+        --name NAME --command "..." [--command "..."] [--kernel k_find_cf --source hough_cf.hip]
 """
 from __future__ import annotations
 
@@ -34,9 +34,21 @@ KERNEL_SOURCE = os.path.join(PKG, "csrc", "hough_kernels.hip")
 COPY_KERNEL = "MulFunctor"
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
+def kernel_source_hash(source: str = KERNEL_SOURCE) -> str:
+    """sha256/16 of a kernel source file (csrc/ name or path)."""
+    path = source if os.path.isabs(source) else os.path.join(PKG, "csrc", os.path.basename(source))
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _is(name: str, kernel: str) -> bool:
+    # "k_find" must not match "k_find_cf": the template argument list or the
+    # end of the name follows the kernel's own name
+    i = name.find(kernel)
+    if i < 0:
+        return False
+    rest = name[i + len(kernel):]
+    return rest == "" or rest[0] in "<("
 
 
 def _short(name: str) -> str:
@@ -66,7 +78,7 @@ def dispatches_by_grid(trace_dir: str, kernel: str = "k_find"):
         raise FileNotFoundError("no kernel_trace.csv under %s" % trace_dir)
     out = defaultdict(list)
     for r in csv.DictReader(open(files[0])):
-        if kernel not in r["Kernel_Name"]:
+        if not _is(r["Kernel_Name"], kernel):
             continue
         key = (int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
         out[key].append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
@@ -100,7 +112,7 @@ def traffic(fetch_dir: str, write_dir: str, copy_mib: int, kernel: str = "k_find
             raise ValueError("no calibration kernel (%s) in %s" % (COPY_KERNEL, d))
         ref = max(copies) * 1024.0           # counter in KiB
         scale = copy_bytes / ref if ref > 0 else float("nan")
-        mine = [v for k, v in per.items() if kernel in names[k]]
+        mine = [v for k, v in per.items() if _is(names[k], kernel)]
         big = max(mine)
         batched = [v for v in mine if v >= 0.5 * big]
         res[label + "_bytes"] = statistics.median(batched) * 1024.0 * scale
@@ -118,22 +130,25 @@ def main():
     ap.add_argument("--name", required=True, help="summary base name under profiles/")
     ap.add_argument("--command", action="append", default=[], help="a command line that produced the data")
     ap.add_argument("--note", default="")
+    ap.add_argument("--kernel", default="k_find", help="kernel whose dispatches and traffic are summarised")
+    ap.add_argument("--source", default="hough_kernels.hip", help="its source file under csrc/")
     args = ap.parse_args()
 
     stats = kernel_stats(args.trace)
-    h = kernel_source_hash()
+    h = kernel_source_hash(args.source)
+    K = args.kernel
     lines = ["# %s" % args.name, ""]
     if args.note:
         lines += [args.note, ""]
-    lines += ["Kernel source hash (sha256/16 of csrc/hough_kernels.hip): `%s`" % h, "", "Commands:", ""]
+    lines += ["Kernel source hash (sha256/16 of csrc/%s): `%s`" % (args.source, h), "", "Commands:", ""]
     lines += ["    %s" % c for c in args.command] + [""]
     lines += ["| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
     for r in stats:
         lines.append("| %s | %d | %.2f | %.2f | %.2f | %.3f | %.1f |" % (
             r["name"], r["calls"], r["avg_ns"] / 1e3, r["min_ns"] / 1e3, r["max_ns"] / 1e3,
             r["total_ns"] / 1e6, r["pct"]))
-    grids = dispatches_by_grid(args.trace)
-    lines += ["", "k_find dispatches by launch size (the batched call is the largest grid):", "",
+    grids = dispatches_by_grid(args.trace, K)
+    lines += ["", "%s dispatches by launch size (the batched call is the largest grid):" % K, "",
               "| workgroups | threads/wg | dispatches | avg us | min us | max us |", "|---|---|---|---|---|---|"]
     for (gx, wx), d in sorted(grids.items(), key=lambda kv: -kv[0][0]):
         lines.append("| %d | %d | %d | %.2f | %.2f | %.2f |" % (gx // wx, wx, len(d), statistics.mean(d) / 1e3,
@@ -141,12 +156,12 @@ def main():
     kv = {"kernel_sha256_16": h}
     big = max(grids) if grids else None
     if big:
-        kv["batched_k_find_avg_us"] = "%.2f" % (statistics.mean(grids[big]) / 1e3)
+        kv["batched_%s_avg_us" % K] = "%.2f" % (statistics.mean(grids[big]) / 1e3)
     if args.fetch and args.write and args.copy_mib:
-        t = traffic(args.fetch, args.write, args.copy_mib)
-        lines += ["", "HBM traffic of the batched k_find launch (median over %d dispatches), from "
+        t = traffic(args.fetch, args.write, args.copy_mib, K)
+        lines += ["", "HBM traffic of the batched %s launch (median over %d dispatches), from "
                   "FETCH_SIZE / WRITE_SIZE scaled by a %d MiB device copy (scale fetch %.3f, write %.3f):"
-                  % (t["fetch_dispatches"], args.copy_mib, t["fetch_scale"], t["write_scale"]), "",
+                  % (K, t["fetch_dispatches"], args.copy_mib, t["fetch_scale"], t["write_scale"]), "",
                   "| read bytes | written bytes | total |", "|---|---|---|",
                   "| %.0f | %.0f | %.0f |" % (t["fetch_bytes"], t["write_bytes"], t["fetch_bytes"] + t["write_bytes"])]
         kv.update({"fetch_bytes_per_launch": "%.0f" % t["fetch_bytes"],
