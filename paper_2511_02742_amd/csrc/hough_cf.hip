@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hough_internal.h"
+#include "hough_wave.h"
 
 namespace hough {
 
@@ -86,31 +87,6 @@ __device__ __forceinline__ unsigned long long bin_key(uint32_t count, uint32_t f
 
 __device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
     return a > b ? a : b;
-}
-
-// One DPP step of the wave maximum: v and the value `ctrl` moves into this
-// lane (lanes the move does not reach keep their own).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long v) {
-    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-    const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, CTRL, ROW_MASK, 0xf, false);
-    const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, CTRL, ROW_MASK, 0xf, false);
-    return umax64(v, ((unsigned long long)ohi << 32) | olo);
-}
-
-// Largest value over the wave (every lane active), in registers: row_shr
-// 1, 2, 4, 8 leave each row's maximum in its lane 15, row_bcast 15 and 31
-// carry them up to lane 63.
-__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
-    v = dpp_max_step<0x111, 0xf>(v);
-    v = dpp_max_step<0x112, 0xf>(v);
-    v = dpp_max_step<0x114, 0xf>(v);
-    v = dpp_max_step<0x118, 0xf>(v);
-    v = dpp_max_step<0x142, 0xa>(v);
-    v = dpp_max_step<0x143, 0xc>(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 63);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 63);
-    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Hit i of the event if it is still in the pool: its (phi, z).

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hough_internal.h"
+#include "hough_wave.h"
 
 #include <algorithm>
 
@@ -474,7 +475,12 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     if (A.peak_mode == 0) {
         if (threadIdx.x == 0) sh.best = 0ull;
         __syncthreads();
-        for (int e = threadIdx.x; e < n_hs; e += NT) atomicMax(&sh.best, L.hs[e]);
+        // the largest key: per thread, per wave (DPP), then one LDS atomic
+        // per wave
+        unsigned long long m = 0ull;
+        for (int e = threadIdx.x; e < n_hs; e += NT) m = L.hs[e] > m ? L.hs[e] : m;
+        m = wave_max64(m);
+        if (lane_id() == 0 && m) atomicMax(&sh.best, m);
         __syncthreads();
         const unsigned long long best = sh.best;
         const int npk = best != 0ull ? 1 : 0;
