@@ -46,6 +46,7 @@ constexpr int kWave = 64;
 extern __shared__ __align__(16) uint32_t g_lds[];
 constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
 constexpr int kMaxLists = 5;  // row lists of the banded sweep: 2 w + 1 for w <= 2
+constexpr int kClaimBlockW = 8;  // alive-hit words up to which claims are resolved in registers
 
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1060,6 +1061,53 @@ __device__ __forceinline__ void claim_serial(const FindArgs &A, unsigned long lo
     }
 }
 
+// The same claims for at most kClaimBlockW words of alive hits, by one
+// wave: lane l holds peak p0 + l of a block of 64 peaks in key order and the
+// count of its matches not yet claimed. Counts only fall as peaks are taken,
+// so a peak below T now stays rejected: the wave visits only the lanes still
+// at T or above, lowest first. The lowest of them is taken (every earlier
+// taken peak is already out of its count); its unclaimed words (its match
+// words less the claimed ones, read at one address by every lane) become
+// claimed and come off the later lanes' counts. Most peaks of a pileup event
+// are rejected without a visit.
+__device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
+                                            int W, int nb) {
+    if (wave_id() != 0) return;
+    const int lane = lane_id();
+    const int T = (int)A.min_votes;
+    for (int p0 = 0; p0 < nb; p0 += kWave) {
+        const int p = p0 + lane;
+        const unsigned long long *mp = M + (size_t)(p < nb ? p : p0) * W;
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < kClaimBlockW; ++w)
+            if (w < W) cnt += __popcll(mp[w] & ~icl[w]);
+        int res = -1;
+        unsigned long long open = __ballot(p < nb && cnt >= T);
+        while (open) {
+            const int q = __ffsll((long long)open) - 1;
+            if (lane == q) res = cnt;
+            unsigned long long *mq = M + (size_t)(p0 + q) * W;
+            int drop = 0;
+#pragma unroll
+            for (int w = 0; w < kClaimBlockW; ++w) {
+                if (w < W) {
+                    const unsigned long long c = icl[w];
+                    const unsigned long long t = mq[w] & ~c;
+                    drop += __popcll(mp[w] & t);
+                    if (lane == 0) {
+                        mq[w] = t;
+                        icl[w] = c | t;
+                    }
+                }
+            }
+            if (lane > q) cnt -= drop;
+            open = __ballot(lane > q && p < nb && cnt >= T);
+        }
+        if (p < nb) pst[p] = res;
+    }
+}
+
 template <int NT>
 __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
@@ -1162,7 +1210,9 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         }
         __syncthreads();
         // B: which peaks claim which hits
-        if (rounds)
+        if (W <= kClaimBlockW)
+            claim_block(A, icl, M, pst, W, nb);
+        else if (rounds)
             claim_rounds<NT>(A, icl, M, pst, owner, W, nb, sh);
         else
             claim_serial<NT>(A, icl, M, pst, W, nb);
@@ -1650,16 +1700,8 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     long long carry_c = 0, carry_h = 0;
-    // per-event statistics: sums, and the largest iteration count
-    unsigned long long sum[kEvStats], max_it = 0ull;
-    for (int k = 0; k < kEvStats; ++k) sum[k] = 0ull;
     for (int base = 0; base < A.n_events; base += NT) {
         const int e = base + threadIdx.x;
-        if (e < A.n_events) {
-            for (int k = 0; k < kEvStats; ++k) sum[k] += A.ev_stats[(size_t)k * A.n_events + e];
-            const unsigned long long it = A.ev_stats[(size_t)kEvIters * A.n_events + e];
-            max_it = it > max_it ? it : max_it;
-        }
         const long long c = e < A.n_events ? A.ev_ncand[e] : 0;
         const long long h = e < A.n_events ? A.ev_nhits[e] : 0;
         long long ic = c, ih = h;
@@ -1691,8 +1733,15 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         carry_h += th;
         __syncthreads();
     }
+    // per-event statistics: word k summed over the events (k = kEvStats: the
+    // largest iteration count), one word at a time
     for (int k = 0; k <= kEvStats; ++k) {
-        unsigned long long v = k < kEvStats ? sum[k] : max_it;
+        const int src = k < kEvStats ? k : (int)kEvIters;
+        unsigned long long v = 0ull;
+        for (int e = threadIdx.x; e < A.n_events; e += NT) {
+            const unsigned long long x = A.ev_stats[(size_t)src * A.n_events + e];
+            v = k < kEvStats ? v + x : (x > v ? x : v);
+        }
         for (int o = kWave / 2; o > 0; o >>= 1) {
             const unsigned long long t = __shfl_xor(v, o, kWave);
             v = k < kEvStats ? v + t : (t > v ? t : v);
@@ -1700,13 +1749,16 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         if (lane == 0) ws[wave][k] = v;
     }
     __syncthreads();
+    // thread k combines word k over the waves
+    if (threadIdx.x <= kEvStats) {
+        const int k = threadIdx.x;
+        unsigned long long t = 0ull;
+        for (int u = 0; u < NW; ++u) t = k < kEvStats ? t + ws[u][k] : (ws[u][k] > t ? ws[u][k] : t);
+        ws[0][k] = t;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long tot[kEvStats + 1];
-        for (int k = 0; k <= kEvStats; ++k) {
-            tot[k] = 0ull;
-            for (int u = 0; u < NW; ++u)
-                tot[k] = k < kEvStats ? tot[k] + ws[u][k] : (ws[u][k] > tot[k] ? ws[u][k] : tot[k]);
-        }
+        const unsigned long long *tot = ws[0];
         const long long st = A.err[0];
         A.counts[HOUGH_COUNT_CANDIDATES] = st ? 0 : carry_c;
         A.counts[HOUGH_COUNT_HITS] = st ? 0 : carry_h;
