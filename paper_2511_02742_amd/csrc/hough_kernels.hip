@@ -539,18 +539,20 @@ __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restr
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
-    for (int e0 = wave * kWave; e0 < n_hs; e0 += NW * kWave) {
-        // 64 bins at once: lane l loads bin e0 + l and its (cos, sin), then
-        // the wave counts the bins one after another
+    // the bins are split evenly over the waves, at most 64 at a time: lane l
+    // loads bin e0 + l and its (cos, sin), then the wave counts the bins one
+    // after another
+    const int per = min(kWave, (n_hs + NW - 1) / NW);
+    for (int e0 = wave * per; e0 < n_hs; e0 += NW * per) {
         const int e = e0 + lane;
-        const unsigned long long key = e < n_hs ? hs[e] : 0ull;
+        const unsigned long long key = lane < per && e < n_hs ? hs[e] : 0ull;
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
         const int j = key != 0ull ? (int)(flat / (uint32_t)A.n_rho) : 0;
         const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
         const float2 t = cs[j];
         const unsigned long long live = __ballot(key != 0ull);
         unsigned long long out = 0ull;
-        const int nb = min(kWave, n_hs - e0);
+        const int nb = min(per, n_hs - e0);
         for (int i = 0; i < nb; ++i) {
             if (!((live >> i) & 1ull)) continue;
             const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.x), i));
