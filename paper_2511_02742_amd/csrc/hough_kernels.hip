@@ -489,8 +489,12 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
         __syncthreads();
         return npk;
     }
+    // at most half full; up to one eighth where the row buffers (hs_off
+    // bytes, ahead of the hot set) have room, which keeps the linear-probe
+    // runs of the window test short
     int log2n = 6;
     while ((1 << log2n) < 2 * n_hs) ++log2n;
+    while ((1 << log2n) < 8 * n_hs && (8 << (log2n + 1)) <= A.hs_off) ++log2n;
     const int ht = 1 << log2n;
     uint32_t *htk = L.tile;        // flat + 1, 0 = empty
     uint32_t *htc = L.tile + ht;   // count
