@@ -1371,7 +1371,8 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     }
     const int n = (int)n64;
 
-    // validate and put every hit in the pool
+    // validate, put every hit in the pool and write the first iteration's
+    // alive list (every hit, in order)
     int badhit = 0;
     for (int i = threadIdx.x; i < n; i += NT) {
         const int v = A.vane[b + i];
@@ -1379,6 +1380,10 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         if (v < 0 || v >= A.n_vanes || !(fabsf(zz) <= HOUGH_Z_LIMIT)) {
             badhit = 1;
             atomicMin(&A.err[1], (long long)(b + i));
+        } else {
+            A.aidx[b + i] = i;
+            A.aphi[b + i] = A.phi_v[v];
+            A.az[b + i] = zz;
         }
         A.state[b + i] = -1;
     }
@@ -1419,9 +1424,10 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     HitRegs h;
     for (;;) {
         if (A.max_iters > 0 && iter >= A.max_iters) break;
-        // alive list, in ascending hit order
-        int carry = 0;
-        for (int base = 0; base < n; base += NT) {
+        // alive list, in ascending hit order (written with the validation
+        // for the first iteration)
+        int carry = iter == 0 ? n : 0;
+        for (int base = 0; base < n && iter > 0; base += NT) {
             const int i = base + threadIdx.x;
             const bool alive = i < n && A.state[b + i] == -1;
             const unsigned long long m = __ballot(alive);
