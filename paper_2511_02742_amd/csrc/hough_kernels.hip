@@ -1745,20 +1745,27 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         carry_h += th;
         __syncthreads();
     }
-    // per-event statistics: word k summed over the events (k = kEvStats: the
-    // largest iteration count), one word at a time
+    // per-event statistics: every word summed over the events in one pass
+    // (k = kEvStats: the largest iteration count), then over the wave one
+    // word at a time
+    unsigned long long acc[kEvStats + 1];
+#pragma unroll
+    for (int k = 0; k <= kEvStats; ++k) acc[k] = 0ull;
+    for (int e = threadIdx.x; e < A.n_events; e += NT) {
+#pragma unroll
+        for (int k = 0; k < kEvStats; ++k) acc[k] += A.ev_stats[(size_t)k * A.n_events + e];
+        const unsigned long long it = A.ev_stats[(size_t)kEvIters * A.n_events + e];
+        acc[kEvStats] = it > acc[kEvStats] ? it : acc[kEvStats];
+    }
+#pragma unroll
     for (int k = 0; k <= kEvStats; ++k) {
-        const int src = k < kEvStats ? k : (int)kEvIters;
-        unsigned long long v = 0ull;
-        for (int e = threadIdx.x; e < A.n_events; e += NT) {
-            const unsigned long long x = A.ev_stats[(size_t)src * A.n_events + e];
-            v = k < kEvStats ? v + x : (x > v ? x : v);
-        }
+        unsigned long long v = acc[k];
         for (int o = kWave / 2; o > 0; o >>= 1) {
             const unsigned long long t = __shfl_xor(v, o, kWave);
             v = k < kEvStats ? v + t : (t > v ? t : v);
         }
         if (lane == 0) ws[wave][k] = v;
+        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     // thread k combines word k over the waves
