@@ -142,6 +142,7 @@ struct Shared {
     int slot;        // device-memory slot of a large event, or -1
     int nruns;       // runs of equal counts in a large event's peak list
     int rollc[16 * kMaxLists];  // fill of each wave's row lists (banded sweep)
+    int rlive;       // live bins the last recount tested
 };
 
 // LDS layout of k_find (dynamic part):
@@ -503,12 +504,18 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     __syncthreads();
     hash_insert<NT>(L.hs, n_hs, htk, htc, log2n);
     __syncthreads();
+    // A peak's bin is below T in the next iteration whatever the claims:
+    // taken, it loses every hit it voted with; rejected, fewer than T of its
+    // matches (a superset of its voters) were left unclaimed at its turn.
+    // So the peaks leave the hot set here, and the next iteration's recount
+    // skips them (the window test reads the hash table, not the hot set).
     for (int e = threadIdx.x; e < n_hs; e += NT) {
         const unsigned long long key = L.hs[e];
         if (key == 0ull) continue;
         if (window_peak(A, htk, htc, log2n, key)) {
             const int slot = atomicAdd(&sh.pcnt, 1);
             if (slot < A.pkeep + A.hcap) L.pbuf[slot] = key;
+            L.hs[e] = 0ull;
         }
     }
     __syncthreads();
@@ -539,7 +546,7 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
 // are marked dead (key 0).
 template <int NT>
 __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restrict__ cs, unsigned long long *hs, const HitRegs &h,
-                        const float2 *xh, int nx, int n_alive, int n_hs) {
+                        const float2 *xh, int nx, int n_alive, int n_hs, int *live_cnt) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
@@ -555,6 +562,7 @@ __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restr
         const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
         const float2 t = cs[j];
         const unsigned long long live = __ballot(key != 0ull);
+        if (lane == 0 && live) atomicAdd(live_cnt, __popcll(live));
         unsigned long long out = 0ull;
         const int nb = min(per, n_hs - e0);
         for (int i = 0; i < nb; ++i) {
@@ -1484,10 +1492,12 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                     __syncthreads();
                 } else if (hs_valid) {
                     // recount the previous hot set (no histogram sweep)
-                    recount<NT>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs);
-                    ++recounts;
-                    evals += (unsigned long long)n_hs * (unsigned long long)(h.nch * kWave);
+                    if (threadIdx.x == 0) sh.rlive = 0;
                     __syncthreads();
+                    recount<NT>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs, &sh.rlive);
+                    ++recounts;
+                    __syncthreads();
+                    evals += (unsigned long long)sh.rlive * (unsigned long long)(h.nch * kWave);
                 } else {
                     // row-stream sweep; a hot set larger than LDS holds
                     // sends the event to the large-event path below
