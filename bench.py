@@ -62,15 +62,37 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     from paper_2511_02742_amd import eventgen
-    from paper_2511_02742_amd.hough import HoughFinder
 
-    dev = torch.device("cuda", 0)
     t0 = time.time()
     batch = eventgen.pileup_batch(N_EVENTS, n_tracks=PILEUP, seed0=0)
     log("generated %d events in %.1f s: %s" % (N_EVENTS, time.time() - t0, eventgen.hit_histogram(batch)))
+
+    # ---- CPU oracle on a bounded sample, before anything touches the GPU
+    # (the all-cores figure starts worker processes)
+    cpu = cpu_all = None
+    if not args.no_cpu_baseline:
+        from oracle import OracleConfig, oracle_find
+        ocfg = OracleConfig()
+        n_done = 0
+        tc0 = time.perf_counter()
+        while n_done < N_EVENTS and (time.perf_counter() - tc0 < args.cpu_seconds or n_done < 16):
+            lo, hi = int(batch.offsets[n_done]), int(batch.offsets[n_done + 1])
+            oracle_find(ocfg, batch.z[lo:hi], batch.vane[lo:hi], event_id=n_done)
+            n_done += 1
+        tc = time.perf_counter() - tc0
+        cpu = {"value": round(n_done / tc, 2), "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": "first %d of the same %d pileup-50 events, one thread, %.1f s"
+                         % (n_done, N_EVENTS, tc)}
+        log("cpu oracle: %.1f events/s over %d events" % (n_done / tc, n_done))
+        cpu_all = oracle_all_cores(batch, args.cpu_seconds, log)
+
+    import torch
+
+    from paper_2511_02742_amd.hough import HoughFinder
+
+    dev = torch.device("cuda", 0)
     z = torch.from_numpy(batch.z).to(dev)
     vane = torch.from_numpy(batch.vane).to(dev)
     offs = torch.from_numpy(batch.offsets).to(dev)
@@ -108,6 +130,9 @@ def main():
     from paper_2511_02742_amd.hough import COUNT_NAMES
     info = dict(zip(COUNT_NAMES, (int(x) for x in out.counts.cpu().numpy())))
     assert info["status"] == 0, info
+    main_cand, main_hits, _ = out.to_host()
+    eff = eq5_efficiency(batch, main_cand, main_hits)
+    log("Eq. (5) efficiency: %s" % eff)
     wall = t2 - t1
     ms_per_step = 1e3 * wall / args.steps
     value = N_EVENTS * args.steps / wall
@@ -152,26 +177,24 @@ def main():
                 "evals_per_launch": info["evals"], "flops_per_eval": FLOPS_PER_VOTE,
                 "evals_per_s": round(info["evals"] / (kern_avg_ms * 1e-3), 1)}
 
-    # ---- CPU oracle on a bounded sample -----------------------------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import OracleConfig, oracle_find
-        ocfg = OracleConfig()
-        n_done = 0
-        tc0 = time.perf_counter()
-        while n_done < N_EVENTS and (time.perf_counter() - tc0 < args.cpu_seconds or n_done < 16):
-            lo, hi = int(batch.offsets[n_done]), int(batch.offsets[n_done + 1])
-            oracle_find(ocfg, batch.z[lo:hi], batch.vane[lo:hi], event_id=n_done)
-            n_done += 1
-        tc = time.perf_counter() - tc0
-        cpu = {"value": round(n_done / tc, 2), "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d of the same %d pileup-50 events, one thread, %.1f s"
-                         % (n_done, N_EVENTS, tc)}
-        log("cpu oracle: %.1f events/s over %d events" % (n_done / tc, n_done))
+
+    # ---- LDS atomic roofline of the finder's votes (the survey's denominator:
+    # every histogram vote is one LDS atomic add)
+    from paper_2511_02742_amd.hough import lds_peak
+    peak_cf = lds_peak(0)
+    peak_vote = lds_peak(1)
+    votes_s = info["votes"] / (kern_avg_ms * 1e-3)
+    lds = {"bound": "lds", "achieved": round(votes_s, 1), "unit": "lane atomics/s",
+           "peak": round(peak_cf, 1), "frac": round(votes_s / peak_cf, 4),
+           "peak_vote_pattern": round(peak_vote, 1), "frac_vote_pattern": round(votes_s / peak_vote, 4),
+           "votes_per_launch": info["votes"], "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
+           "note": "peak: conflict-free ds_add_u32 without return; vote pattern: random bins of a 1024-word "
+                   "row with return (hough_lds_peak, measured in this run)"}
+    log("LDS roofline: %s" % lds)
 
     served = serve_bench(args, f, log) if args.serve_events > 0 else None
     refit = refit_bench(args, f, log) if args.refit_events > 0 else None
-    coarse_fine = None if args.no_coarse_fine else coarse_fine_bench(args, batch, z, vane, offs, log)
+    coarse_fine = None if args.no_coarse_fine else coarse_fine_bench(args, batch, z, vane, offs, log, peak_vote)
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
@@ -189,8 +212,11 @@ def main():
         "speedup_batched_vs_plain": round(value / plain_rate, 2),
         "work": {k: info[k] for k in ("candidates", "hits", "evals", "iters", "max_iters", "passes", "tiled",
                                       "truncations", "hot_scans", "hotset_full", "recounts")},
+        "efficiency_eq5": eff,
         "roofline": roofline,
+        "lds_roofline": lds,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
         "served": served,
         "refit": refit,
         "coarse_fine": coarse_fine,
@@ -359,6 +385,43 @@ def refit_bench(args, finder, log):
     return res
 
 
+def _oracle_slice(args):
+    """Worker: the oracle over one contiguous slice of events for about
+    `seconds` (at least 4 events); returns (events done, seconds)."""
+    z, vane, offsets, seconds = args
+    from oracle import OracleConfig, oracle_find
+    cfg = OracleConfig()
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(offsets) - 1 and (time.perf_counter() - t0 < seconds or done < 4):
+        lo, hi = int(offsets[done]), int(offsets[done + 1])
+        oracle_find(cfg, z[lo:hi], vane[lo:hi])
+        done += 1
+    return done, time.perf_counter() - t0
+
+
+def oracle_all_cores(batch, seconds, log):
+    """The same single-thread oracle in independent worker processes (one per
+    core of the host's share, at most 16) over disjoint slices of the batch."""
+    import multiprocessing as mp
+    import numpy as np
+    workers = max(1, min(16, os.cpu_count() or 1))
+    bounds = np.linspace(0, N_EVENTS, workers + 1).astype(int)
+    jobs = []
+    for w in range(workers):
+        e0, e1 = bounds[w], bounds[w + 1]
+        lo, hi = int(batch.offsets[e0]), int(batch.offsets[e1])
+        jobs.append((batch.z[lo:hi].copy(), batch.vane[lo:hi].copy(), batch.offsets[e0:e1 + 1] - lo, seconds))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_slice, jobs)
+    done = sum(r[0] for r in res)
+    span = max(r[1] for r in res)
+    log("cpu oracle, %d processes: %.1f events/s" % (workers, done / span))
+    return {"value": round(done / span, 2), "unit": "events/s", "cores": workers, "kind": "oracle",
+            "sample": "%d independent single-thread processes over disjoint slices of the same %d pileup-50 "
+                      "events, %d events in %.1f s" % (workers, N_EVENTS, done, span)}
+
+
 def profiled_traffic(name, source):
     """HBM bytes per launch (read + written) from the committed counter
     summary profiles/<name>.txt, or None when it is missing or was taken from
@@ -376,6 +439,37 @@ def profiled_traffic(name, source):
     except (OSError, ValueError):
         pass
     return None
+
+
+def _has_run(vanes, length, n_vanes=40):
+    """Whether the vane set holds `length` consecutive vanes (cyclic)."""
+    return any(all((v + i) % n_vanes in vanes for i in range(length)) for v in vanes)
+
+
+def eq5_efficiency(batch, cand, hit_index, run=5):
+    """Track-finding efficiency of Eq. (5), N_found / N_all: a generated track
+    counts as found when one candidate holds its hits on `run` consecutive
+    vanes. Returned over all generated tracks and over the tracks whose own
+    hits span such a run (the ones a seed can find at all)."""
+    import numpy as np
+    found = set()
+    for cd in cand:
+        ev = batch.events[cd["event"]]
+        idx = hit_index[cd["hit_offset"]:cd["hit_offset"] + cd["n_hits"]]
+        tr, vn = ev.track[idx], ev.vane[idx]
+        for t in np.unique(tr[tr >= 0]):
+            if _has_run(set(vn[tr == t].tolist()), run):
+                found.add((int(cd["event"]), int(t)))
+    n_all = n_findable = n_found_findable = 0
+    for e, ev in enumerate(batch.events):
+        n_all += ev.n_tracks
+        for t in np.unique(ev.track[ev.track >= 0]):
+            if _has_run(set(ev.vane[ev.track == t].tolist()), run):
+                n_findable += 1
+                n_found_findable += (e, int(t)) in found
+    return {"found": len(found), "all_tracks": n_all, "findable_tracks": n_findable,
+            "efficiency": round(len(found) / max(n_all, 1), 4),
+            "efficiency_findable": round(n_found_findable / max(n_findable, 1), 4)}
 
 
 def seeded_fraction(batch, cand, hit_index, min_hits):
@@ -404,7 +498,7 @@ def seeded_fraction(batch, cand, hit_index, min_hits):
     return hit / max(findable, 1), findable
 
 
-def coarse_fine_bench(args, batch, z, vane, offs, log):
+def coarse_fine_bench(args, batch, z, vane, offs, log, lds_vote_peak=None):
     """The paper's two-stage histogram (18 x 100 coarse, 10 x 10 fine, on the
     180 x 1000 grid) on the same pileup-50 batch, against full-grid argmax and
     nms on the same grid: events/s, finder kernel time, Eq. (4) evaluations,
@@ -433,13 +527,18 @@ def coarse_fine_bench(args, batch, z, vane, offs, log):
         cand, hits, info = out.to_host()
         assert info["status"] == 0, info
         frac, findable = seeded_fraction(batch, cand, hits, 6)
+        e5 = eq5_efficiency(batch, cand, hits)
         kavg = kern_ms / max(launches, 1)
         res[name] = {"events_per_s": round(N_EVENTS * args.steps / wall, 1),
                      "ms_per_step": round(1e3 * wall / args.steps, 4), "kernel_avg_ms": round(kavg, 4),
                      "kernel": "k_find_cf" if name == "coarse_fine" else "k_find",
                      "evals": info["evals"], "evals_per_s": round(info["evals"] / (kavg * 1e-3), 1),
+                     "votes": info["votes"],
+                     "lds_frac_vote_pattern": round(info["votes"] / (kavg * 1e-3) / lds_vote_peak, 4)
+                     if lds_vote_peak else None,
                      "candidates": info["candidates"], "iters": info["iters"],
-                     "seeded_track_fraction": round(frac, 4)}
+                     "seeded_track_fraction": round(frac, 4),
+                     "efficiency_eq5": e5["efficiency"], "efficiency_eq5_findable": e5["efficiency_findable"]}
         res["findable_tracks"] = findable
         log("coarse-fine leg, %s: %s" % (name, res[name]))
     cf = res["coarse_fine"]

@@ -146,7 +146,10 @@ typedef struct {
                                       (hot set and peaks in device memory;
                                       mode 2: hits of events beyond 1024
                                       hits read from device memory)       */
-/* entries 14..15 are written as 0 */
+#define HOUGH_COUNT_VOTES 14        /* histogram votes cast by the finder kernel
+                                      (LDS atomic adds; the part of EVALS
+                                      that fills histograms there)        */
+/* entry 15 is written as 0 */
 
 /* Largest hit count of one event. */
 #define HOUGH_MAX_EVENT_HITS 131072
@@ -263,6 +266,22 @@ hough_status hough_autotune(const hough_config *base, int device, void *stream, 
                             int64_t n_hits_total, const int64_t *event_offsets, const float *z,
                             const int16_t *vane, int32_t repeats, hough_config *best, double *best_ms,
                             int32_t *n_tried);
+
+/*
+ * LDS atomic throughput of `device` (a measurement helper: the denominator of
+ * the finder's vote-rate roofline, since every histogram vote is one LDS
+ * atomic add). Launches two 1024-thread workgroups per compute unit that add
+ * 1 to LDS words, 8 atomics per thread per round for 4096 rounds, and times
+ * the launch with HIP events on `stream` (the best of two timed launches
+ * after a warm-up; synchronises the stream). mode 0: lane-consecutive
+ * addresses, no returned value (the conflict-free peak); mode 1:
+ * pseudo-random addresses inside each wave's 1024-word row, returning the
+ * old value (the finder's vote pattern). *lane_atomics_per_s receives the
+ * device-wide rate in lane operations per second. Allocates and frees a
+ * small device buffer. HOUGH_ERR_INVALID_ARG for a bad device, mode or null
+ * pointer; HOUGH_ERR_DEVICE if a HIP call fails.
+ */
+hough_status hough_lds_peak(int device, void *stream, int mode, double *lane_atomics_per_s);
 
 /*
  * Served form: a request loop with continuous batching.

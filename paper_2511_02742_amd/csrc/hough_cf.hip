@@ -318,6 +318,7 @@ __device__ void put_ev_stats(const FindArgs &A, int e, const CfStats &st) {
     p[kEvIters * ne] = (unsigned long long)st.iter;
     p[kEvPasses * ne] = (unsigned long long)st.passes;
     p[kEvLarge * ne] = (unsigned long long)st.unstaged;
+    p[kEvVotes * ne] = st.evals;  // every evaluation here is an LDS atomic
 }
 
 __device__ void write_error_counts(int64_t *counts, long long status, long long detail) {
@@ -441,6 +442,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
             A.counts[HOUGH_COUNT_PASSES] = st.passes;
             for (int i = HOUGH_COUNT_TILED; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
             A.counts[HOUGH_COUNT_LARGE] = st.unstaged;
+            A.counts[HOUGH_COUNT_VOTES] = (long long)st.evals;
         }
         return;
     }

@@ -655,6 +655,22 @@ hough_status hough_launch_shape(const void *ctx, int32_t *tile_rows, int32_t *wg
     return HOUGH_OK;
 }
 
+hough_status hough_lds_peak(int device, void *stream, int mode, double *lane_atomics_per_s) {
+    if (!lane_atomics_per_s || (mode != 0 && mode != 1))
+        return fail(nullptr, HOUGH_ERR_INVALID_ARG, "hough_lds_peak: mode must be 0 or 1, output non-null");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, HOUGH_ERR_INVALID_ARG, "no such device");
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return fail(nullptr, HOUGH_ERR_DEVICE, "hipGetDeviceProperties failed");
+    hipError_t st = hough::lds_atomic_rate(mode, static_cast<hipStream_t>(stream), prop.multiProcessorCount,
+                                           lane_atomics_per_s);
+    if (st != hipSuccess) return fail(nullptr, HOUGH_ERR_DEVICE, std::string("LDS probe failed: ") + hipGetErrorString(st));
+    return HOUGH_OK;
+}
+
 hough_status hough_set_timing(void *ctx, int enable) {
     Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;

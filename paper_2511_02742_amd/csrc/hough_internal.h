@@ -29,6 +29,7 @@ enum EvStat {
     kEvHotsetFull,    // row-stream sweeps whose hot set overflowed
     kEvRecounts,      // iterations served by a hot-set recount
     kEvLarge,         // iterations in the large-event path
+    kEvVotes,         // histogram votes cast by the kernel (LDS atomic adds)
     kEvStats
 };
 
@@ -140,6 +141,10 @@ hipError_t find_blocks_per_cu(int wg_threads, int lds_bytes, int *blocks);
 // LDS bytes of k_find beyond the tile (hot list, peak lists, dummies).
 int find_lds_extra(int wg_threads, int hcap, int pkeep);
 hipError_t set_dump_lds_limit(int lds_bytes);
+
+// LDS atomic rate probe (hough_probe.hip): mode 0 conflict-free without
+// return, mode 1 random rows with return; lane operations per second.
+hipError_t lds_atomic_rate(int mode, hipStream_t s, int n_cu, double *lane_ops_per_s);
 
 // Coarse-to-fine finder (hough_cf.hip): one workgroup per event; events of
 // at most kCfStage hits keep their hits and pool flags in LDS.

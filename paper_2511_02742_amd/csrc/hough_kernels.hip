@@ -1306,7 +1306,7 @@ __device__ void write_error_counts(int64_t *counts, long long status, long long 
 
 // The event's statistics words (multi-event calls; the scan kernel sums them).
 __device__ void put_ev_stats(const FindArgs &A, int e, unsigned long long evals, int iter, int passes, int tiled,
-                             int trunc, int hotscan, int hs_full, int recounts, int bigs) {
+                             int trunc, int hotscan, int hs_full, int recounts, int bigs, unsigned long long votes) {
     unsigned long long *p = A.ev_stats + e;
     const size_t ne = (size_t)A.n_events;
     p[kEvEvals * ne] = evals;
@@ -1318,6 +1318,7 @@ __device__ void put_ev_stats(const FindArgs &A, int e, unsigned long long evals,
     p[kEvHotsetFull * ne] = (unsigned long long)hs_full;
     p[kEvRecounts * ne] = (unsigned long long)recounts;
     p[kEvLarge * ne] = (unsigned long long)bigs;
+    p[kEvVotes * ne] = votes;
 }
 
 template <int NT>
@@ -1373,7 +1374,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             if (A.counts != nullptr)
                 write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
             else
-                put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0);
+                put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0, 0ull);
         }
         return;
     }
@@ -1404,7 +1405,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             atomicMin(&A.err[0], (long long)HOUGH_ERR_DATA);
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
-            if (A.counts == nullptr) put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0);
+            if (A.counts == nullptr) put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0, 0ull);
         }
         if (A.counts != nullptr) {
             // first invalid hit of the event (the only event of the call)
@@ -1420,6 +1421,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     }
 
     unsigned long long evals = 0;
+    unsigned long long votes = 0;  // of them, histogram votes cast here (LDS atomics)
     int iter = 0;
     int passes = 0;
     int tiled = 0, hs_full = 0, recounts = 0;
@@ -1510,6 +1512,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                     hs_valid = n_hs <= A.hs_cap;
                     hs_full += hs_valid ? 0 : 1;
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                    votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                 }
                 if (hs_valid) {
                     const int npk = hotset_peaks<NT>(A, L, n_hs, sh);
@@ -1545,6 +1548,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                     band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
                     sync_global();
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+                    votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                     int npk = -1;
                     if (sh.big_ovf == 0) {
                         if (A.peak_mode == 0) {
@@ -1574,6 +1578,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         if (!done) {
             hs_valid = false;
             evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
+            votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
         }
         unsigned long long ceil_key = ~0ull;
         for (; !done;) {
@@ -1638,14 +1643,15 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             A.counts[HOUGH_COUNT_HOTSET_FULL] = hs_full;
             A.counts[HOUGH_COUNT_RECOUNTS] = recounts;
             A.counts[HOUGH_COUNT_LARGE] = bigs;
-            for (int i = HOUGH_COUNT_LARGE + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+            A.counts[HOUGH_COUNT_VOTES] = (long long)votes;
+            A.counts[HOUGH_COUNT_VOTES + 1] = 0;
         }
         return;
     }
     if (threadIdx.x == 0) {
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
-        put_ev_stats(A, e, evals, iter, passes, tiled, sh.n_trunc, sh.n_hotscan, hs_full, recounts, bigs);
+        put_ev_stats(A, e, evals, iter, passes, tiled, sh.n_trunc, sh.n_hotscan, hs_full, recounts, bigs, votes);
     }
 }
 
@@ -1803,7 +1809,8 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         A.counts[HOUGH_COUNT_HOTSET_FULL] = (long long)tot[kEvHotsetFull];
         A.counts[HOUGH_COUNT_RECOUNTS] = (long long)tot[kEvRecounts];
         A.counts[HOUGH_COUNT_LARGE] = (long long)tot[kEvLarge];
-        for (int i = HOUGH_COUNT_LARGE + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+        A.counts[HOUGH_COUNT_VOTES] = (long long)tot[kEvVotes];
+        A.counts[HOUGH_COUNT_VOTES + 1] = 0;
         // leave the error words cleared for the next call
         A.err[0] = 0;
         A.err[1] = 0x7fffffffffffffffll;

@@ -26,7 +26,7 @@ HOUGH_ERR_DATA = -6
 
 HOUGH_COUNTS = 16
 COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_iters", "passes",
-               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "r14", "r15")
+               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "votes", "r15")
 
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
@@ -34,7 +34,7 @@ EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_outpu
            "hough_autotune", "hough_server_create", "hough_server_destroy", "hough_server_clock",
            "hough_server_submit", "hough_server_poll", "hough_server_drain", "hough_server_get_stats",
            "hough_refit_gather", "hough_refit_init", "hough_refit_chi2", "hough_refit_grad",
-           "hough_refit_gauss_newton", "hough_status_string", "hough_last_error")
+           "hough_refit_gauss_newton", "hough_lds_peak", "hough_status_string", "hough_last_error")
 
 cand_dtype = np.dtype([("event", "<i4"), ("iter", "<i4"), ("theta_bin", "<i4"), ("rho_bin", "<i4"),
                        ("peak_votes", "<u4"), ("n_hits", "<u4"), ("hit_offset", "<i8"),
@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     lib.hough_set_timing.restype = st
     lib.hough_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), ctypes.c_int]
     lib.hough_timing.restype = st
+    lib.hough_lds_peak.argtypes = [ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.hough_lds_peak.restype = st
     lib.hough_graph_create.argtypes = [P, I32, I64, P, P, P, P, I64, P, I64, P, ctypes.POINTER(P)]
     lib.hough_graph_create.restype = st
     lib.hough_graph_launch.argtypes = [P, P]
@@ -369,6 +371,19 @@ class FindGraph:
             self.close()
         except Exception:
             pass
+
+
+def lds_peak(mode: int, device: int = 0, stream=None) -> float:
+    """LDS atomic lane operations per second of the device (hough_lds_peak):
+    mode 0 conflict-free without return, mode 1 the finder's vote pattern."""
+    import torch
+    lib = load_library()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    out = ctypes.c_double()
+    st = lib.hough_lds_peak(device, ctypes.c_void_p(s.cuda_stream), mode, ctypes.byref(out))
+    if st != HOUGH_OK:
+        raise HoughError(st, lib.hough_last_error(None).decode())
+    return out.value
 
 
 def autotune(z, vane, offsets, device: int = 0, repeats: int = 3, stream=None, **overrides):

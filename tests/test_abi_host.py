@@ -198,3 +198,12 @@ def test_refit_calls_reject_bad_arguments_without_a_device():
     assert lib.hough_refit_gather(None, 1, None, None, None, None, None, None, None, None, None, None) == E
     # nothing to do is not an error
     assert lib.hough_refit_chi2(None, 0, None, None, None, None, 40, None, None, None, 0.055, None) == 0
+
+
+def test_lds_peak_rejects_bad_arguments_without_a_device():
+    import ctypes as C
+    from paper_2511_02742_amd import hough
+    lib = hough.load_library()
+    out = C.c_double()
+    assert lib.hough_lds_peak(0, None, 2, C.byref(out)) == hough.HOUGH_ERR_INVALID_ARG
+    assert lib.hough_lds_peak(0, None, 0, None) == hough.HOUGH_ERR_INVALID_ARG

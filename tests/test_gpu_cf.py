@@ -26,6 +26,7 @@ def check(batch, what="", **kw):
     assert_same(got, want, what)
     info = got[2]
     assert info["evals"] == expected_evals(f.config, batch.offsets, want.cand), (what, info["evals"])
+    assert info["votes"] == info["evals"]          # every evaluation is an LDS vote here
     assert info["max_iters"] == want.n_iters, what
     # one candidate per iteration: no iteration ends without one
     assert info["iters"] == info["candidates"], what

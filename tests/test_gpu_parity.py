@@ -397,3 +397,20 @@ def test_autotune_picks_a_shape_that_matches(gpu_available):
     f = HoughFinder(0, config=best)
     got = f.find_host(b.z, b.vane, b.offsets)
     assert_same(got, oracle_find_batch(_ocfg(f.config), b.offsets, b.z, b.vane), "autotuned")
+
+
+def test_lds_peak_probe(gpu_available):
+    # the roofline denominator: both patterns run and the conflict-free one
+    # is the faster
+    from paper_2511_02742_amd.hough import lds_peak
+    p0, p1 = lds_peak(0), lds_peak(1)
+    assert p0 > 0 and p1 > 0 and p0 >= p1
+
+
+def test_vote_count_is_the_sweeps(gpu_available):
+    # one full sweep per event of the pileup-50 set: every hit votes once per
+    # theta row in the first iteration, and later iterations recount
+    b = eventgen.pileup_batch(64, seed0=8100)
+    f = finder()
+    _, _, info = run_batch(f, b)
+    assert info["votes"] >= b.n_hits * f.config.n_theta and info["votes"] <= info["evals"]
