@@ -23,6 +23,11 @@ namespace {
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
+// one-event calls split their first sweep over this many 256-thread
+// workgroups when the configuration leaves the split to the library: the
+// event's latency is then the sweep's spread over several CUs
+constexpr int kSingleSweepGroups = 32;
+constexpr int kSingleSweepThreads = 256;
 }  // namespace
 thread_local std::string g_last_global_error;
 
@@ -227,6 +232,12 @@ hough_status choose_shape(Ctx &c, std::string &why) {
             return HOUGH_ERR_DEVICE;
         }
     }
+    c.single_split = 0;
+    if (c.stream_ok && g.sweep_groups == 0 && g.peak_mode != 2) {
+        const int sl = hough::sweep_lds_bytes(kSingleSweepThreads, c.pitch);
+        if (sl + kStaticLds <= lds_max && hough::set_sweep_lds_limit(kSingleSweepThreads, sl) == hipSuccess)
+            c.single_split = 1;
+    }
     int drows = std::min(g.n_theta, std::max(1, (lds_max - kStaticLds) / row_bytes));
     c.dump_rows = std::min(drows, 64);
     c.dump_lds = c.dump_rows * row_bytes;
@@ -275,7 +286,9 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     const size_t o_enc = take(4 * ne), o_enh = take(4 * ne), o_eco = take(8 * ne), o_eho = take(8 * ne);
     const size_t o_evst = take(8 * (size_t)hough::kEvStats * ne), o_err = take(8 * 4), o_offs = take(8 * 4);
     const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
-    const size_t o_ghs = c.sweep_groups > 0 ? take(8 * (size_t)ne * (size_t)std::max(c.hs_cap, 1)) : 0;
+    // split-sweep hot lists: one per event, or one for the one-event split
+    const int64_t ghs_events = c.sweep_groups > 0 ? ne : (c.single_split ? 1 : 0);
+    const size_t o_ghs = ghs_events > 0 ? take(8 * (size_t)ghs_events * (size_t)std::max(c.hs_cap, 1)) : 0;
     // large-event slots: no more workgroups than events, nor than fit the
     // device at once, hold one at a time
     const int32_t slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ne, std::max(c.max_resident, 1)));
@@ -308,7 +321,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     w.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
     w.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
     w.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
-    w.g_hs = c.sweep_groups > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
+    w.g_hs = ghs_events > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
     w.pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
     w.pool = reinterpret_cast<unsigned char *>(base + o_pool);
     w.pool_slots = slots;
@@ -400,7 +413,12 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         a.cand_ws = cand;
         a.hits_ws = hit_index;
     }
-    if (a.g_hs != nullptr && n_events > 0) {
+    if (single && c.single_split && a.g_hs == nullptr) {
+        // one event: its first sweep spread over several workgroups
+        a.g_hs = w.g_hs;
+        hipError_t ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
+        if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
+    } else if (a.g_hs != nullptr && n_events > 0) {
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
