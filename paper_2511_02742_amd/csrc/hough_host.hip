@@ -23,11 +23,12 @@ namespace {
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
-// one-event calls split their first sweep over this many 256-thread
-// workgroups when the configuration leaves the split to the library: the
-// event's latency is then the sweep's spread over several CUs
+// calls of at most kSmallCall events split each event's first sweep over
+// this many 256-thread workgroups when the configuration leaves the split to
+// the library: an event's latency is then its sweep spread over several CUs
 constexpr int kSingleSweepGroups = 32;
 constexpr int kSingleSweepThreads = 256;
+constexpr int kSmallCall = 8;
 }  // namespace
 thread_local std::string g_last_global_error;
 
@@ -287,7 +288,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     const size_t o_evst = take(8 * (size_t)hough::kEvStats * ne), o_err = take(8 * 4), o_offs = take(8 * 4);
     const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
     // split-sweep hot lists: one per event, or one for the one-event split
-    const int64_t ghs_events = c.sweep_groups > 0 ? ne : (c.single_split ? 1 : 0);
+    const int64_t ghs_events = c.sweep_groups > 0 ? ne : (c.single_split ? std::min<int64_t>(ne, kSmallCall) : 0);
     const size_t o_ghs = ghs_events > 0 ? take(8 * (size_t)ghs_events * (size_t)std::max(c.hs_cap, 1)) : 0;
     // large-event slots: no more workgroups than events, nor than fit the
     // device at once, hold one at a time
@@ -413,8 +414,8 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         a.cand_ws = cand;
         a.hits_ws = hit_index;
     }
-    if (single && c.single_split && a.g_hs == nullptr) {
-        // one event: its first sweep spread over several workgroups
+    if (n_events > 0 && n_events <= kSmallCall && c.single_split && a.g_hs == nullptr) {
+        // a few events: each one's first sweep spread over several workgroups
         a.g_hs = w.g_hs;
         hipError_t ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));

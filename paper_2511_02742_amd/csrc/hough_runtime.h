@@ -57,7 +57,7 @@ struct Ctx {
     // launch shape
     int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
     int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
-    int single_split = 0;                     // one-event calls split their first sweep
+    int single_split = 0;                     // calls of a few events split their first sweeps
     int stream_ok = 0, hs_off = 0, sorted_off = 0;
     int big_pk = 0;                           // peak entries per large-event slot
     int big_sort = 0;                         // longest equal-count run sorted in LDS
