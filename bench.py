@@ -3,9 +3,15 @@
 One step = one call of the finder (the whole find-and-remove hot path) over a
 batch of 4096 synthetic pileup-50 events already resident in HBM (1024 x 1024
 uint32 histogram, T = 6, window peaks with w = 1). Reports batched events/s
-as the value, the plain one-event-per-call rate and latency percentiles
-beside it, the finder kernel's roofline figures and the CPU oracle's rate on
-a bounded sample of the same events.
+as the value, and beside it:
+  * the plain one-event-per-call rate and latency percentiles;
+  * the finder kernel's roofline figures: VALU ("roofline"), the LDS atomic
+    rate of its votes against the device's measured rate ("lds_roofline"),
+    HBM traffic from the committed rocprofv3 counter summary;
+  * the CPU oracle on one core and on every core of the host's share, both
+    before the GPU is touched;
+  * the Eq. (5) track-finding efficiency on the generator truth;
+  * the served stream, the helix refit and the coarse-to-fine search legs.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--plain-events P]
 """
