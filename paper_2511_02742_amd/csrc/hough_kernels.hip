@@ -1075,50 +1075,82 @@ __device__ __forceinline__ void claim_serial(const FindArgs &A, unsigned long lo
     }
 }
 
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int l) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // The same claims for at most kClaimBlockW words of alive hits, by one
-// wave: lane l holds peak p0 + l of a block of 64 peaks in key order and the
-// count of its matches not yet claimed. Counts only fall as peaks are taken,
-// so a peak below T now stays rejected: the wave visits only the lanes still
-// at T or above, lowest first. The lowest of them is taken (every earlier
-// taken peak is already out of its count); its unclaimed words (its match
-// words less the claimed ones, read at one address by every lane) become
-// claimed and come off the later lanes' counts. Most peaks of a pileup event
-// are rejected without a visit.
+// wave: lane l holds peak p0 + l of a block of 64 peaks in key order, its
+// match words in registers and the count of its matches not yet claimed.
+// Counts only fall as peaks are taken, so a peak below T now stays rejected:
+// the wave visits only the lanes still at T or above, lowest first. The
+// lowest of them is taken (every earlier taken peak is already out of its
+// count); its unclaimed words (its match words, read from its lane, less the
+// claimed words, which are wave-uniform scalars) become claimed and come off
+// the later lanes' counts. Most peaks of a pileup event are rejected without
+// a visit. Only the taken peaks' words and the claimed words go back to LDS.
 __device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
                                             int W, int nb) {
     if (wave_id() != 0) return;
     const int lane = lane_id();
     const int T = (int)A.min_votes;
+    // the claimed words and each lane's match words stay in registers for a
+    // block of 64 peaks; the taken peak's words reach the others by readlane
+    unsigned long long c[kClaimBlockW];
+#pragma unroll
+    for (int w = 0; w < kClaimBlockW; ++w) {
+        // an unconditional (clamped) load: a load under the select made the
+        // backend emit an invalid aperture compare
+        const unsigned long long x = uniform64(icl[min(w, W - 1)]);
+        c[w] = w < W ? x : 0ull;
+    }
     for (int p0 = 0; p0 < nb; p0 += kWave) {
         const int p = p0 + lane;
-        const unsigned long long *mp = M + (size_t)(p < nb ? p : p0) * W;
+        unsigned long long *mp = M + (size_t)(p < nb ? p : p0) * W;
+        unsigned long long m[kClaimBlockW];
         int cnt = 0;
 #pragma unroll
-        for (int w = 0; w < kClaimBlockW; ++w)
-            if (w < W) cnt += __popcll(mp[w] & ~icl[w]);
+        for (int w = 0; w < kClaimBlockW; ++w) {
+            m[w] = w < W ? mp[w] : 0ull;
+            cnt += __popcll(m[w] & ~c[w]);
+        }
         int res = -1;
         unsigned long long open = __ballot(p < nb && cnt >= T);
         while (open) {
             const int q = __ffsll((long long)open) - 1;
-            if (lane == q) res = cnt;
-            unsigned long long *mq = M + (size_t)(p0 + q) * W;
             int drop = 0;
 #pragma unroll
             for (int w = 0; w < kClaimBlockW; ++w) {
-                if (w < W) {
-                    const unsigned long long c = icl[w];
-                    const unsigned long long t = mq[w] & ~c;
-                    drop += __popcll(mp[w] & t);
-                    if (lane == 0) {
-                        mq[w] = t;
-                        icl[w] = c | t;
-                    }
-                }
+                const unsigned long long t = readlane64(m[w], q) & ~c[w];
+                drop += __popcll(m[w] & t);
+                c[w] |= t;
+                if (lane == q) m[w] = t;
             }
+            if (lane == q) res = cnt;
             if (lane > q) cnt -= drop;
             open = __ballot(lane > q && p < nb && cnt >= T);
         }
-        if (p < nb) pst[p] = res;
+        if (p < nb) {
+            pst[p] = res;
+            if (res >= 0) {
+#pragma unroll
+                for (int w = 0; w < kClaimBlockW; ++w)
+                    if (w < W) mp[w] = m[w];
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < kClaimBlockW; ++w)
+            if (w < W) icl[w] = c[w];
     }
 }
 
