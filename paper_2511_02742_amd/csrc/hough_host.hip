@@ -22,6 +22,7 @@ namespace rt {
 namespace {
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
+static_assert(kHotCap % 4 == 0, "the finder reads its peak list, placed after the hot list, 16 bytes at a time");
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
 // calls of at most kSmallCall events split each event's first sweep over
 // this many 256-thread workgroups when the configuration leaves the split to

@@ -526,11 +526,18 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     int G = 1;
     while (G < kWave && 2 * G * npk <= NT) G *= 2;
     const int g = threadIdx.x & (G - 1);
+    // two keys per 16-byte load (the peak list starts 16-byte aligned)
+    const ulonglong2 *pb2 = reinterpret_cast<const ulonglong2 *>(L.pbuf);
+    const int npair = npk >> 1;
     for (int p = threadIdx.x / G; p < npk; p += NT / G) {
         const unsigned long long key = L.pbuf[p];
         int r = 0;
 #pragma unroll 4
-        for (int q = g; q < npk; q += G) r += L.pbuf[q] > key ? 1 : 0;
+        for (int q = g; q < npair; q += G) {
+            const ulonglong2 x = pb2[q];
+            r += (x.x > key ? 1 : 0) + (x.y > key ? 1 : 0);
+        }
+        if ((npk & 1) && g == 0) r += L.pbuf[npk - 1] > key ? 1 : 0;
         for (int m = 1; m < G; m <<= 1) r += __shfl_xor(r, m);
         if (g == 0) L.sorted[r] = key;
     }
@@ -1361,6 +1368,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     Lds L;
     L.tile = reinterpret_cast<uint32_t *>(lds);
     L.hot = reinterpret_cast<uint32_t *>(lds + A.tile_bytes);
+    // 16-byte aligned: tile_bytes is a multiple of 16 and hcap of 4
     L.pbuf = reinterpret_cast<unsigned long long *>(lds + A.tile_bytes + 4 * A.hcap);
     L.dummy = reinterpret_cast<uint32_t *>(L.pbuf + (A.pkeep + A.hcap));
     L.hs = reinterpret_cast<unsigned long long *>(lds + A.hs_off);
