@@ -416,10 +416,22 @@ __device__ __forceinline__ uint32_t hs_hash(uint32_t flat, int log2n) {
     return (flat * 2654435761u) >> (32 - log2n);
 }
 
-// Window test of one bin >= T against the hash table of the bins >= T
-// (htk: flat + 1, 0 = empty; htc: count): a neighbour absent from the table
-// is below T and cannot beat the bin.
-__device__ __forceinline__ bool window_peak(const FindArgs &A, const uint32_t *htk, const uint32_t *htc, int log2n,
+// Hash table of the bins >= T: one 64-bit slot per bin, (flat + 1) << 32 |
+// count, 0 = empty, so a probe is one LDS load.
+__device__ __forceinline__ uint32_t ht_count(const unsigned long long *ht, uint32_t mask, uint32_t f2,
+                                             uint32_t slot, unsigned long long v) {
+    for (;;) {
+        if (v == 0ull) return 0u;
+        if ((uint32_t)(v >> 32) == f2 + 1u) return (uint32_t)v;
+        slot = (slot + 1u) & mask;
+        v = ht[slot];
+    }
+}
+
+// Window test of one bin >= T against the hash table: a neighbour absent
+// from the table is below T and cannot beat the bin; a neighbour with a
+// lower flat index wins ties.
+__device__ __forceinline__ bool window_peak(const FindArgs &A, const unsigned long long *ht, int log2n,
                                             unsigned long long key) {
     const uint32_t c = (uint32_t)(key >> 32);
     const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
@@ -428,6 +440,29 @@ __device__ __forceinline__ bool window_peak(const FindArgs &A, const uint32_t *h
     const int w = A.nms_radius;
     const uint32_t mask = (1u << log2n) - 1u;
     bool peak = true;
+    if (w == 1) {
+        // the eight first probes are issued together
+        uint32_t f2[8], slot[8];
+        unsigned long long v[8];
+        bool ok[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int d = u < 4 ? u : u + 1;  // 3 x 3 window less its centre
+            const int jj = j + d / 3 - 1;
+            const int kk = k + d % 3 - 1;
+            ok[u] = jj >= 0 && jj < A.n_theta && kk >= 0 && kk < A.n_rho;
+            f2[u] = (uint32_t)(jj * A.n_rho + kk);
+            slot[u] = hs_hash(f2[u], log2n);
+            v[u] = ht[slot[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (!ok[u]) continue;
+            const uint32_t c2 = ht_count(ht, mask, f2[u], slot[u], v[u]);
+            if (c2 > c || (c2 == c && f2[u] < flat)) peak = false;
+        }
+        return peak;
+    }
     for (int dr = -w; dr <= w; ++dr) {
         const int jj = j + dr;
         if (jj < 0 || jj >= A.n_theta) continue;
@@ -435,18 +470,8 @@ __device__ __forceinline__ bool window_peak(const FindArgs &A, const uint32_t *h
             const int kk = k + dk;
             if (kk < 0 || kk >= A.n_rho || (dr == 0 && dk == 0)) continue;
             const uint32_t f2 = (uint32_t)(jj * A.n_rho + kk);
-            uint32_t slot = hs_hash(f2, log2n);
-            uint32_t c2 = 0u;
-            for (;;) {
-                const uint32_t kf = htk[slot];
-                if (kf == 0u) break;
-                if (kf == f2 + 1u) {
-                    c2 = htc[slot];
-                    break;
-                }
-                slot = (slot + 1u) & mask;
-            }
-            // a neighbour with a lower flat index wins ties
+            const uint32_t slot = hs_hash(f2, log2n);
+            const uint32_t c2 = ht_count(ht, mask, f2, slot, ht[slot]);
             if (c2 > c || (c2 == c && f2 < flat)) peak = false;
         }
     }
@@ -455,16 +480,15 @@ __device__ __forceinline__ bool window_peak(const FindArgs &A, const uint32_t *h
 
 // Inserts the live keys of hot set hs[0, n_hs) into the hash table.
 template <int NT>
-__device__ __forceinline__ void hash_insert(const unsigned long long *hs, int n_hs, uint32_t *htk, uint32_t *htc,
-                                           int log2n) {
+__device__ __forceinline__ void hash_insert(const unsigned long long *hs, int n_hs, unsigned long long *ht, int log2n) {
     const uint32_t mask = (1u << log2n) - 1u;
     for (int e = threadIdx.x; e < n_hs; e += NT) {
         const unsigned long long key = hs[e];
         if (key == 0ull) continue;
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+        const unsigned long long entry = ((unsigned long long)(flat + 1u) << 32) | (key >> 32);
         uint32_t slot = hs_hash(flat, log2n);
-        while (atomicCAS(&htk[slot], 0u, flat + 1u) != 0u) slot = (slot + 1u) & mask;
-        htc[slot] = (uint32_t)(key >> 32);
+        while (atomicCAS(&ht[slot], 0ull, entry) != 0ull) slot = (slot + 1u) & mask;
     }
 }
 
@@ -497,12 +521,11 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     while ((1 << log2n) < 2 * n_hs) ++log2n;
     while ((1 << log2n) < 8 * n_hs && (8 << (log2n + 1)) <= A.hs_off) ++log2n;
     const int ht = 1 << log2n;
-    uint32_t *htk = L.tile;        // flat + 1, 0 = empty
-    uint32_t *htc = L.tile + ht;   // count
-    for (int i = threadIdx.x; i < ht; i += NT) htk[i] = 0u;
+    unsigned long long *htab = reinterpret_cast<unsigned long long *>(L.tile);
+    for (int i = threadIdx.x; i < ht; i += NT) htab[i] = 0ull;
     if (threadIdx.x == 0) sh.pcnt = 0;
     __syncthreads();
-    hash_insert<NT>(L.hs, n_hs, htk, htc, log2n);
+    hash_insert<NT>(L.hs, n_hs, htab, log2n);
     __syncthreads();
     // A peak's bin is below T in the next iteration whatever the claims:
     // taken, it loses every hit it voted with; rejected, fewer than T of its
@@ -512,7 +535,7 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     for (int e = threadIdx.x; e < n_hs; e += NT) {
         const unsigned long long key = L.hs[e];
         if (key == 0ull) continue;
-        if (window_peak(A, htk, htc, log2n, key)) {
+        if (window_peak(A, htab, log2n, key)) {
             const int slot = atomicAdd(&sh.pcnt, 1);
             if (slot < A.pkeep + A.hcap) L.pbuf[slot] = key;
             L.hs[e] = 0ull;
