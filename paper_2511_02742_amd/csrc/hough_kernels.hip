@@ -1213,6 +1213,17 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     int *pst = pbase + pb;
     int *elist = pst + pb;
 
+    // coordinates and (cos, sin) of the first pass's peaks, read ahead so
+    // that this device-memory read overlaps the one of the claimed hits
+    const int nb0 = min(pb, npk);
+    int2 d0 = make_int2(0, 0);
+    float2 t0 = make_float2(0.0f, 0.0f);
+    if (nb0 <= NT && threadIdx.x < nb0) {
+        const uint32_t flat = 0xffffffffu - (uint32_t)(keys[threadIdx.x] & 0xffffffffull);
+        const int j = (int)(flat / (uint32_t)A.n_rho);
+        d0 = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
+        t0 = cs[j];
+    }
     // the hits claimed by an earlier pass of this iteration
     for (int ch = wave; ch < W; ch += NW) {
         const int q = ch * kWave + lane;
@@ -1225,11 +1236,18 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     for (int p0 = 0; p0 < npk; p0 += pb) {
         const int nb = min(pb, npk - p0);
         // coordinates and (cos, sin) of this pass's peaks
-        for (int p = threadIdx.x; p < nb; p += NT) {
-            const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p0 + p] & 0xffffffffull);
-            const int j = (int)(flat / (uint32_t)A.n_rho);
-            dec[p] = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
-            pcs[p] = cs[j];
+        if (p0 == 0 && nb0 <= NT) {
+            if (threadIdx.x < nb0) {
+                dec[threadIdx.x] = d0;
+                pcs[threadIdx.x] = t0;
+            }
+        } else {
+            for (int p = threadIdx.x; p < nb; p += NT) {
+                const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p0 + p] & 0xffffffffull);
+                const int j = (int)(flat / (uint32_t)A.n_rho);
+                dec[p] = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
+                pcs[p] = cs[j];
+            }
         }
         __syncthreads();
         // A: match masks
@@ -1497,6 +1515,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     HitRegs h;
     for (;;) {
         if (A.max_iters > 0 && iter >= A.max_iters) break;
+        if (threadIdx.x == 0) sh.rlive = 0;  // live bins of a recount in this iteration
         // alive list, in ascending hit order (written with the validation
         // for the first iteration)
         int carry = iter == 0 ? n : 0;
@@ -1556,9 +1575,8 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                     __syncthreads();
                 } else if (hs_valid) {
-                    // recount the previous hot set (no histogram sweep)
-                    if (threadIdx.x == 0) sh.rlive = 0;
-                    __syncthreads();
+                    // recount the previous hot set (no histogram sweep);
+                    // rlive was cleared before the alive-list barriers
                     recount<NT>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs, &sh.rlive);
                     ++recounts;
                     __syncthreads();
