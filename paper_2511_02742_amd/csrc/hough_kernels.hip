@@ -93,6 +93,18 @@ __device__ __forceinline__ int rho_bin(float phi, float z, float c, float s, flo
     return k;
 }
 
+// rho_bin(...) in [lo, hi_excl - 1], decided on the same u: for finite u,
+// floor(u) >= lo <=> u >= lo and floor(u) < hi_excl <=> u < hi_excl (lo and
+// hi_excl are small integers, exact in float)
+__device__ __forceinline__ bool rho_in(float phi, float z, float c, float s, float rho_min, float inv_w, float lo,
+                                       float hi_excl) {
+    float a = phi * c;
+    float b = z * s;
+    float rho = a + b;
+    float u = (rho - rho_min) * inv_w;
+    return u >= lo && u < hi_excl;
+}
+
 __device__ __forceinline__ unsigned long long bin_key(uint32_t count, uint32_t flat) {
     return ((unsigned long long)count << 32) | (unsigned long long)(0xffffffffu - flat);
 }
@@ -601,18 +613,19 @@ __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restr
             const float sn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t.y), i));
             const int ki = __builtin_amdgcn_readlane(k, i);
             int cnt = 0;
+            const float lo = (float)ki, hi = (float)(ki + 1);
 #pragma unroll
             for (int ch = 0; ch < kChunks; ++ch) {
                 if (ch < h.nch) {
-                    const int kk = rho_bin(h.phi[ch], h.z[ch], c, sn, A.rho_min, A.inv_w);
-                    cnt += __popcll(__ballot(ch * kWave + lane < n_alive && kk == ki));
+                    const bool in = rho_in(h.phi[ch], h.z[ch], c, sn, A.rho_min, A.inv_w, lo, hi);
+                    cnt += __popcll(__ballot(ch * kWave + lane < n_alive && in));
                 }
             }
             for (int x = 0; x < nx; ++x) {
                 const int q = x * kWave + lane;
                 const float2 pz = xh[q];
-                const int kk = rho_bin(pz.x, pz.y, c, sn, A.rho_min, A.inv_w);
-                cnt += __popcll(__ballot(kChunks * kWave + q < n_alive && kk == ki));
+                const bool in = rho_in(pz.x, pz.y, c, sn, A.rho_min, A.inv_w, lo, hi);
+                cnt += __popcll(__ballot(kChunks * kWave + q < n_alive && in));
             }
             if (lane == i) out = (uint32_t)cnt >= A.min_votes ? bin_key((uint32_t)cnt, flat) : 0ull;
         }
@@ -1256,11 +1269,11 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             for (int p = wave; p < nb; p += NW) {
                 const int kp = dec[p].y;
                 const float2 t = pcs[p];
+                const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
-                    const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                    const int d = k - kp;
-                    const unsigned long long m = __ballot((d < 0 ? -d : d) <= A.assoc_window);
+                    const bool in = rho_in(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w, lo, hi);
+                    const unsigned long long m = __ballot(in);
                     if (lane == 0) M[(size_t)p * W + c] = m;
                 }
                 for (int xb = 0; xb + kChunks < W; xb += kChunks) {
@@ -1272,10 +1285,8 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
 #pragma unroll
                     for (int u = 0; u < kChunks; ++u) {
                         if (xb + u + kChunks < W) {
-                            const int k = rho_bin(pz[u].x, pz[u].y, t.x, t.y, A.rho_min, A.inv_w);
-                            const int d = k - kp;
-                            const bool hit = kChunks * kWave + (xb + u) * kWave + lane < n_alive &&
-                                             (d < 0 ? -d : d) <= A.assoc_window;
+                            const bool in = rho_in(pz[u].x, pz[u].y, t.x, t.y, A.rho_min, A.inv_w, lo, hi);
+                            const bool hit = kChunks * kWave + (xb + u) * kWave + lane < n_alive && in;
                             const unsigned long long m = __ballot(hit);
                             if (lane == 0) M[(size_t)p * W + kChunks + xb + u] = m;
                         }
@@ -1289,12 +1300,12 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             for (int p = wave; p < nb; p += NW) {
                 const int kp = dec[p].y;
                 const float2 t = pcs[p];
+                const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
                     if (c < h.nch) {
-                        const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                        const int d = k - kp;
-                        const bool hit = (qbase + c * kWave) < n_alive && (d < 0 ? -d : d) <= A.assoc_window;
+                        const bool in = rho_in(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w, lo, hi);
+                        const bool hit = (qbase + c * kWave) < n_alive && in;
                         const unsigned long long m = __ballot(hit);
                         if (lane == 0) M[(size_t)p * W + bt * kChunks + c] = m;
                     }
