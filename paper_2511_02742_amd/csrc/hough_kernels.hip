@@ -1297,9 +1297,16 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         for (int bt = 0; bt < nbatch && (xh == nullptr || nbatch == 1); ++bt) {
             if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
             const int qbase = bt * kChunks * kWave + lane;
+            // the next peak's coordinates are read while this one is tested
+            int kp_next = wave < nb ? dec[wave].y : 0;
+            float2 t_next = wave < nb ? pcs[wave] : make_float2(0.0f, 0.0f);
             for (int p = wave; p < nb; p += NW) {
-                const int kp = dec[p].y;
-                const float2 t = pcs[p];
+                const int kp = kp_next;
+                const float2 t = t_next;
+                if (p + NW < nb) {
+                    kp_next = dec[p + NW].y;
+                    t_next = pcs[p + NW];
+                }
                 const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
