@@ -1539,7 +1539,14 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         int carry = iter == 0 ? n : 0;
         for (int base = 0; base < n && iter > 0; base += NT) {
             const int i = base + threadIdx.x;
-            const bool alive = i < n && A.state[b + i] == -1;
+            // the hit's state, vane and z are read together, and its phi
+            // before the barrier
+            const bool in = i < n;
+            const int st = in ? A.state[b + i] : 0;
+            const int vn = in ? (int)A.vane[b + i] : 0;
+            const float zz = in ? A.z[b + i] : 0.0f;
+            const bool alive = in && st == -1;
+            const float ph = alive ? A.phi_v[vn] : 0.0f;
             const unsigned long long m = __ballot(alive);
             if (lane == 0) sh.wtot[wave] = __popcll(m);
             __syncthreads();
@@ -1552,8 +1559,8 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             if (alive) {
                 const int q = carry + woff + mbcnt64(m);
                 A.aidx[b + q] = i;
-                A.aphi[b + q] = A.phi_v[A.vane[b + i]];
-                A.az[b + q] = A.z[b + i];
+                A.aphi[b + q] = ph;
+                A.az[b + q] = zz;
             }
             carry += tot;
             __syncthreads();
