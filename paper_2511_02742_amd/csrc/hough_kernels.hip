@@ -1140,29 +1140,27 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
 // claimed words, which are wave-uniform scalars) become claimed and come off
 // the later lanes' counts. Most peaks of a pileup event are rejected without
 // a visit. Only the taken peaks' words and the claimed words go back to LDS.
-__device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
-                                            int W, int nb) {
+template <int W>
+__device__ __forceinline__ void claim_block_w(const FindArgs &A, unsigned long long *icl, unsigned long long *M,
+                                              int *pst, int nb) {
     if (wave_id() != 0) return;
     const int lane = lane_id();
     const int T = (int)A.min_votes;
     // the claimed words and each lane's match words stay in registers for a
     // block of 64 peaks; the taken peak's words reach the others by readlane
-    unsigned long long c[kClaimBlockW];
+    unsigned long long c[W];
 #pragma unroll
-    for (int w = 0; w < kClaimBlockW; ++w) {
-        // an unconditional (clamped) load: a load under the select made the
-        // backend emit an invalid aperture compare
-        const unsigned long long x = uniform64(icl[min(w, W - 1)]);
-        c[w] = w < W ? x : 0ull;
+    for (int w = 0; w < W; ++w) {
+        c[w] = uniform64(icl[w]);
     }
     for (int p0 = 0; p0 < nb; p0 += kWave) {
         const int p = p0 + lane;
         unsigned long long *mp = M + (size_t)(p < nb ? p : p0) * W;
-        unsigned long long m[kClaimBlockW];
+        unsigned long long m[W];
         int cnt = 0;
 #pragma unroll
-        for (int w = 0; w < kClaimBlockW; ++w) {
-            m[w] = w < W ? mp[w] : 0ull;
+        for (int w = 0; w < W; ++w) {
+            m[w] = mp[w];
             cnt += __popcll(m[w] & ~c[w]);
         }
         int res = -1;
@@ -1171,7 +1169,7 @@ __device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long lon
             const int q = __ffsll((long long)open) - 1;
             int drop = 0;
 #pragma unroll
-            for (int w = 0; w < kClaimBlockW; ++w) {
+            for (int w = 0; w < W; ++w) {
                 const unsigned long long t = readlane64(m[w], q) & ~c[w];
                 drop += __popcll(m[w] & t);
                 c[w] |= t;
@@ -1185,15 +1183,28 @@ __device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long lon
             pst[p] = res;
             if (res >= 0) {
 #pragma unroll
-                for (int w = 0; w < kClaimBlockW; ++w)
-                    if (w < W) mp[w] = m[w];
+                for (int w = 0; w < W; ++w) mp[w] = m[w];
             }
         }
     }
     if (lane == 0) {
 #pragma unroll
-        for (int w = 0; w < kClaimBlockW; ++w)
-            if (w < W) icl[w] = c[w];
+        for (int w = 0; w < W; ++w) icl[w] = c[w];
+    }
+}
+
+// claim_block_w for the event's word count (W <= kClaimBlockW)
+__device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
+                                            int W, int nb) {
+    switch (W) {
+    case 1: claim_block_w<1>(A, icl, M, pst, nb); break;
+    case 2: claim_block_w<2>(A, icl, M, pst, nb); break;
+    case 3: claim_block_w<3>(A, icl, M, pst, nb); break;
+    case 4: claim_block_w<4>(A, icl, M, pst, nb); break;
+    case 5: claim_block_w<5>(A, icl, M, pst, nb); break;
+    case 6: claim_block_w<6>(A, icl, M, pst, nb); break;
+    case 7: claim_block_w<7>(A, icl, M, pst, nb); break;
+    default: claim_block_w<kClaimBlockW>(A, icl, M, pst, nb); break;
     }
 }
 
