@@ -585,8 +585,8 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
 // previous histogram: recounting those bins gives the complete hot set of the
 // new histogram. Each wave takes bins; lanes test the register-resident hits
 // against the bin with Eq. (4) and ballots count the matches. Bins below T
-// are marked dead (key 0).
-template <int NT>
+// are marked dead (key 0). NCH is the register batch's chunk count (h.nch).
+template <int NT, int NCH>
 __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restrict__ cs, unsigned long long *hs, const HitRegs &h,
                         const float2 *xh, int nx, int n_alive, int n_hs, int *live_cnt) {
     constexpr int NW = NT / kWave;
@@ -615,11 +615,9 @@ __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restr
             int cnt = 0;
             const float lo = (float)ki, hi = (float)(ki + 1);
 #pragma unroll
-            for (int ch = 0; ch < kChunks; ++ch) {
-                if (ch < h.nch) {
-                    const bool in = rho_in(h.phi[ch], h.z[ch], c, sn, A.rho_min, A.inv_w, lo, hi);
-                    cnt += __popcll(__ballot(ch * kWave + lane < n_alive && in));
-                }
+            for (int ch = 0; ch < NCH; ++ch) {
+                const bool in = rho_in(h.phi[ch], h.z[ch], c, sn, A.rho_min, A.inv_w, lo, hi);
+                cnt += __popcll(__ballot(ch * kWave + lane < n_alive && in));
             }
             for (int x = 0; x < nx; ++x) {
                 const int q = x * kWave + lane;
@@ -1208,6 +1206,39 @@ __device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long lon
     }
 }
 
+// Match masks of a pass's peaks against register batch bt (NCH chunks
+// present): wave w takes peaks w, w + NW, ...; the ballot of chunk c is the
+// peak's match word bt * kChunks + c. The next peak's coordinates are read
+// while this one is tested.
+template <int NCH, int NW>
+__device__ __forceinline__ void match_masks(const FindArgs &A, const HitRegs &h, const int2 *dec, const float2 *pcs,
+                                            unsigned long long *M, int W, int nb, int n_alive, int bt) {
+    const int wave = wave_id();
+    const int lane = lane_id();
+    const int qbase = bt * kChunks * kWave + lane;
+    int kp_next = wave < nb ? dec[wave].y : 0;
+    float2 t_next = wave < nb ? pcs[wave] : make_float2(0.0f, 0.0f);
+    for (int p = wave; p < nb; p += NW) {
+        const int kp = kp_next;
+        const float2 t = t_next;
+        if (p + NW < nb) {
+            kp_next = dec[p + NW].y;
+            t_next = pcs[p + NW];
+        }
+        const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
+        unsigned long long m[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const bool in = rho_in(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w, lo, hi);
+            m[c] = __ballot((qbase + c * kWave) < n_alive && in);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) M[(size_t)p * W + bt * kChunks + c] = m[c];
+        }
+    }
+}
+
 template <int NT>
 __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
@@ -1307,28 +1338,22 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         }
         for (int bt = 0; bt < nbatch && (xh == nullptr || nbatch == 1); ++bt) {
             if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
-            const int qbase = bt * kChunks * kWave + lane;
-            // the next peak's coordinates are read while this one is tested
-            int kp_next = wave < nb ? dec[wave].y : 0;
-            float2 t_next = wave < nb ? pcs[wave] : make_float2(0.0f, 0.0f);
-            for (int p = wave; p < nb; p += NW) {
-                const int kp = kp_next;
-                const float2 t = t_next;
-                if (p + NW < nb) {
-                    kp_next = dec[p + NW].y;
-                    t_next = pcs[p + NW];
-                }
-                const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
-#pragma unroll
-                for (int c = 0; c < kChunks; ++c) {
-                    if (c < h.nch) {
-                        const bool in = rho_in(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w, lo, hi);
-                        const bool hit = (qbase + c * kWave) < n_alive && in;
-                        const unsigned long long m = __ballot(hit);
-                        if (lane == 0) M[(size_t)p * W + bt * kChunks + c] = m;
-                    }
-                }
+#define HOUGH_MASK_CASE(N)                                                                                     \
+    case N:                                                                                                    \
+        match_masks<N, NW>(A, h, dec, pcs, M, W, nb, n_alive, bt);                                             \
+        break;
+            switch (h.nch) {
+                HOUGH_MASK_CASE(1)
+                HOUGH_MASK_CASE(2)
+                HOUGH_MASK_CASE(3)
+                HOUGH_MASK_CASE(4)
+                HOUGH_MASK_CASE(5)
+                HOUGH_MASK_CASE(6)
+                HOUGH_MASK_CASE(7)
+                HOUGH_MASK_CASE(8)
+            default: break;
             }
+#undef HOUGH_MASK_CASE
             if (nbatch > 1) __syncthreads();
         }
         __syncthreads();
@@ -1613,7 +1638,22 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                 } else if (hs_valid) {
                     // recount the previous hot set (no histogram sweep);
                     // rlive was cleared before the alive-list barriers
-                    recount<NT>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs, &sh.rlive);
+#define HOUGH_RECOUNT_CASE(N)                                                                                  \
+    case N:                                                                                                    \
+        recount<NT, N>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs, &sh.rlive);                                  \
+        break;
+                    switch (h.nch) {
+                        HOUGH_RECOUNT_CASE(1)
+                        HOUGH_RECOUNT_CASE(2)
+                        HOUGH_RECOUNT_CASE(3)
+                        HOUGH_RECOUNT_CASE(4)
+                        HOUGH_RECOUNT_CASE(5)
+                        HOUGH_RECOUNT_CASE(6)
+                        HOUGH_RECOUNT_CASE(7)
+                        HOUGH_RECOUNT_CASE(8)
+                    default: break;
+                    }
+#undef HOUGH_RECOUNT_CASE
                     ++recounts;
                     __syncthreads();
                     evals += (unsigned long long)sh.rlive * (unsigned long long)(h.nch * kWave);
