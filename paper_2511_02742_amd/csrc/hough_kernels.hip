@@ -567,8 +567,15 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     for (int p = threadIdx.x / G; p < npk; p += NT / G) {
         const unsigned long long key = L.pbuf[p];
         int r = 0;
-#pragma unroll 4
-        for (int q = g; q < npair; q += G) {
+        int q = g;
+        // four loads in flight before the first compare
+        for (; q + 3 * G < npair; q += 4 * G) {
+            const ulonglong2 x0 = pb2[q], x1 = pb2[q + G], x2 = pb2[q + 2 * G], x3 = pb2[q + 3 * G];
+            __builtin_amdgcn_sched_barrier(0);
+            r += (x0.x > key ? 1 : 0) + (x0.y > key ? 1 : 0) + (x1.x > key ? 1 : 0) + (x1.y > key ? 1 : 0) +
+                 (x2.x > key ? 1 : 0) + (x2.y > key ? 1 : 0) + (x3.x > key ? 1 : 0) + (x3.y > key ? 1 : 0);
+        }
+        for (; q < npair; q += G) {
             const ulonglong2 x = pb2[q];
             r += (x.x > key ? 1 : 0) + (x.y > key ? 1 : 0);
         }
