@@ -101,6 +101,26 @@ def test_pileup_levels(gpu_available, pileup):
     check_batch(b, "pileup %d" % pileup)
 
 
+@pytest.mark.parametrize("assoc_window", [0, 1])
+def test_every_register_batch_width(gpu_available, assoc_window):
+    # hit counts on both sides of every 64-hit chunk boundary up to one
+    # register batch (512 hits): each chunk count of the masks and the
+    # recount and each word count of the one-wave claims is taken, batched
+    # and as single-event calls
+    sizes = [6, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257, 319, 320, 321,
+             383, 384, 385, 447, 448, 449, 511, 512]
+    evs = []
+    for i, n in enumerate(sizes):
+        e = eventgen.pileup_event(9000 + i, n_tracks=120)
+        assert e.n_hits >= n
+        e.z, e.vane, e.r, e.track = e.z[:n], e.vane[:n], e.r[:n], e.track[:n]
+        evs.append(e)
+    got, want = check_batch(eventgen.make_batch(evs), "widths", assoc_window=assoc_window)
+    assert len(want.cand) > len(sizes)
+    for n, e in zip(sizes, evs):
+        check_batch(eventgen.make_batch([e]), "width %d alone" % n, assoc_window=assoc_window)
+
+
 def test_uneven_batch(gpu_available):
     b = eventgen.poisson_batch(256)
     check_batch(b, "poisson batch")
