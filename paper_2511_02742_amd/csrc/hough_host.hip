@@ -24,6 +24,7 @@ constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 static_assert(kHotCap % 4 == 0, "the finder reads its peak list, placed after the hot list, 16 bytes at a time");
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
+constexpr int kOrderMin = 64;           // calls of this many events run the longest events first
 // calls of at most kSmallCall events split each event's first sweep over
 // this many 256-thread workgroups when the configuration leaves the split to
 // the library: an event's latency is then its sweep spread over several CUs
@@ -287,7 +288,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     const size_t o_hits = take(4 * nh), o_cand = take(sizeof(hough_candidate) * ncand);
     const size_t o_enc = take(4 * ne), o_enh = take(4 * ne), o_eco = take(8 * ne), o_eho = take(8 * ne);
     const size_t o_evst = take(8 * (size_t)hough::kEvStats * ne), o_err = take(8 * 4), o_offs = take(8 * 4);
-    const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne);
+    const size_t o_gcnt = take(4 * ne), o_gflag = take(4 * ne), o_order = take(4 * ne);
     // split-sweep hot lists: one per event, or one for the one-event split
     const int64_t ghs_events = c.sweep_groups > 0 ? ne : (c.single_split ? std::min<int64_t>(ne, kSmallCall) : 0);
     const size_t o_ghs = ghs_events > 0 ? take(8 * (size_t)ghs_events * (size_t)std::max(c.hs_cap, 1)) : 0;
@@ -323,6 +324,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     w.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
     w.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
     w.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
+    w.order = reinterpret_cast<int32_t *>(base + o_order);
     w.g_hs = ghs_events > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
     w.pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
     w.pool = reinterpret_cast<unsigned char *>(base + o_pool);
@@ -363,6 +365,7 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     a.ev_ncand = w.ev_ncand;
     a.ev_nhits = w.ev_nhits;
     a.ev_stats = w.ev_stats;
+    a.order = nullptr;
     a.err = w.err;
     a.tile_rows = c.tile_rows;
     a.pitch = c.pitch;
@@ -423,6 +426,13 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     } else if (a.g_hs != nullptr && n_events > 0) {
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
+    }
+    if (n_events >= kOrderMin && c.cfg.peak_mode != 2) {
+        // the longest events start first and the short ones fill the CUs at
+        // the end of the launch
+        hipError_t so = hough::launch_order(offsets, n_events, w.order, s);
+        if (so != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("order launch failed: ") + hipGetErrorString(so));
+        a.order = w.order;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed && n_events > 0) {

@@ -49,6 +49,9 @@ struct FindArgs {
     const int64_t *offsets;
     const float *z;
     const int16_t *vane;
+    // finder workgroup x takes event order[x] (events by descending hit
+    // count), or event x when NULL
+    const int32_t *order;
     // workspace (device), indexed by global hit / event
     int32_t *state;      // per hit: owning candidate id (event-local) or -1
     int32_t *aidx;       // alive list: event-local hit index
@@ -132,6 +135,8 @@ hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t 
 hipError_t set_sweep_lds_limit(int threads, int lds_bytes);
 int sweep_lds_bytes(int threads, int pitch);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+// order[0, n_events): the events by descending hit count (device offsets)
+hipError_t launch_order(const int64_t *offsets, int32_t n_events, int32_t *order, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 hipError_t launch_dump(const DumpArgs &a, int lds_bytes, hipStream_t s);
 hipError_t launch_set_offsets(int64_t *offsets, int64_t n, hipStream_t s);

@@ -1476,7 +1476,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     L.hs = reinterpret_cast<unsigned long long *>(lds + A.hs_off);
     L.sorted = reinterpret_cast<unsigned long long *>(lds + A.sorted_off);
 
-    const int e = blockIdx.x;
+    const int e = A.order != nullptr ? __builtin_amdgcn_readfirstlane(A.order[blockIdx.x]) : (int)blockIdx.x;
     const int wave = wave_id();
     const int lane = lane_id();
     // the event's bounds are uniform: keep them (and every address derived
@@ -2090,9 +2090,50 @@ hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t 
     return hipGetLastError();
 }
 
+// Counting sort of the events by hit count, descending (counts of 1023 hits
+// or more share the first bucket): one workgroup of kOrderBins threads, one
+// bucket each. Within a bucket the order is whatever the LDS atomics give;
+// every event's results are written to its own slots, so the finder's output
+// does not depend on it.
+constexpr int kOrderBins = 1024;
+
+__global__ __launch_bounds__(kOrderBins) void k_order(const int64_t *offsets, int32_t n_events, int32_t *order) {
+    __shared__ int cur[kOrderBins];
+    __shared__ int wsum[kOrderBins / kWave];
+    const int t = threadIdx.x;
+    cur[t] = 0;
+    __syncthreads();
+    for (int e = t; e < n_events; e += kOrderBins) {
+        const int64_t n = offsets[e + 1] - offsets[e];
+        const int k = n <= 0 ? 0 : (n >= kOrderBins - 1 ? kOrderBins - 1 : (int)n);
+        atomicAdd(&cur[kOrderBins - 1 - k], 1);
+    }
+    __syncthreads();
+    // bucket starts: exclusive scan over the buckets
+    const int v = cur[t];
+    const int incl = wave_incl_scan(v);
+    if (lane_id() == kWave - 1) wsum[wave_id()] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave_id(); ++w) before += wsum[w];
+    cur[t] = before + incl - v;
+    __syncthreads();
+    for (int e = t; e < n_events; e += kOrderBins) {
+        const int64_t n = offsets[e + 1] - offsets[e];
+        const int k = n <= 0 ? 0 : (n >= kOrderBins - 1 ? kOrderBins - 1 : (int)n);
+        order[atomicAdd(&cur[kOrderBins - 1 - k], 1)] = e;
+    }
+}
+
 __global__ void k_zero_i32(int32_t *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
+}
+
+hipError_t launch_order(const int64_t *offsets, int32_t n_events, int32_t *order, hipStream_t s) {
+    if (n_events <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(kOrderBins), 0, s, offsets, n_events, order);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) {

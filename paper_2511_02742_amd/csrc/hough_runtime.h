@@ -29,6 +29,7 @@ struct Workspace {
     hough_candidate *cand_ws = nullptr;
     long long *ev_cout = nullptr, *ev_hout = nullptr, *err = nullptr;
     unsigned long long *ev_stats = nullptr;
+    int32_t *order = nullptr;  // finder workgroup -> event, longest events first
     int64_t *tmp_offsets = nullptr;
     unsigned long long *g_hs = nullptr;
     int32_t *g_cnt = nullptr, *g_flag = nullptr;
