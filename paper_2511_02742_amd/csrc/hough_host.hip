@@ -404,7 +404,8 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
 // and counts itself. With timing on, HIP events bracket the finder kernel.
 hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
                           const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
-                          hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed) {
+                          hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed,
+                          bool longest_first) {
     hough::FindArgs a = find_args(c, w);
     a.n_events = n_events;
     a.n_total = n_total;
@@ -427,7 +428,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
-    if (n_events >= kOrderMin && c.cfg.peak_mode != 2) {
+    if (longest_first && n_events >= kOrderMin && c.cfg.peak_mode != 2) {
         // the longest events start first and the short ones fill the CUs at
         // the end of the launch
         hipError_t so = hough::launch_order(offsets, n_events, w.order, s);
@@ -618,7 +619,7 @@ hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hit
     st = ensure_workspace(*c, c->ws, n_hits_total, n_events, s);
     if (st) return fail(c, st, "workspace allocation failed");
     st = enqueue_find(*c, c->ws, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand,
-                      hit_index, counts, c->timing);
+                      hit_index, counts, c->timing, true);
     if (st) return st;
     c->last_error.clear();
     return HOUGH_OK;
@@ -641,7 +642,7 @@ hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, co
     // iters == 0 still runs the finder for its input validation; the dump
     // then ignores the state and counts every hit
     st = enqueue_find(*c, w, s, 1, n_hits, w.tmp_offsets, z, vane, iters > 0 ? iters : 0, w.cand_ws, w.hits_ws,
-                      counts, false);
+                      counts, false, false);
     if (st) return st;
     hough::DumpArgs da{};
     da.n_theta = c->cfg.n_theta;
@@ -765,7 +766,7 @@ hough_status hough_graph_create(void *ctx, int32_t n_events, int64_t n_hits_tota
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return cleanup(HOUGH_ERR_DEVICE, "hipStreamBeginCapture failed");
     st = enqueue_find(*c, g->ws, cap, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand,
-                      hit_index, counts, false);
+                      hit_index, counts, false, true);
     hipGraph_t captured = nullptr;
     const hipError_t ec = hipStreamEndCapture(cap, &captured);
     g->graph = captured;

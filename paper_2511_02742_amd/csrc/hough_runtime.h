@@ -96,10 +96,12 @@ void free_context(Ctx *c);
 hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_t n_events, hipStream_t s);
 void free_workspace(Workspace &w);
 // Enqueues one finder call on s (split sweep, finder, compaction); outputs
-// as in hough_find.
+// as in hough_find. With longest_first, a call of many events runs its
+// longest events first (an ordering kernel ahead of the finder).
 hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
                           const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
-                          hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed);
+                          hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed,
+                          bool longest_first);
 
 }  // namespace rt
 }  // namespace hough

@@ -123,11 +123,14 @@ struct Server {
         const size_t bytes = vo + 2 * (size_t)nh;
         if (hipMemcpyAsync(L.d_in, L.h_in, bytes, hipMemcpyHostToDevice, L.stream) != hipSuccess)
             return HOUGH_ERR_DEVICE;
+        // no longest-first ordering here: the lanes' launches overlap on the
+        // device, and ordered overlapping launches of thousands of mixed
+        // events (every lane's large events at once) ran slower than unordered
         hough_status s = hough::rt::enqueue_find(*ctx, L.ws, L.stream, (int32_t)ne, nh,
                                                  reinterpret_cast<const int64_t *>(L.d_in),
                                                  reinterpret_cast<const float *>(L.d_in + zo),
                                                  reinterpret_cast<const int16_t *>(L.d_in + vo), ctx->cfg.max_iters,
-                                                 L.cand, L.hits, L.counts, false);
+                                                 L.cand, L.hits, L.counts, false, false);
         if (s) return s;
         if (hipEventRecord(L.done, L.stream) != hipSuccess) return HOUGH_ERR_DEVICE;
         L.t_admit = t;
