@@ -344,7 +344,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
     L.mm = L.pool + kSegWords;
     L.red = L.mm + kSegWords;
 
-    const int e = blockIdx.x;
+    const int e = A.order != nullptr ? __builtin_amdgcn_readfirstlane(A.order[blockIdx.x]) : (int)blockIdx.x;
     const int64_t b = uniform64(A.offsets[e]);
     const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
     if (threadIdx.x == 0) {

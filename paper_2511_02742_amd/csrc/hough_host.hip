@@ -428,7 +428,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
-    if (longest_first && n_events >= kOrderMin && c.cfg.peak_mode != 2) {
+    if (longest_first && n_events >= kOrderMin) {
         // the longest events start first and the short ones fill the CUs at
         // the end of the launch
         hipError_t so = hough::launch_order(offsets, n_events, w.order, s);

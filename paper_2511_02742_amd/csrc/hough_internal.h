@@ -49,8 +49,8 @@ struct FindArgs {
     const int64_t *offsets;
     const float *z;
     const int16_t *vane;
-    // finder workgroup x takes event order[x] (events by descending hit
-    // count), or event x when NULL
+    // finder workgroup x (k_find, k_find_cf) takes event order[x] (events by
+    // descending hit count), or event x when NULL
     const int32_t *order;
     // workspace (device), indexed by global hit / event
     int32_t *state;      // per hit: owning candidate id (event-local) or -1
