@@ -121,6 +121,29 @@ def test_every_register_batch_width(gpu_available, assoc_window):
         check_batch(eventgen.make_batch([e]), "width %d alone" % n, assoc_window=assoc_window)
 
 
+def test_longest_first_order_edge_sizes(gpu_available):
+    # a call of 64 or more events runs them longest first: empty and one-hit
+    # events, events above 1023 hits (one shared bucket of the ordering sort)
+    # and many events of one size must all come out once, in event order
+    evs = []
+    for i in range(70):
+        kind = i % 7
+        if kind == 0:
+            e = eventgen.make_event(1, 0, noise_frac=0.0)                        # empty
+        elif kind == 1:
+            e = eventgen.pileup_event(9500 + i)
+            e.z, e.vane, e.r, e.track = e.z[:1], e.vane[:1], e.r[:1], e.track[:1]  # one hit
+        elif kind == 2:
+            e = eventgen.pileup_event(9500 + i, n_tracks=260)                     # above 1023 hits
+        else:
+            e = eventgen.pileup_event(9500 + i, n_tracks=50)
+            e.z, e.vane, e.r, e.track = e.z[:200], e.vane[:200], e.r[:200], e.track[:200]  # one size
+        evs.append(e)
+    assert max(e.n_hits for e in evs) > 1023
+    got, want = check_batch(eventgen.make_batch(evs), "order edges")
+    assert len(want.cand) > 0
+
+
 def test_uneven_batch(gpu_available):
     b = eventgen.poisson_batch(256)
     check_batch(b, "poisson batch")
