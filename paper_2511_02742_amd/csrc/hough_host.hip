@@ -24,7 +24,7 @@ constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 static_assert(kHotCap % 4 == 0, "the finder reads its peak list, placed after the hot list, 16 bytes at a time");
 constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
-constexpr int kOrderMin = 64;           // calls of this many events run the longest events first
+constexpr int kOrderMin = 64;           // calls of more events than this (and than resident workgroups) run the longest events first
 // calls of at most kSmallCall events split each event's first sweep over
 // this many 256-thread workgroups when the configuration leaves the split to
 // the library: an event's latency is then its sweep spread over several CUs
@@ -428,9 +428,10 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
-    if (longest_first && n_events >= kOrderMin) {
+    if (longest_first && n_events > std::max(c.max_resident, kOrderMin)) {
         // the longest events start first and the short ones fill the CUs at
-        // the end of the launch
+        // the end of the launch (with no more events than resident
+        // workgroups every event starts at once and the order is moot)
         hipError_t so = hough::launch_order(offsets, n_events, w.order, s);
         if (so != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("order launch failed: ") + hipGetErrorString(so));
         a.order = w.order;

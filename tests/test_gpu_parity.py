@@ -122,11 +122,12 @@ def test_every_register_batch_width(gpu_available, assoc_window):
 
 
 def test_longest_first_order_edge_sizes(gpu_available):
-    # a call of 64 or more events runs them longest first: empty and one-hit
-    # events, events above 1023 hits (one shared bucket of the ordering sort)
-    # and many events of one size must all come out once, in event order
+    # a call of more events than resident finder workgroups runs them longest
+    # first: empty and one-hit events, events above 1023 hits (one shared
+    # bucket of the ordering sort) and many events of one size must all come
+    # out once, in event order
     evs = []
-    for i in range(70):
+    for i in range(630):
         kind = i % 7
         if kind == 0:
             e = eventgen.make_event(1, 0, noise_frac=0.0)                        # empty
@@ -140,6 +141,8 @@ def test_longest_first_order_edge_sizes(gpu_available):
             e.z, e.vane, e.r, e.track = e.z[:200], e.vane[:200], e.r[:200], e.track[:200]  # one size
         evs.append(e)
     assert max(e.n_hits for e in evs) > 1023
+    # (630 events: more than the 256 finder workgroups of 1024 threads an
+    # MI355X holds at once)
     got, want = check_batch(eventgen.make_batch(evs), "order edges")
     assert len(want.cand) > 0
 
