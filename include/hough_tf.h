@@ -35,6 +35,15 @@
 extern "C" {
 #endif
 
+/* Opaque handles. A context holds one configuration's lookup tables, launch
+ * shape and finder workspace on one device; a graph is a captured batched
+ * launch; a server is the served form's request loop. Each is created and
+ * destroyed only through the calls below, and every call checks the handle's
+ * kind, so a handle of the wrong kind is refused with HOUGH_ERR_INVALID_ARG. */
+typedef struct hough_ctx hough_ctx;
+typedef struct hough_graph hough_graph;
+typedef struct hough_server hough_server;
+
 typedef enum {
     HOUGH_OK = 0,
     HOUGH_ERR_INVALID_ARG = -1,   /* bad config, null pointer, bad offsets  */
@@ -65,7 +74,7 @@ typedef enum {
  * Bins are ordered by the 64-bit key (count << 32) | (2^32 - 1 - flat),
  * flat = j * n_rho + k: higher count first, then lower flat index.
  *
- * Coarse-to-fine mode (peak_mode 2; Sec. 6 and Fig. 2: an 18 x 100 coarse
+ * Coarse-to-fine mode (peak_mode 2; Sec. 6 and Fig. 4: an 18 x 100 coarse
  * histogram, then a 10 x 10 fine one inside its most likely region). Per
  * iteration the alive hits fill a coarse histogram of
  * (n_theta / coarse_theta) x (n_rho / coarse_rho) bins over the same ranges,
@@ -160,23 +169,36 @@ typedef struct {
  * degrees, T = 6, nms with w = 1, a = 0, no iteration cap, tuned launch. */
 hough_status hough_config_default(hough_config *cfg);
 
-/* Validates cfg, builds the lookup tables on the host, uploads them to
- * `device` and returns a new context in *out (host pointer). On error *out is
- * NULL. */
-hough_status hough_create(const hough_config *cfg, int device, void **out);
+/* Validates cfg, builds the lookup tables on the host (Sec. 5's binning:
+ * cos and sin at the theta bin centres, the azimuth of each vane, the rho bin
+ * width), uploads them to `device` and returns a new context in *out (host
+ * pointer). On error *out is NULL: HOUGH_ERR_INVALID_ARG for a bad config or
+ * device, HOUGH_ERR_OOM or HOUGH_ERR_DEVICE if the upload fails. */
+hough_status hough_create(const hough_config *cfg, int device, hough_ctx **out);
 
-/* Frees the context and its device memory. NULL is accepted. The caller
- * must have synchronised every stream that still uses the context. */
-hough_status hough_destroy(void *ctx);
+/* Frees the context, its tables and workspace. NULL is accepted. The caller
+ * must have synchronised every stream that still uses the context; a context
+ * with live graphs is refused (HOUGH_ERR_INVALID_ARG). */
+hough_status hough_destroy(hough_ctx *ctx);
 
 /* Upper bounds of the outputs for n_events events holding n_hits_total hits
- * in total: at most floor(n_e / T) candidates per event, so
- * floor(n_hits_total / T) overall, and at most n_hits_total hit indices. */
-hough_status hough_output_bounds(const void *ctx, int32_t n_events, int64_t n_hits_total,
+ * in total. A candidate needs at least T hits of its own (Sec. 5: a seed is a
+ * peak whose line carries enough hits) and the hits it claims leave the pool
+ * (Sec. 4: find and remove), so an event of n_e hits yields at most
+ * floor(n_e / T) candidates, floor(n_hits_total / T) overall, and at most
+ * n_hits_total hit indices. Pure host arithmetic; *max_candidates and
+ * *max_hit_index are host pointers. HOUGH_ERR_INVALID_ARG for a bad context,
+ * a null output pointer or negative sizes. */
+hough_status hough_output_bounds(const hough_ctx *ctx, int32_t n_events, int64_t n_hits_total,
                                  int64_t *max_candidates, int64_t *max_hit_index);
 
 /*
- * Runs the finder on n_events events.
+ * Runs the finder on n_events events: per event, the find-and-remove loop of
+ * Sec. 4 over the Hough histogram of Eq. (4) (Sec. 5: every hit votes in every
+ * theta bin; peaks are the most populated bins; the hits on a peak's line
+ * form a seed, are claimed, leave the pool, and the search repeats).
+ * Candidates come out in the order (event, iteration, peak key descending),
+ * each with its claimed hits as ascending event-local indices.
  *   event_offsets  device int64[n_events + 1]; event e holds hits
  *                  [offsets[e], offsets[e+1]); offsets[0] must be 0 and
  *                  offsets[n_events] must equal n_hits_total (the host
@@ -200,19 +222,22 @@ hough_status hough_output_bounds(const void *ctx, int32_t n_events, int64_t n_hi
  * context, HOUGH_ERR_OOM if the workspace cannot grow, HOUGH_ERR_DEVICE if a
  * launch fails.
  */
-hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
+hough_status hough_find(hough_ctx *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
                         const int64_t *event_offsets, const float *z, const int16_t *vane,
                         hough_candidate *cand, int64_t cand_capacity,
                         int32_t *hit_index, int64_t hit_capacity, int64_t *counts);
 
 /*
- * Debug view of the vote histogram of one event: acc_out (device
+ * Debug view of the vote histogram of one event (Sec. 5: the histogram that
+ * Eq. (4) fills, one vote per hit and theta bin): acc_out (device
  * uint32[n_theta * n_rho], row-major theta x rho) receives the histogram of
  * the hits still in the pool after `iters` iterations of the finder
- * (iters = 0: all n_hits hits). z and vane are device arrays of n_hits hits.
- * counts as in hough_find (device int64[HOUGH_COUNTS]).
+ * (iters = 0: all n_hits hits; Sec. 4: the pool after that many
+ * find-and-remove passes). z and vane are device arrays of n_hits hits.
+ * counts as in hough_find (device int64[HOUGH_COUNTS]). In mode 2 acc_out is
+ * the coarse histogram. Errors as for hough_find; the caller owns acc_out.
  */
-hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, const float *z,
+hough_status hough_debug_accumulator(hough_ctx *ctx, void *stream, int64_t n_hits, const float *z,
                                      const int16_t *vane, int32_t iters, uint32_t *acc_out,
                                      int64_t *counts);
 
@@ -220,18 +245,18 @@ hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, co
  * (float[n_theta]), phi per vane (float[n_vanes]), inv_w (float[1]), theta
  * and rho bin centres (float[n_theta], float[n_rho]). Any pointer may be
  * NULL. */
-hough_status hough_tables(const void *ctx, float *cos_t, float *sin_t, float *phi_v,
+hough_status hough_tables(const hough_ctx *ctx, float *cos_t, float *sin_t, float *phi_v,
                           float *inv_w, float *theta_c, float *rho_c);
 
 /* Launch shape chosen for this context (after defaults/tuning). */
-hough_status hough_launch_shape(const void *ctx, int32_t *tile_rows, int32_t *wg_threads,
+hough_status hough_launch_shape(const hough_ctx *ctx, int32_t *tile_rows, int32_t *wg_threads,
                                 int32_t *lds_bytes);
 
 /* Kernel timing: when enabled, hough_find records HIP events around its
  * finder kernel; hough_timing returns the summed milliseconds and the number
  * of launches measured since the last reset (it synchronises those events). */
-hough_status hough_set_timing(void *ctx, int enable);
-hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, int reset);
+hough_status hough_set_timing(hough_ctx *ctx, int enable);
+hough_status hough_timing(hough_ctx *ctx, double *find_kernel_ms, int64_t *launches, int reset);
 
 /*
  * Captured launch (batched form). Records the kernel sequence hough_find
@@ -245,11 +270,11 @@ hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, 
  * handle. Nothing is enqueued by hough_graph_create itself except the
  * workspace setup, which it synchronises.
  */
-hough_status hough_graph_create(void *ctx, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
+hough_status hough_graph_create(hough_ctx *ctx, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
                                 const float *z, const int16_t *vane, hough_candidate *cand, int64_t cand_capacity,
-                                int32_t *hit_index, int64_t hit_capacity, int64_t *counts, void **graph);
-hough_status hough_graph_launch(void *graph, void *stream);
-hough_status hough_graph_destroy(void *graph);
+                                int32_t *hit_index, int64_t hit_capacity, int64_t *counts, hough_graph **graph);
+hough_status hough_graph_launch(hough_graph *graph, void *stream);
+hough_status hough_graph_destroy(hough_graph *graph);
 
 /*
  * Launch-shape autotuner. Times every candidate shape (finder workgroup of
@@ -350,11 +375,11 @@ typedef struct {
  * defaults) and starts its dispatcher thread. All device and pinned memory
  * is allocated here. */
 hough_status hough_server_create(const hough_config *cfg, int device, const hough_server_config *scfg,
-                                 void **server);
+                                 hough_server **server);
 /* Stops the dispatcher after the launches in flight finish; requests still
  * queued and results not polled are dropped. */
-hough_status hough_server_destroy(void *server);
-double hough_server_clock(const void *server);
+hough_status hough_server_destroy(hough_server *server);
+double hough_server_clock(const hough_server *server);
 /*
  * Queues n requests: request r has hits [offsets[r], offsets[r+1]) of the
  * host arrays z and vane (offsets[0] may be nonzero; the hits are copied
@@ -366,7 +391,7 @@ double hough_server_clock(const void *server);
  * taken; it is less than n only when the queue is full (back-pressure: submit
  * the rest later). Returns HOUGH_ERR_INVALID_ARG for bad pointers or offsets.
  */
-hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
+hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
                                  const float *z, const int16_t *vane, const double *t_arrival,
                                  int32_t *n_accepted);
 /*
@@ -377,13 +402,13 @@ hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, 
  * Returns HOUGH_ERR_CAPACITY (and moves nothing) when the oldest waiting
  * result alone does not fit the arrays.
  */
-hough_status hough_server_poll(void *server, int32_t max_results, hough_served *results, hough_candidate *cand,
+hough_status hough_server_poll(hough_server *server, int32_t max_results, hough_served *results, hough_candidate *cand,
                                int64_t cand_capacity, int32_t *hit_index, int64_t hit_capacity,
                                int32_t *n_results);
 /* Waits until no request is queued or in flight (HOUGH_ERR_CAPACITY after
  * timeout_s seconds). */
-hough_status hough_server_drain(void *server, double timeout_s);
-hough_status hough_server_get_stats(const void *server, hough_server_stats *stats);
+hough_status hough_server_drain(hough_server *server, double timeout_s);
+hough_status hough_server_get_stats(const hough_server *server, hough_server_stats *stats);
 
 /*
  * Helix refit of track candidates (a continuous fit of each candidate's hits;
@@ -440,9 +465,13 @@ hough_status hough_refit_gauss_newton(void *stream, int32_t n_cand, const int64_
                                       const float *hit_aref, const int32_t *status, float *params, int32_t steps,
                                       float damping, float sigma, float *chi2);
 
+/* Static, NUL-terminated name of a status code ("unknown status" for others). */
 const char *hough_status_string(hough_status st);
-/* Detail of the last failing call on ctx (empty string if none). */
-const char *hough_last_error(const void *ctx);
+/* Detail of the last failing call on ctx (empty string if none). With a NULL
+ * or invalid ctx, the last failure of any call on this host thread. The
+ * string belongs to the library and stays valid until the next call on
+ * ctx. */
+const char *hough_last_error(const hough_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,7 @@
  *   - an event stops when no peak reaches T, when an iteration emits
  *     nothing, or after max_iters iterations (0 = no cap).
  *
- * Coarse-to-fine mode (peak_mode 2; Sec. 6 and Fig. 2: the paper fills an
+ * Coarse-to-fine mode (peak_mode 2; Sec. 6 and Fig. 4: the paper fills an
  * 18 x 100 coarse histogram and then a 10 x 10 fine one inside the most
  * likely coarse region, to fit GPU shared memory):
  *   - the coarse grid has n_theta / coarse_theta x n_rho / coarse_rho bins

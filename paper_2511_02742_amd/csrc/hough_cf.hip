@@ -1,7 +1,7 @@
 // gfx950 kernel of the coarse-to-fine find-and-remove loop (peak_mode 2).
 //
 // The paper fills its Hough space in two stages to fit GPU shared memory
-// (Sec. 6, Fig. 2): an 18 x 100 coarse histogram over the whole (theta, rho)
+// (Sec. 6, Fig. 4): an 18 x 100 coarse histogram over the whole (theta, rho)
 // range, then a 10 x 10 fine histogram inside the most likely coarse bin,
 // whose maximum is the line. Here one workgroup owns one event for the whole
 // loop, and per iteration

@@ -34,12 +34,12 @@ constexpr int kSmallCall = 8;
 }  // namespace
 thread_local std::string g_last_global_error;
 
-Ctx *as_ctx(void *p) {
-    Ctx *c = static_cast<Ctx *>(p);
+Ctx *as_ctx(hough_ctx *p) {
+    Ctx *c = reinterpret_cast<Ctx *>(p);
     return (c && c->magic == kCtxMagic) ? c : nullptr;
 }
-const Ctx *as_ctx(const void *p) {
-    const Ctx *c = static_cast<const Ctx *>(p);
+const Ctx *as_ctx(const hough_ctx *p) {
+    const Ctx *c = reinterpret_cast<const Ctx *>(p);
     return (c && c->magic == kCtxMagic) ? c : nullptr;
 }
 
@@ -580,15 +580,15 @@ hough_status hough_config_default(hough_config *cfg) {
     return HOUGH_OK;
 }
 
-hough_status hough_create(const hough_config *cfg, int device, void **out) {
+hough_status hough_create(const hough_config *cfg, int device, hough_ctx **out) {
     if (!out) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "null output pointer");
     Ctx *c = nullptr;
     hough_status st = make_context(cfg, device, &c);
-    *out = c;
+    *out = handle_of(c);
     return st;
 }
 
-hough_status hough_destroy(void *ctx) {
+hough_status hough_destroy(hough_ctx *ctx) {
     if (!ctx) return HOUGH_OK;
     Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;
@@ -597,7 +597,7 @@ hough_status hough_destroy(void *ctx) {
     return HOUGH_OK;
 }
 
-hough_status hough_output_bounds(const void *ctx, int32_t n_events, int64_t n_hits_total,
+hough_status hough_output_bounds(const hough_ctx *ctx, int32_t n_events, int64_t n_hits_total,
                                  int64_t *max_candidates, int64_t *max_hit_index) {
     const Ctx *c = as_ctx(ctx);
     if (!c || n_events < 0 || n_hits_total < 0 || !max_candidates || !max_hit_index) return HOUGH_ERR_INVALID_ARG;
@@ -606,7 +606,7 @@ hough_status hough_output_bounds(const void *ctx, int32_t n_events, int64_t n_hi
     return HOUGH_OK;
 }
 
-hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
+hough_status hough_find(hough_ctx *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
                         const int64_t *event_offsets, const float *z, const int16_t *vane,
                         hough_candidate *cand, int64_t cand_capacity, int32_t *hit_index,
                         int64_t hit_capacity, int64_t *counts) {
@@ -626,7 +626,7 @@ hough_status hough_find(void *ctx, void *stream, int32_t n_events, int64_t n_hit
     return HOUGH_OK;
 }
 
-hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, const float *z,
+hough_status hough_debug_accumulator(hough_ctx *ctx, void *stream, int64_t n_hits, const float *z,
                                      const int16_t *vane, int32_t iters, uint32_t *acc_out, int64_t *counts) {
     Ctx *c = as_ctx(ctx);
     if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
@@ -665,7 +665,7 @@ hough_status hough_debug_accumulator(void *ctx, void *stream, int64_t n_hits, co
     return HOUGH_OK;
 }
 
-hough_status hough_tables(const void *ctx, float *cos_t, float *sin_t, float *phi_v, float *inv_w,
+hough_status hough_tables(const hough_ctx *ctx, float *cos_t, float *sin_t, float *phi_v, float *inv_w,
                           float *theta_c, float *rho_c) {
     const Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;
@@ -678,7 +678,7 @@ hough_status hough_tables(const void *ctx, float *cos_t, float *sin_t, float *ph
     return HOUGH_OK;
 }
 
-hough_status hough_launch_shape(const void *ctx, int32_t *tile_rows, int32_t *wg_threads, int32_t *lds_bytes) {
+hough_status hough_launch_shape(const hough_ctx *ctx, int32_t *tile_rows, int32_t *wg_threads, int32_t *lds_bytes) {
     const Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;
     if (tile_rows) *tile_rows = c->tile_rows;
@@ -703,14 +703,14 @@ hough_status hough_lds_peak(int device, void *stream, int mode, double *lane_ato
     return HOUGH_OK;
 }
 
-hough_status hough_set_timing(void *ctx, int enable) {
+hough_status hough_set_timing(hough_ctx *ctx, int enable) {
     Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;
     c->timing = enable != 0;
     return HOUGH_OK;
 }
 
-hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, int reset) {
+hough_status hough_timing(hough_ctx *ctx, double *find_kernel_ms, int64_t *launches, int reset) {
     Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;
     for (auto &pr : c->ev_pairs) {
@@ -732,9 +732,9 @@ hough_status hough_timing(void *ctx, double *find_kernel_ms, int64_t *launches, 
     return HOUGH_OK;
 }
 
-hough_status hough_graph_create(void *ctx, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
+hough_status hough_graph_create(hough_ctx *ctx, int32_t n_events, int64_t n_hits_total, const int64_t *event_offsets,
                                 const float *z, const int16_t *vane, hough_candidate *cand, int64_t cand_capacity,
-                                int32_t *hit_index, int64_t hit_capacity, int64_t *counts, void **graph) {
+                                int32_t *hit_index, int64_t hit_capacity, int64_t *counts, hough_graph **graph) {
     Ctx *c = as_ctx(ctx);
     if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
     if (!graph) return fail(c, HOUGH_ERR_INVALID_ARG, "null graph pointer");
@@ -777,13 +777,13 @@ hough_status hough_graph_create(void *ctx, int32_t n_events, int64_t n_hits_tota
         return cleanup(HOUGH_ERR_DEVICE, "hipGraphInstantiate failed");
     (void)hipStreamDestroy(cap);
     c->graphs += 1;
-    *graph = g;
+    *graph = reinterpret_cast<hough_graph *>(g);
     c->last_error.clear();
     return HOUGH_OK;
 }
 
-hough_status hough_graph_launch(void *graph, void *stream) {
-    Graph *g = static_cast<Graph *>(graph);
+hough_status hough_graph_launch(hough_graph *graph, void *stream) {
+    Graph *g = reinterpret_cast<Graph *>(graph);
     if (!g || g->magic != kGraphMagic) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad graph");
     if (hipSetDevice(g->ctx->device) != hipSuccess) return fail(g->ctx, HOUGH_ERR_DEVICE, "hipSetDevice failed");
     if (hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
@@ -791,9 +791,9 @@ hough_status hough_graph_launch(void *graph, void *stream) {
     return HOUGH_OK;
 }
 
-hough_status hough_graph_destroy(void *graph) {
+hough_status hough_graph_destroy(hough_graph *graph) {
     if (!graph) return HOUGH_OK;
-    Graph *g = static_cast<Graph *>(graph);
+    Graph *g = reinterpret_cast<Graph *>(graph);
     if (g->magic != kGraphMagic) return HOUGH_ERR_INVALID_ARG;
     (void)hipSetDevice(g->ctx->device);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -852,12 +852,12 @@ hough_status hough_autotune(const hough_config *base, int device, void *stream, 
     for (const hough_config &cfg : cands) {
         Ctx *c = nullptr;
         if (make_context(&cfg, device, &c) != HOUGH_OK) continue;  // shape not supported here
-        hough_status r = hough_find(c, stream, n_events, n_hits_total, event_offsets, z, vane, d_cand, ccap, d_hits,
+        hough_status r = hough_find(handle_of(c), stream, n_events, n_hits_total, event_offsets, z, vane, d_cand, ccap, d_hits,
                                     hcap, d_counts);
         if (r == HOUGH_OK) {
             (void)hipEventRecord(e0, s);
             for (int i = 0; i < repeats && r == HOUGH_OK; ++i)
-                r = hough_find(c, stream, n_events, n_hits_total, event_offsets, z, vane, d_cand, ccap, d_hits,
+                r = hough_find(handle_of(c), stream, n_events, n_hits_total, event_offsets, z, vane, d_cand, ccap, d_hits,
                                hcap, d_counts);
             (void)hipEventRecord(e1, s);
         }
@@ -912,7 +912,7 @@ const char *hough_status_string(hough_status st) {
     }
 }
 
-const char *hough_last_error(const void *ctx) {
+const char *hough_last_error(const hough_ctx *ctx) {
     const Ctx *c = as_ctx(ctx);
     if (!c) return g_last_global_error.c_str();
     return c->last_error.c_str();

@@ -85,8 +85,10 @@ struct Graph {
     hipGraphExec_t exec = nullptr;
 };
 
-Ctx *as_ctx(void *p);
-const Ctx *as_ctx(const void *p);
+Ctx *as_ctx(hough_ctx *p);
+const Ctx *as_ctx(const hough_ctx *p);
+// The handle the C ABI hands out for a context.
+inline hough_ctx *handle_of(Ctx *c) { return reinterpret_cast<hough_ctx *>(c); }
 // Records msg as the context's (and the thread's) last error; returns st.
 hough_status fail(Ctx *c, hough_status st, const std::string &msg);
 hough_status make_context(const hough_config *cfg, int device, Ctx **out);

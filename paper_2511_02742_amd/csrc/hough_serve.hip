@@ -256,12 +256,12 @@ struct Server {
     }
 };
 
-Server *as_server(void *p) {
-    Server *s = static_cast<Server *>(p);
+Server *as_server(hough_server *p) {
+    Server *s = reinterpret_cast<Server *>(p);
     return (s && s->magic == kServerMagic) ? s : nullptr;
 }
-const Server *as_server(const void *p) {
-    const Server *s = static_cast<const Server *>(p);
+const Server *as_server(const hough_server *p) {
+    const Server *s = reinterpret_cast<const Server *>(p);
     return (s && s->magic == kServerMagic) ? s : nullptr;
 }
 
@@ -334,7 +334,7 @@ bool valid_hits(const Server &s, const float *z, const int16_t *vane, int64_t b,
 extern "C" {
 
 hough_status hough_server_create(const hough_config *cfg, int device, const hough_server_config *scfg,
-                                 void **server) {
+                                 hough_server **server) {
     if (!server) return HOUGH_ERR_INVALID_ARG;
     *server = nullptr;
     hough_server_config c{};
@@ -374,11 +374,11 @@ hough_status hough_server_create(const hough_config *cfg, int device, const houg
         free_server(s);
         return HOUGH_ERR_INTERNAL;
     }
-    *server = s;
+    *server = reinterpret_cast<hough_server *>(s);
     return HOUGH_OK;
 }
 
-hough_status hough_server_destroy(void *server) {
+hough_status hough_server_destroy(hough_server *server) {
     if (!server) return HOUGH_OK;
     Server *s = as_server(server);
     if (!s) return HOUGH_ERR_INVALID_ARG;
@@ -393,12 +393,12 @@ hough_status hough_server_destroy(void *server) {
     return HOUGH_OK;
 }
 
-double hough_server_clock(const void *server) {
+double hough_server_clock(const hough_server *server) {
     const Server *s = as_server(server);
     return s ? s->now() : -1.0;
 }
 
-hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
+hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
                                  const float *z, const int16_t *vane, const double *t_arrival,
                                  int32_t *n_accepted) {
     Server *s = as_server(server);
@@ -459,7 +459,7 @@ hough_status hough_server_submit(void *server, int32_t n, const uint64_t *tags, 
     return HOUGH_OK;
 }
 
-hough_status hough_server_poll(void *server, int32_t max_results, hough_served *results, hough_candidate *cand,
+hough_status hough_server_poll(hough_server *server, int32_t max_results, hough_served *results, hough_candidate *cand,
                                int64_t cand_capacity, int32_t *hit_index, int64_t hit_capacity,
                                int32_t *n_results) {
     Server *s = as_server(server);
@@ -489,7 +489,7 @@ hough_status hough_server_poll(void *server, int32_t max_results, hough_served *
     return HOUGH_OK;
 }
 
-hough_status hough_server_drain(void *server, double timeout_s) {
+hough_status hough_server_drain(hough_server *server, double timeout_s) {
     Server *s = as_server(server);
     if (!s) return HOUGH_ERR_INVALID_ARG;
     const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
@@ -499,7 +499,7 @@ hough_status hough_server_drain(void *server, double timeout_s) {
     return ok ? HOUGH_OK : HOUGH_ERR_CAPACITY;
 }
 
-hough_status hough_server_get_stats(const void *server, hough_server_stats *out) {
+hough_status hough_server_get_stats(const hough_server *server, hough_server_stats *out) {
     const Server *s = as_server(server);
     if (!s || !out) return HOUGH_ERR_INVALID_ARG;
     Server *m = const_cast<Server *>(s);

@@ -1,6 +1,6 @@
 """Pins of the oracle's coarse-to-fine mode (peak_mode 2; the paper's 18 x 100
 coarse histogram refined by a 10 x 10 fine one inside the most likely coarse
-region, Sec. 6 and Fig. 2). The coarse and fine histograms are checked
+region, Sec. 6 and Fig. 4). The coarse and fine histograms are checked
 against the oracle's plain histogram fill on the coarse grid and on the full
 grid, a different code path that is the definition of both."""
 import math
