@@ -91,7 +91,8 @@ def refit_init(r, z, vane, n_vanes: int = N_VANES):
     """(params (5,), root sign s (n,), reference turning angle a_ref (n,))
     from the measured hits of one candidate, in float64; params is None for a
     candidate no helix is fitted to (fewer than 3 hits or 3 distinct vanes,
-    or a circle of radius above R_MAX_MM: hits along a line, not a helix)."""
+    a singular circle system (exactly collinear points), or a circle of
+    radius above R_MAX_MM: hits along a line, not a helix)."""
     if len(r) < 3 or len(set(np.asarray(vane).tolist())) < 3:
         return None, np.ones(len(r)), np.zeros(len(r))
     r = np.asarray(r, np.float64)
@@ -105,7 +106,10 @@ def refit_init(r, z, vane, n_vanes: int = N_VANES):
                   [np.dot(u, v), np.dot(v, v), v.sum()],
                   [u.sum(), v.sum(), float(len(u))]])
     rhs = -np.array([np.dot(u, w), np.dot(v, w), w.sum()])
-    D, E, F = np.linalg.solve(A, rhs)
+    try:
+        D, E, F = np.linalg.solve(A, rhs)
+    except np.linalg.LinAlgError:      # exactly collinear points: no circle at all
+        return None, np.ones(len(r)), np.zeros(len(r))
     cx, cy = xm - D / 2.0, ym - E / 2.0
     R2 = D * D / 4.0 + E * E / 4.0 - F
     cn = math.hypot(cx, cy)

@@ -174,3 +174,106 @@ def test_generator_track_refit_is_physical():
         assert abs(momentum_mev(p) / ev.p[t] - 1.0) < 0.05
         done += 1
     assert done >= 2
+
+
+# --- refusal rule (a reading: the paper is silent on which candidates a helix
+# fit should skip) and the flat-track branch of the turning-angle unwrap ---
+
+def _vane_circle_hits(cx, cy, R, vanes, n_vanes=40):
+    """Exact crossings (r, vane) of the circle (centre (cx, cy), radius R) with
+    the given vane rays: the root of |t u - c|^2 = R^2 nearest the origin
+    that lies in front of it."""
+    rs, vs = [], []
+    for k in vanes:
+        ph = 2 * math.pi * k / n_vanes
+        b = math.cos(ph) * cx + math.sin(ph) * cy
+        disc = b * b - (cx * cx + cy * cy - R * R)
+        assert disc > 0
+        t = b - math.sqrt(disc)
+        assert t > 0
+        rs.append(t)
+        vs.append(k)
+    return np.array(rs), np.array(vs, np.int16)
+
+
+def test_two_vanes_are_refused_three_are_fitted():
+    r, z, v, a = _track()
+    # the truth track crosses one vane plane twice; that pair plus one hit on
+    # a second vane is three hits on two vanes: refused
+    vals, cnt = np.unique(v, return_counts=True)
+    twice = vals[cnt == 2][0]
+    pair = np.nonzero(v == twice)[0]
+    other = np.nonzero(v != twice)[0][0]
+    sel = np.concatenate([pair, [other]])
+    p0, _, _ = refit_init(r[sel], z[sel], v[sel])
+    assert p0 is None
+    # three hits on three distinct vanes define the circle and the z line
+    # exactly: the initial fit returns the truth
+    sel3 = np.concatenate([pair[:1], np.nonzero(v != twice)[0][[0, 3]]])
+    assert len(set(v[sel3].tolist())) == 3
+    p0, _, aref = refit_init(r[sel3], z[sel3], v[sel3])
+    assert p0 is not None
+    assert np.allclose(p0, TRUTH, rtol=1e-9, atol=1e-9), (p0, TRUTH)
+    assert np.allclose(aref, a[sel3], atol=1e-9)
+    # two hits are refused whatever their vanes
+    assert refit_init(r[sel3[:2]], z[sel3[:2]], v[sel3[:2]])[0] is None
+
+
+def test_straight_lines_are_refused():
+    # hits on the straight line x = 150 mm (vanes at -9, 0, 9 and 18 degrees)
+    vanes = np.array([39, 0, 1, 2], np.int16)
+    ph = 2 * math.pi * vanes / 40
+    r = 150.0 / np.cos(ph)
+    z = np.array([1.0, 2.0, 3.0, 4.0])
+    assert refit_init(r, z, vanes)[0] is None
+    # exact circles through the detector: radius 2e4 mm is above the 1e4 mm
+    # limit (refused), radius 5e3 mm is below it (fitted, radius recovered)
+    for R, fitted in ((2.0e4, False), (5.0e3, True)):
+        d0 = 150.0
+        cx, cy = d0 + R, 0.0
+        r, v = _vane_circle_hits(cx, cy, R, [37, 38, 39, 0, 1, 2, 3])
+        z = 0.2 * np.arange(len(r))
+        p0, _, _ = refit_init(r, z, v)
+        if not fitted:
+            assert p0 is None
+        else:
+            assert p0 is not None
+            assert abs(1.0 / p0[0] - R) < 1e-6 * R and abs(p0[2] - d0) < 1e-6
+
+
+@pytest.mark.parametrize("tan_lambda", [0.0, 0.0015])
+def test_flat_track_unwraps_between_the_sides_of_the_largest_gap(tan_lambda):
+    # a z spread under 1 mm takes the largest-gap branch: the arc through the
+    # detector is contiguous, so the largest angular gap is the rest of the
+    # circle and the unwrapped angles are the true turning angles
+    truth = TRUTH.copy()
+    truth[4] = tan_lambda
+    r, z, v, a = helix_hits(truth, -math.pi + 0.01, math.pi - 0.01)
+    assert len(r) == 11 and np.ptp(z) < 1.0
+    p0, _, aref = refit_init(r, z, v)
+    assert np.allclose(aref, a, atol=1e-9)
+    assert np.allclose(p0, truth, rtol=1e-9, atol=1e-9), (p0, truth)
+    # the same hits in another order unwrap the same way
+    perm = np.random.default_rng(5).permutation(len(r))
+    p1, _, aref1 = refit_init(r[perm], z[perm], v[perm])
+    assert np.allclose(aref1, a[perm], atol=1e-9) and np.allclose(p1, p0, rtol=1e-9, atol=1e-12)
+
+
+def test_full_circle_flat_track_starts_after_the_largest_gap():
+    # a circle wholly inside the detector (perigee 100 mm, apogee 220 mm) with
+    # tan lambda = 0: every unwrapped angle is its true angle modulo 2 pi, the
+    # span is under one turn, and it starts at the hit that follows the
+    # largest gap between neighbouring angles
+    R = 60.0
+    truth = np.array([1.0 / R, 0.3, 100.0, -5.0, 0.0])
+    r, z, v, a = helix_hits(truth, -math.pi + 1e-3, math.pi - 1e-3)
+    p0, _, aref = refit_init(r, z, v)
+    assert np.allclose(p0[[0, 2, 3, 4]], truth[[0, 2, 3, 4]], rtol=1e-9, atol=1e-9)
+    assert abs(math.remainder(p0[1] - truth[1], 2 * math.pi)) < 1e-9
+    d = np.mod(aref - a, 2 * math.pi)
+    assert np.all(np.minimum(d, 2 * math.pi - d) < 1e-9)
+    assert np.ptp(aref) < 2 * math.pi
+    srt = np.sort(a)
+    gaps = np.append(np.diff(srt), srt[0] + 2 * math.pi - srt[-1])
+    start = srt[(int(np.argmax(gaps)) + 1) % len(srt)]
+    assert abs(aref.min() - start) < 1e-9
