@@ -39,6 +39,201 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu_info():
+    """CPU model and the cores this process may use (the oracle's host)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def event_mismatches(got_cand, got_hits, want):
+    """Events whose candidates (every field) or ordered hit lists differ
+    between a finder output and the oracle's; 0 means the two outputs are
+    byte-identical."""
+    import numpy as np
+    if (len(got_cand) == len(want.cand) and len(got_hits) == len(want.hit_index)
+            and np.array_equal(got_cand.view(np.uint8), want.cand.view(np.uint8))
+            and np.array_equal(got_hits, want.hit_index)):
+        return 0
+    evs = np.union1d(np.unique(got_cand["event"]), np.unique(want.cand["event"]))
+    bad = 0
+    for e in evs:
+        a = got_cand[got_cand["event"] == e]
+        b = want.cand[want.cand["event"] == e]
+        if len(a) != len(b) or any(not np.array_equal(a[f], b[f]) for f in a.dtype.names if f != "hit_offset"):
+            bad += 1
+            continue
+        if len(a):
+            ha = got_hits[a["hit_offset"][0]:a["hit_offset"][0] + int(a["n_hits"].sum())]
+            hb = want.hit_index[b["hit_offset"][0]:b["hit_offset"][0] + int(b["n_hits"].sum())]
+            bad += int(not np.array_equal(ha, hb))
+    return bad
+
+
+def parity_record(got_cand, got_hits, want, n_events):
+    return {"events": n_events, "candidates": len(got_cand), "hits": len(got_hits),
+            "oracle_candidates": len(want.cand), "oracle_hits": len(want.hit_index),
+            "mismatched_events": event_mismatches(got_cand, got_hits, want), "check": "byte-equal, every event"}
+
+
+def timed_batched(f, z, vane, offs, out, stream, steps, warmup):
+    """(ms per call from the host clock, finder kernel ms per launch from HIP
+    events on the launch stream) over `steps` calls after `warmup` calls."""
+    import torch
+    for _ in range(warmup):
+        f.find(z, vane, offs, out=out, stream=stream)
+    torch.cuda.synchronize()
+    f.set_timing(True)
+    f.timing(reset=True)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        f.find(z, vane, offs, out=out, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    f.set_timing(False)
+    kern_ms, launches = f.timing(reset=True)
+    return 1e3 * wall / steps, kern_ms / max(launches, 1)
+
+
+def event_latency(f, z, vane, offs, out, stream, n_events, repeats):
+    """Per-event latency of the batched call from device clock stamps: an
+    event's retire stamp (its finder workgroup wrote its last output) minus
+    the call's first finder workgroup start, over `repeats` calls."""
+    import numpy as np
+    import torch
+    from paper_2511_02742_amd.hough import clock_rate
+    rate = clock_rate(0)
+    stamps = torch.zeros(2 * n_events, dtype=torch.int64, device=z.device)
+    f.set_event_clock(stamps)
+    lat, spans = [], []
+    try:
+        for _ in range(repeats):
+            stamps.zero_()
+            f.find(z, vane, offs, out=out, stream=stream)
+            torch.cuda.synchronize()
+            s = stamps.cpu().numpy().reshape(-1, 2).astype(np.float64)
+            t0 = s[:, 0].min()
+            lat.append((s[:, 1] - t0) / rate)
+            spans.append((s[:, 1].max() - t0) / rate)
+    finally:
+        f.set_event_clock(None)
+    lat = np.concatenate(lat)
+    return {"latency_us_p50": round(1e6 * float(np.percentile(lat, 50)), 2),
+            "latency_us_p99": round(1e6 * float(np.percentile(lat, 99)), 2),
+            "latency_us_max": round(1e6 * float(lat.max()), 2),
+            "device_span_us_median": round(1e6 * float(np.median(spans)), 2),
+            "calls": repeats, "clock_hz": rate,
+            "definition": "retire stamp of each event (its finder workgroup wrote its last output) minus the "
+                          "call's first finder-workgroup start; device wall clock"}
+
+
+def graph_legs(f, batch, z, vane, offs, stream, steps, warmup, want):
+    """The batched call captured in a HIP graph: replays on device-resident
+    hits, and the whole transfer-inclusive round (pinned host hits to the
+    device, replay, counts and the exact outputs back to pinned host memory)
+    as the paper's timings count host-device copies (Table 1)."""
+    import numpy as np
+    import torch
+    g = f.capture(z, vane, offs)
+    for _ in range(warmup):
+        g.launch(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        g.launch(stream)
+    torch.cuda.synchronize()
+    replay_ms = 1e3 * (time.perf_counter() - t1) / steps
+    cand, hits, info = g.out.to_host()
+    par = parity_record(cand, hits, want, len(batch.offsets) - 1) if want is not None else None
+    hz = torch.from_numpy(batch.z).pin_memory()
+    hv = torch.from_numpy(batch.vane).pin_memory()
+    ho = torch.from_numpy(batch.offsets).pin_memory()
+    hcnt = torch.empty(g.out.counts.shape, dtype=torch.int64).pin_memory()
+    hcand = torch.empty(g.out.cand.shape, dtype=torch.uint8).pin_memory()
+    hhits = torch.empty(g.out.hit_index.shape, dtype=torch.int32).pin_memory()
+
+    def round_trip():
+        z.copy_(hz, non_blocking=True)
+        vane.copy_(hv, non_blocking=True)
+        offs.copy_(ho, non_blocking=True)
+        g.launch(stream)
+        hcnt.copy_(g.out.counts, non_blocking=True)
+        stream.synchronize()
+        nc, nh = int(hcnt[0]), int(hcnt[1])
+        hcand[:nc].copy_(g.out.cand[:nc], non_blocking=True)
+        hhits[:nh].copy_(g.out.hit_index[:nh], non_blocking=True)
+        stream.synchronize()
+    for _ in range(warmup):
+        round_trip()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        round_trip()
+    rt_ms = 1e3 * (time.perf_counter() - t1) / steps
+    nc, nh = int(hcnt[0]), int(hcnt[1])
+    rt_ok = (want is not None and nc == len(want.cand) and nh == len(want.hit_index)
+             and np.array_equal(hcand[:nc].numpy().reshape(-1), want.cand.view(np.uint8).reshape(-1))
+             and np.array_equal(hhits[:nh].numpy(), want.hit_index))
+    g.close()
+    ne = len(batch.offsets) - 1
+    return {"replay": {"events_per_s": round(ne / (replay_ms * 1e-3), 1), "ms_per_call": round(replay_ms, 4),
+                       "parity": par},
+            "with_transfers": {"events_per_s": round(ne / (rt_ms * 1e-3), 1), "ms_per_call": round(rt_ms, 4),
+                               "h2d_bytes": int(batch.z.nbytes + batch.vane.nbytes + batch.offsets.nbytes),
+                               "d2h_bytes": int(16 * 8 + 40 * nc + 4 * nh),
+                               "outputs_byte_equal_oracle": bool(rt_ok),
+                               "note": "pinned host hits -> device, graph replay, counts back, then exactly the "
+                                       "candidates and hit lists back; two stream synchronisations per call"}}
+
+
+def oracle_references(jobs, log):
+    """The oracle's full outputs for every event of each (name, config,
+    batch) job, in independent processes over event slices (the unchanged
+    single-threaded oracle in each)."""
+    from oracle.oracle import oracle_find_batch_sliced
+    workers = max(1, min(16, os.cpu_count() or 1))
+    refs = {}
+    for name, ocfg, b in jobs:
+        t0 = time.perf_counter()
+        refs[name] = oracle_find_batch_sliced(ocfg, b.offsets, b.z, b.vane, workers=workers)
+        log("oracle reference %s: %d candidates, %d hits in %.1f s"
+            % (name, len(refs[name].cand), len(refs[name].hit_index), time.perf_counter() - t0))
+    return refs
+
+
+def cpu_sample(ocfg, batch, seconds, label):
+    """The single-threaded oracle over the first events of `batch` for about
+    `seconds` (at least 16 events): events/s and per-event p50/p99."""
+    import numpy as np
+    from oracle import oracle_find
+    n_ev = len(batch.offsets) - 1
+    n_done = 0
+    per = []
+    tc0 = time.perf_counter()
+    while n_done < n_ev and (time.perf_counter() - tc0 < seconds or n_done < 16):
+        lo, hi = int(batch.offsets[n_done]), int(batch.offsets[n_done + 1])
+        ts = time.perf_counter()
+        oracle_find(ocfg, batch.z[lo:hi], batch.vane[lo:hi], event_id=n_done)
+        per.append(time.perf_counter() - ts)
+        n_done += 1
+    tc = time.perf_counter() - tc0
+    per = np.array(per)
+    return {"value": round(n_done / tc, 2), "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the same %d %s events, one thread, %.1f s" % (n_done, n_ev, label, tc),
+            "latency_us_p50": round(1e6 * float(np.percentile(per, 50)), 1),
+            "latency_us_p99": round(1e6 * float(np.percentile(per, 99)), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,8 +241,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-events", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-events", type=int, default=50000,
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timings and the oracle references (no parity check then)")
+    ap.add_argument("--no-autotune", action="store_true", help="headline on the library's default shape")
+    ap.add_argument("--serve-events", type=int, default=1000000,
                     help="requests per offered rate in the served-stream leg (0: skip it)")
     ap.add_argument("--serve-rates", default="20000,50000,100000")
     ap.add_argument("--serve-lanes", type=int, default=3)
@@ -58,6 +255,9 @@ def main():
                     help="pure candidates also fitted by the float64 oracle for the parameter error")
     ap.add_argument("--no-coarse-fine", action="store_true",
                     help="skip the coarse-to-fine leg (the paper's 18 x 100 -> 10 x 10 histograms)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="the batched headline leg alone (for profiler runs): no oracle, plain, graph, cfg3, "
+                         "served, refit or coarse-to-fine legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first, as the reference kernel for "
                          "FETCH_SIZE / WRITE_SIZE counter scaling")
@@ -66,37 +266,45 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(events shard across GPUs with no communication; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    if args.only_batched:
+        args.no_cpu_baseline = True
+        args.serve_events = 0
+        args.refit_events = 0
+        args.no_coarse_fine = True
 
     import numpy as np
 
+    from oracle import OracleConfig
     from paper_2511_02742_amd import eventgen
 
     t0 = time.time()
     batch = eventgen.pileup_batch(N_EVENTS, n_tracks=PILEUP, seed0=0)
     log("generated %d events in %.1f s: %s" % (N_EVENTS, time.time() - t0, eventgen.hit_histogram(batch)))
+    b3 = None if args.only_batched else eventgen.poisson_batch(N_EVENTS)
 
-    # ---- CPU oracle on a bounded sample, before anything touches the GPU
-    # (the all-cores figure starts worker processes)
-    cpu = cpu_all = None
+    # ---- CPU oracle: timings on bounded samples and the full references
+    # for the parity checks, all before anything touches the GPU (the
+    # all-cores figures start worker processes)
+    cpu = cpu_all = cpu3 = None
+    refs = {}
+    host = host_cpu_info()
     if not args.no_cpu_baseline:
-        from oracle import OracleConfig, oracle_find
-        ocfg = OracleConfig()
-        n_done = 0
-        tc0 = time.perf_counter()
-        while n_done < N_EVENTS and (time.perf_counter() - tc0 < args.cpu_seconds or n_done < 16):
-            lo, hi = int(batch.offsets[n_done]), int(batch.offsets[n_done + 1])
-            oracle_find(ocfg, batch.z[lo:hi], batch.vane[lo:hi], event_id=n_done)
-            n_done += 1
-        tc = time.perf_counter() - tc0
-        cpu = {"value": round(n_done / tc, 2), "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d of the same %d pileup-50 events, one thread, %.1f s"
-                         % (n_done, N_EVENTS, tc)}
-        log("cpu oracle: %.1f events/s over %d events" % (n_done / tc, n_done))
+        cpu = cpu_sample(OracleConfig(), batch, args.cpu_seconds, "pileup-50")
+        cpu.update(host)
+        log("cpu oracle: %s" % cpu)
         cpu_all = oracle_all_cores(batch, args.cpu_seconds, log)
+        cpu_all.update(host)
+        cpu3 = cpu_sample(OracleConfig(), b3, args.cpu_seconds / 3, "Poisson(20)")
+        log("cpu oracle, Poisson(20) batch: %s" % cpu3)
+        jobs = [("pileup50", OracleConfig(), batch), ("poisson20", OracleConfig(), b3)]
+        if not args.no_coarse_fine:
+            for name, mode in (("coarse_fine", 2), ("argmax", 0), ("nms", 1)):
+                jobs.append(("cf_" + name, OracleConfig(n_theta=180, n_rho=1000, peak_mode=mode), batch))
+        refs = oracle_references(jobs, log)
 
     import torch
 
-    from paper_2511_02742_amd.hough import HoughFinder
+    from paper_2511_02742_amd.hough import COUNT_NAMES, HoughFinder, autotune
 
     dev = torch.device("cuda", 0)
     z = torch.from_numpy(batch.z).to(dev)
@@ -114,93 +322,144 @@ def main():
         log("copy calibration (MulFunctor kernel): %d bytes read, %d bytes written" % (nb, nb))
         del src, dst
 
-    f = HoughFinder(0)
+    stream = torch.cuda.current_stream(dev)
+    # ---- launch shape: the autotuner on this batch (its time is reported
+    # apart and never counted in events/s)
+    tune = None
+    if args.no_autotune:
+        f = HoughFinder(0)
+    else:
+        tt0 = time.perf_counter()
+        best, best_ms, tried = autotune(z, vane, offs, repeats=3)
+        tune = {"seconds": round(time.perf_counter() - tt0, 3), "shapes_tried": tried,
+                "best_ms_per_call": round(best_ms, 4),
+                "best": {k: int(getattr(best, k)) for k in ("wg_threads", "sweep_groups", "sweep_threads",
+                                                             "tile_rows")}}
+        log("autotune: %s" % tune)
+        f = HoughFinder(0, config=best)
     shape = f.launch_shape()
     out = f.alloc_outputs(N_EVENTS, batch.n_hits)
-    stream = torch.cuda.current_stream(dev)
 
     # ---- batched: one call over all events --------------------------------
-    for _ in range(args.warmup):
-        f.find(z, vane, offs, out=out, stream=stream)
-    torch.cuda.synchronize(dev)
-    f.set_timing(True)
-    f.timing(reset=True)
-    torch.cuda.synchronize(dev)
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        f.find(z, vane, offs, out=out, stream=stream)
-    torch.cuda.synchronize(dev)
-    t2 = time.perf_counter()
-    f.set_timing(False)
-    kern_ms, launches = f.timing(reset=True)
-    from paper_2511_02742_amd.hough import COUNT_NAMES
+    ms_per_step, kern_avg_ms = timed_batched(f, z, vane, offs, out, stream, args.steps, args.warmup)
     info = dict(zip(COUNT_NAMES, (int(x) for x in out.counts.cpu().numpy())))
     assert info["status"] == 0, info
     main_cand, main_hits, _ = out.to_host()
+    value = 1e3 * N_EVENTS / ms_per_step
+    log("batched: %.3f ms/step, %.0f events/s, finder kernel %.3f ms avg" % (ms_per_step, value, kern_avg_ms))
+    parity = parity_record(main_cand, main_hits, refs["pileup50"], N_EVENTS) if "pileup50" in refs else None
+    log("parity: %s" % parity)
+    lat_b = event_latency(f, z, vane, offs, out, stream, N_EVENTS, 10)
+    log("batched per-event latency: %s" % lat_b)
+
+    if args.only_batched:
+        print(json.dumps({"metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+                          "kernel_avg_ms": round(kern_avg_ms, 4), "launch": shape, "autotune": tune,
+                          "only_batched": True}), flush=True)
+        return
+
     eff = eq5_efficiency(batch, main_cand, main_hits)
     log("Eq. (5) efficiency: %s" % eff)
-    wall = t2 - t1
-    ms_per_step = 1e3 * wall / args.steps
-    value = N_EVENTS * args.steps / wall
-    kern_avg_ms = kern_ms / max(launches, 1)
-    log("batched: %.3f ms/step, %.0f events/s, finder kernel %.3f ms avg over %d launches"
-        % (ms_per_step, value, kern_avg_ms, launches))
+    graph = graph_legs(f, batch, z, vane, offs, stream, args.steps, args.warmup, refs.get("pileup50"))
+    log("graph: %s" % graph)
 
-    # ---- plain: one event per call ----------------------------------------
+    # ---- plain: one event per call, the library's default shape ----------
+    fp = HoughFinder(0)
     npl = min(args.plain_events, N_EVENTS)
     single = []
     for e in range(npl):
         lo, hi = int(batch.offsets[e]), int(batch.offsets[e + 1])
         o = torch.tensor([0, hi - lo], dtype=torch.int64, device=dev)
-        single.append((z[lo:hi], vane[lo:hi], o, f.alloc_outputs(1, hi - lo)))
+        single.append((z[lo:hi], vane[lo:hi], o, fp.alloc_outputs(1, hi - lo)))
     for e in range(min(16, npl)):
         zz, vv, oo, oo_out = single[e]
-        f.find(zz, vv, oo, out=oo_out, stream=stream)
+        fp.find(zz, vv, oo, out=oo_out, stream=stream)
     torch.cuda.synchronize(dev)
     lat = np.zeros(npl)
     tp0 = time.perf_counter()
     for e in range(npl):
         zz, vv, oo, oo_out = single[e]
         ts = time.perf_counter()
-        f.find(zz, vv, oo, out=oo_out, stream=stream)
+        fp.find(zz, vv, oo, out=oo_out, stream=stream)
         stream.synchronize()
         lat[e] = time.perf_counter() - ts
     tp1 = time.perf_counter()
     plain_rate = npl / (tp1 - tp0)
-    log("plain: %.0f events/s, p50 %.1f us, p99 %.1f us" % (plain_rate, 1e6 * np.percentile(lat, 50),
-                                                              1e6 * np.percentile(lat, 99)))
+    plain_bad = 0
+    if "pileup50" in refs:
+        want = refs["pileup50"]
+        for e in range(npl):
+            c, h, _ = single[e][3].to_host()
+            sel = want.cand["event"] == e
+            wc = want.cand[sel].copy()
+            wh = want.hit_index[wc["hit_offset"][0]:wc["hit_offset"][0] + int(wc["n_hits"].sum())] if len(wc) \
+                else want.hit_index[:0]
+            wc["event"] = 0
+            if len(wc):
+                wc["hit_offset"] -= wc["hit_offset"][0]
+            plain_bad += int(not (np.array_equal(c.view(np.uint8), wc.view(np.uint8)) and np.array_equal(h, wh)))
+    log("plain: %.0f events/s, p50 %.1f us, p99 %.1f us, %d mismatched events"
+        % (plain_rate, 1e6 * np.percentile(lat, 50), 1e6 * np.percentile(lat, 99), plain_bad))
+
+    # ---- the uneven Poisson(20) batch -------------------------------------
+    z3 = torch.from_numpy(b3.z).to(dev)
+    v3 = torch.from_numpy(b3.vane).to(dev)
+    o3 = torch.from_numpy(b3.offsets).to(dev)
+    out3 = f.alloc_outputs(N_EVENTS, b3.n_hits)
+    ms3, k3 = timed_batched(f, z3, v3, o3, out3, stream, args.steps, args.warmup)
+    c3, h3, i3 = out3.to_host()
+    lens3 = np.diff(b3.offsets)
+    poisson = {"workload": "%d events, tracks ~ Poisson(20) clipped to [1, 100] + 1%% noise, seeds 1000000.., "
+                           "1024x1024, T=6, nms w=1" % N_EVENTS,
+               "hits_total": int(b3.n_hits), "hits_per_event_mean": round(float(lens3.mean()), 1),
+               "hits_per_event_range": [int(lens3.min()), int(lens3.max())],
+               "events_per_s": round(1e3 * N_EVENTS / ms3, 1), "ms_per_step": round(ms3, 4),
+               "kernel_avg_ms": round(k3, 4), "candidates": i3["candidates"],
+               "parity": parity_record(c3, h3, refs["poisson20"], N_EVENTS) if "poisson20" in refs else None,
+               "cpu_baseline": cpu3,
+               "event_latency": event_latency(f, z3, v3, o3, out3, stream, N_EVENTS, 5)}
+    log("Poisson(20) batch: %s" % poisson)
 
     # ---- HBM traffic of the finder kernel from the committed counter summary
     # (reported only while the kernel source still matches the one profiled)
     traffic = profiled_traffic("k_find_pileup50", "hough_kernels.hip")
 
-    # ---- roofline of the finder kernel ------------------------------------
-    flops = FLOPS_PER_VOTE * info["evals"]
-    achieved = flops / (kern_avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
-                "evals_per_launch": info["evals"], "flops_per_eval": FLOPS_PER_VOTE,
-                "evals_per_s": round(info["evals"] / (kern_avg_ms * 1e-3), 1)}
-
-
-    # ---- LDS atomic roofline of the finder's votes (the survey's denominator:
-    # every histogram vote is one LDS atomic add)
+    # ---- LDS atomic roofline of the finder's votes: every histogram vote is
+    # one LDS atomic add. The method's votes (N_theta x the alive hits of
+    # every iteration's histogram, the oracle's count) are the work; the
+    # kernel's own atomics (fewer: later histograms are recounted from the
+    # hot set) are reported beside them.
     from paper_2511_02742_amd.hough import lds_peak
     peak_cf = lds_peak(0)
     peak_vote = lds_peak(1)
-    votes_s = info["votes"] / (kern_avg_ms * 1e-3)
-    lds = {"bound": "lds", "achieved": round(votes_s, 1), "unit": "lane atomics/s",
+    method_votes = refs["pileup50"].votes if "pileup50" in refs else None
+    work = method_votes if method_votes is not None else info["votes"]
+    votes_s = work / (kern_avg_ms * 1e-3)
+    lds = {"bound": "lds", "achieved": round(votes_s, 1), "unit": "votes/s (lane LDS atomics)",
            "peak": round(peak_cf, 1), "frac": round(votes_s / peak_cf, 4),
            "peak_vote_pattern": round(peak_vote, 1), "frac_vote_pattern": round(votes_s / peak_vote, 4),
-           "votes_per_launch": info["votes"], "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
-           "note": "peak: conflict-free ds_add_u32 without return; vote pattern: random bins of a 1024-word "
-                   "row with return (hough_lds_peak, measured in this run)"}
+           "method_votes_per_launch": method_votes, "kernel_votes_per_launch": info["votes"],
+           "kernel_votes_frac": round(info["votes"] / (kern_avg_ms * 1e-3) / peak_cf, 4),
+           "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
+           "note": "work: the method's votes, N_theta x alive hits summed over every iteration's histogram "
+                   "(oracle count); peak: conflict-free ds_add_u32 without return; vote pattern: random bins "
+                   "of a 1024-word row with return (hough_lds_peak, measured in this run)"}
     log("LDS roofline: %s" % lds)
+    # the same work against the unfused float VALU issue rate: 5 rounded
+    # float operations of Eq. (4) per vote
+    achieved = FLOPS_PER_VOTE * work / (kern_avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(VALU_PEAK_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_find", "kernel_avg_ms": round(kern_avg_ms, 4),
+                "method_votes_per_launch": method_votes, "flops_per_vote": FLOPS_PER_VOTE,
+                "kernel_evals_per_launch": info["evals"],
+                "lds_frac": lds["frac"], "lds_frac_vote_pattern": lds["frac_vote_pattern"]}
 
     served = serve_bench(args, f, log) if args.serve_events > 0 else None
     refit = refit_bench(args, f, log) if args.refit_events > 0 else None
-    coarse_fine = None if args.no_coarse_fine else coarse_fine_bench(args, batch, z, vane, offs, log, peak_vote)
+    coarse_fine = None if args.no_coarse_fine else coarse_fine_bench(args, batch, z, vane, offs, log, peak_vote,
+                                                                     refs)
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
@@ -211,18 +470,24 @@ def main():
                                "1024x1024 uint32 histogram, T=6, nms w=1" % (N_EVENTS, N_EVENTS - 1),
                    "n_events": N_EVENTS, "hits_total": batch.n_hits, "n_theta": 1024, "n_rho": 1024,
                    "min_votes": 6, "peak_mode": "nms", "launch": shape},
+        "parity": parity,
+        "autotune": tune,
+        "batched_ms_per_launch": round(ms_per_step, 4),
+        "batched_event_latency": lat_b,
+        "graph": graph,
         "plain": {"value": round(plain_rate, 1), "unit": "events/s", "events": npl,
                   "latency_us_p50": round(1e6 * float(np.percentile(lat, 50)), 2),
-                  "latency_us_p99": round(1e6 * float(np.percentile(lat, 99)), 2)},
-        "batched_latency_ms_p99": round(ms_per_step, 4),
+                  "latency_us_p99": round(1e6 * float(np.percentile(lat, 99)), 2),
+                  "mismatched_events": plain_bad if refs else None},
         "speedup_batched_vs_plain": round(value / plain_rate, 2),
-        "work": {k: info[k] for k in ("candidates", "hits", "evals", "iters", "max_iters", "passes", "tiled",
-                                      "truncations", "hot_scans", "hotset_full", "recounts")},
+        "work": {k: info[k] for k in ("candidates", "hits", "evals", "votes", "iters", "max_iters", "passes",
+                                      "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "ordered")},
         "efficiency_eq5": eff,
         "roofline": roofline,
         "lds_roofline": lds,
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
+        "poisson20": poisson,
         "served": served,
         "refit": refit,
         "coarse_fine": coarse_fine,
@@ -249,10 +514,42 @@ def serve_bench(args, finder, log):
     dev = torch.device("cuda", 0)
     out = finder.find(torch.from_numpy(pool.z).to(dev), torch.from_numpy(pool.vane).to(dev),
                       torch.from_numpy(pool.offsets).to(dev))
-    cand, _, info = out.to_host()
+    cand, whits, info = out.to_host()
     assert info["status"] == 0
     want_nc = np.bincount(cand["event"], minlength=P)
     want_nh = np.bincount(cand["event"], weights=cand["n_hits"], minlength=P).astype(np.int64)
+    want_c0 = np.concatenate([[0], np.cumsum(want_nc)])
+    want_h0 = np.concatenate([[0], np.cumsum(want_nh)])
+    fields = [k for k in cand.dtype.names if k not in ("event", "hit_offset")]
+
+    def mismatches(r, rc, rh):
+        """Requests whose candidates (every field but the event number and the
+        hit offset, which are request-relative there) or hit lists differ from
+        the batched reference's event."""
+        ev = idx[r["tag"].astype(np.int64)]
+        bad = (r["n_candidates"] != want_nc[ev]) | (r["n_hit_index"] != want_nh[ev])
+        ok = ~bad
+        nc = r["n_candidates"][ok].astype(np.int64)
+        if nc.sum():
+            got_i = np.repeat(r["cand_offset"][ok], nc) + (np.arange(nc.sum()) - np.repeat(np.cumsum(nc) - nc, nc))
+            want_i = np.repeat(want_c0[ev[ok]], nc) + (np.arange(nc.sum()) - np.repeat(np.cumsum(nc) - nc, nc))
+            diff = np.zeros(nc.sum(), bool)
+            for k in fields:
+                diff |= rc[k][got_i] != cand[k][want_i]
+            rel = rc["hit_offset"][got_i] - rc["hit_offset"][np.repeat(r["cand_offset"][ok], nc)]
+            wrel = cand["hit_offset"][want_i] - cand["hit_offset"][np.repeat(want_c0[ev[ok]], nc)]
+            diff |= rel != wrel
+            req = np.repeat(np.nonzero(ok)[0], nc)
+            bad[np.unique(req[diff])] = True
+        nh = r["n_hit_index"][~bad].astype(np.int64)
+        if nh.sum():
+            okr = np.nonzero(~bad)[0]
+            got_i = np.repeat(r["hit_offset"][okr], nh) + (np.arange(nh.sum()) - np.repeat(np.cumsum(nh) - nh, nh))
+            want_i = np.repeat(want_h0[ev[okr]], nh) + (np.arange(nh.sum()) - np.repeat(np.cumsum(nh) - nh, nh))
+            diff = rh[got_i] != whits[want_i]
+            req = np.repeat(okr, nh)
+            bad[np.unique(req[diff])] = True
+        return int(bad.sum())
 
     rates = [float(r) for r in args.serve_rates.split(",") if r] + [float("inf")]
     res = []
@@ -271,6 +568,7 @@ def serve_bench(args, finder, log):
             sub = 0
             recs = []
             got = 0
+            mism = 0
             chunk = 8192 if rate == float("inf") else 4096
             while got < n:
                 now = srv.clock()
@@ -285,17 +583,16 @@ def serve_bench(args, finder, log):
                                      tags=np.arange(sub, hi, dtype=np.uint64), t_arrival=arr[sub:hi])
                     assert acc == hi - sub, (acc, hi - sub)
                     sub = hi
-                r, _, _ = srv.poll_records()
+                r, rc, rh = srv.poll_records()
                 if len(r):
                     recs.append(r)
                     got += len(r)
+                    mism += mismatches(r, rc, rh)
                 else:
                     time.sleep(0.0002)
             r = np.concatenate(recs)
             st1 = srv.stats()
             assert (r["status"] == 0).all()
-            ev = idx[r["tag"].astype(np.int64)]
-            mism = int(((r["n_candidates"] != want_nc[ev]) | (r["n_hit_index"] != want_nh[ev])).sum())
             lat = r["t_done"] - r["t_arrival"]
             span = float(r["t_done"].max() - r["t_arrival"].min())
             launches = st1["launches"] - st0["launches"]
@@ -504,7 +801,7 @@ def seeded_fraction(batch, cand, hit_index, min_hits):
     return hit / max(findable, 1), findable
 
 
-def coarse_fine_bench(args, batch, z, vane, offs, log, lds_vote_peak=None):
+def coarse_fine_bench(args, batch, z, vane, offs, log, lds_vote_peak=None, refs=None):
     """The paper's two-stage histogram (18 x 100 coarse, 10 x 10 fine, on the
     180 x 1000 grid) on the same pileup-50 batch, against full-grid argmax and
     nms on the same grid: events/s, finder kernel time, Eq. (4) evaluations,
@@ -544,7 +841,10 @@ def coarse_fine_bench(args, batch, z, vane, offs, log, lds_vote_peak=None):
                      if lds_vote_peak else None,
                      "candidates": info["candidates"], "iters": info["iters"],
                      "seeded_track_fraction": round(frac, 4),
-                     "efficiency_eq5": e5["efficiency"], "efficiency_eq5_findable": e5["efficiency_findable"]}
+                     "efficiency_eq5": e5["efficiency"], "efficiency_eq5_findable": e5["efficiency_findable"],
+                     "ordered": info["ordered"],
+                     "parity": parity_record(cand, hits, refs["cf_" + name], N_EVENTS)
+                     if refs and ("cf_" + name) in refs else None}
         res["findable_tracks"] = findable
         log("coarse-fine leg, %s: %s" % (name, res[name]))
     cf = res["coarse_fine"]

@@ -158,7 +158,9 @@ typedef struct {
 #define HOUGH_COUNT_VOTES 14        /* histogram votes cast by the finder kernel
                                       (LDS atomic adds; the part of EVALS
                                       that fills histograms there)        */
-/* entry 15 is written as 0 */
+#define HOUGH_COUNT_ORDERED 15       /* 1 when the call ran its events longest
+                                      first (more events than finder
+                                      workgroups resident at once), else 0 */
 
 /* Largest hit count of one event. */
 #define HOUGH_MAX_EVENT_HITS 131072
@@ -257,6 +259,22 @@ hough_status hough_launch_shape(const hough_ctx *ctx, int32_t *tile_rows, int32_
  * of launches measured since the last reset (it synchronises those events). */
 hough_status hough_set_timing(hough_ctx *ctx, int enable);
 hough_status hough_timing(hough_ctx *ctx, double *find_kernel_ms, int64_t *launches, int reset);
+
+/*
+ * Per-event clock stamps (a measurement aid for per-event latency in batched
+ * calls). While set, every finder call of at most max_events events made on
+ * ctx (and every graph captured meanwhile) writes, for each event e,
+ * stamps[2 e] = the device wall clock when the event's finder workgroup
+ * started and stamps[2 e + 1] = the wall clock once that workgroup had
+ * written the event's last output (before the compaction into the caller's
+ * arrays). stamps is a device buffer of 2 * max_events uint64 owned by the
+ * caller, who keeps it alive while set; NULL or max_events <= 0 turns the
+ * stamps off. Calls of more events write none. hough_clock_rate gives the
+ * wall clock's ticks per second on `device`. HOUGH_ERR_INVALID_ARG for a bad
+ * context or null output, HOUGH_ERR_DEVICE if the rate query fails.
+ */
+hough_status hough_set_event_clock(hough_ctx *ctx, uint64_t *stamps, int64_t max_events);
+hough_status hough_clock_rate(int device, double *ticks_per_s);
 
 /*
  * Captured launch (batched form). Records the kernel sequence hough_find

@@ -41,6 +41,7 @@ constexpr int kSegWords = kCfStage / kWave;  // 64-hit words per association seg
 extern __shared__ __align__(16) uint32_t cf_lds[];
 
 struct CfShared {
+    unsigned long long t_start;  // wall clock at the workgroup's start (event clock stamps)
     int bad;
     int ncand;
     int nhit;
@@ -348,6 +349,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
     const int64_t b = uniform64(A.offsets[e]);
     const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
     if (threadIdx.x == 0) {
+        if (A.ev_clock != nullptr) sh.t_start = wall_clock64();
         int bad = 0;
         if (b < 0 || n64 < 0 || b + n64 > A.n_total) bad = HOUGH_ERR_INVALID_ARG;
         if (e == 0 && b != 0) bad = HOUGH_ERR_INVALID_ARG;
@@ -370,6 +372,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
                 write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
             else
                 put_ev_stats(A, e, CfStats{0ull, 0, 0, 0});
+            stamp_event(A, e, sh.t_start);
         }
         return;
     }
@@ -409,7 +412,10 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
             atomicMin(&A.err[0], (long long)HOUGH_ERR_DATA);
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
-            if (A.counts == nullptr) put_ev_stats(A, e, CfStats{0ull, 0, 0, 0});
+            if (A.counts == nullptr) {
+                put_ev_stats(A, e, CfStats{0ull, 0, 0, 0});
+                stamp_event(A, e, sh.t_start);
+            }
         }
         if (A.counts != nullptr) {
             // first invalid hit of the event (the only event of the call)
@@ -419,6 +425,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
                 A.err[0] = 0;
                 A.err[1] = 0x7fffffffffffffffll;
                 write_error_counts(A.counts, HOUGH_ERR_DATA, first);
+                stamp_event(A, e, sh.t_start);
             }
         }
         return;
@@ -443,6 +450,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
             for (int i = HOUGH_COUNT_TILED; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
             A.counts[HOUGH_COUNT_LARGE] = st.unstaged;
             A.counts[HOUGH_COUNT_VOTES] = (long long)st.evals;
+            stamp_event(A, e, sh.t_start);
         }
         return;
     }
@@ -450,6 +458,7 @@ __global__ __launch_bounds__(NT) void k_find_cf(FindArgs A, const float2 *__rest
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
         put_ev_stats(A, e, st);
+        stamp_event(A, e, sh.t_start);
     }
 }
 
@@ -459,6 +468,19 @@ int cf_lds_bytes(int c_bins, int f_bins, int wg_threads) {
     // histograms, staged (phi, z), pool and match words, the two maxima
     (void)wg_threads;
     return ((4 * c_bins + 15) & ~15) + ((4 * f_bins + 15) & ~15) + 8 * kCfStage + 16 * kSegWords + 16;
+}
+
+hipError_t cf_blocks_per_cu(int wg_threads, int lds_bytes, int *blocks) {
+    switch (wg_threads) {
+    case 256:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_find_cf<256>, 256, lds_bytes);
+    case 512:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_find_cf<512>, 512, lds_bytes);
+    case 1024:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_find_cf<1024>, 1024, lds_bytes);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t set_cf_lds_limit(int wg_threads, int lds_bytes) {

@@ -259,6 +259,14 @@ hough_status choose_shape(Ctx &c, std::string &why) {
             why = "hipFuncSetAttribute failed for the coarse-to-fine kernel";
             return HOUGH_ERR_DEVICE;
         }
+        // the longest-first gate compares a call's events with the finder
+        // workgroups resident at once: those of this kernel
+        int per_cu = 0;
+        if (hough::cf_blocks_per_cu(c.wg_threads, c.lds_bytes, &per_cu) != hipSuccess || per_cu < 1) {
+            why = "occupancy query failed for the coarse-to-fine kernel";
+            return HOUGH_ERR_DEVICE;
+        }
+        c.max_resident = per_cu * prop.multiProcessorCount;
     }
     return HOUGH_OK;
 }
@@ -436,6 +444,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         if (so != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("order launch failed: ") + hipGetErrorString(so));
         a.order = w.order;
     }
+    if (c.ev_clock != nullptr && n_events <= c.ev_clock_events) a.ev_clock = c.ev_clock;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed && n_events > 0) {
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -466,6 +475,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     ca.cand = cand;
     ca.hit_index = hit_index;
     ca.counts = counts;
+    ca.ordered = a.order != nullptr ? 1 : 0;
     if (hough::launch_compact(ca, s) != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, "compaction launch failed");
     return HOUGH_OK;
 }
@@ -707,6 +717,28 @@ hough_status hough_set_timing(hough_ctx *ctx, int enable) {
     Ctx *c = as_ctx(ctx);
     if (!c) return HOUGH_ERR_INVALID_ARG;
     c->timing = enable != 0;
+    return HOUGH_OK;
+}
+
+hough_status hough_set_event_clock(hough_ctx *ctx, uint64_t *stamps, int64_t max_events) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
+    if (stamps == nullptr || max_events <= 0) {
+        c->ev_clock = nullptr;
+        c->ev_clock_events = 0;
+        return HOUGH_OK;
+    }
+    c->ev_clock = reinterpret_cast<unsigned long long *>(stamps);
+    c->ev_clock_events = max_events;
+    return HOUGH_OK;
+}
+
+hough_status hough_clock_rate(int device, double *ticks_per_s) {
+    if (!ticks_per_s) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "null output pointer");
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0)
+        return fail(nullptr, HOUGH_ERR_DEVICE, "wall clock rate query failed");
+    *ticks_per_s = 1e3 * (double)khz;
     return HOUGH_OK;
 }
 

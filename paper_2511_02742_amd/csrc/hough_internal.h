@@ -97,7 +97,20 @@ struct FindArgs {
     const float2 *ccs;
     float inv_wc;
     int32_t c_theta, c_rho, f_theta, f_rho;
+    // per-event device clock stamps (optional): ev_clock[2 e] = the wall
+    // clock when the event's finder workgroup started, ev_clock[2 e + 1] when
+    // it had written its last output; NULL = not recorded
+    unsigned long long *ev_clock;
 };
+
+// Records the event's start and retire clock stamps when the call asked for
+// them (one thread of the event's finder workgroup, after its last output).
+__device__ inline void stamp_event(const FindArgs &A, int e, unsigned long long t_start) {
+    if (A.ev_clock != nullptr) {
+        A.ev_clock[2 * (size_t)e] = t_start;
+        A.ev_clock[2 * (size_t)e + 1] = wall_clock64();
+    }
+}
 
 struct DumpArgs {
     int32_t n_theta, n_rho, n_vanes;
@@ -126,6 +139,7 @@ struct CompactArgs {
     hough_candidate *cand;
     int32_t *hit_index;
     int64_t *counts;
+    int32_t ordered;  // the finder ran the events longest first (counts[HOUGH_COUNT_ORDERED])
 };
 
 // Kernel launchers (hough_kernels.hip). Each returns the launch status.
@@ -157,6 +171,8 @@ constexpr int kCfStage = 1024;
 constexpr int kCfMaxBins = 16384;  // coarse plus fine histogram words in LDS
 int cf_lds_bytes(int c_bins, int f_bins, int wg_threads);
 hipError_t set_cf_lds_limit(int wg_threads, int lds_bytes);
+// Coarse-to-fine workgroups one CU holds at once for this shape.
+hipError_t cf_blocks_per_cu(int wg_threads, int lds_bytes, int *blocks);
 hipError_t launch_find_cf(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 
 }  // namespace hough

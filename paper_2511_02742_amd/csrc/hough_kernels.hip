@@ -136,6 +136,7 @@ __device__ __forceinline__ int next_pow2(int v) {
 }
 
 struct Shared {
+    unsigned long long t_start;  // wall clock at the workgroup's start (event clock stamps)
     int hotc[2];
     int hs_cnt;
     int pcnt;
@@ -1485,6 +1486,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
     const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
 
     if (threadIdx.x == 0) {
+        if (A.ev_clock != nullptr) sh.t_start = wall_clock64();
         int bad = 0;
         if (b < 0 || n64 < 0 || b + n64 > A.n_total) bad = HOUGH_ERR_INVALID_ARG;
         if (e == 0 && b != 0) bad = HOUGH_ERR_INVALID_ARG;
@@ -1517,6 +1519,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                 write_error_counts(A.counts, sh.bad, sh.bad == HOUGH_ERR_CAPACITY ? b : -1);
             else
                 put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0, 0ull);
+            stamp_event(A, e, sh.t_start);
         }
         return;
     }
@@ -1547,7 +1550,10 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             atomicMin(&A.err[0], (long long)HOUGH_ERR_DATA);
             A.ev_ncand[e] = 0;
             A.ev_nhits[e] = 0;
-            if (A.counts == nullptr) put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0, 0ull);
+            if (A.counts == nullptr) {
+                put_ev_stats(A, e, 0ull, 0, 0, 0, 0, 0, 0, 0, 0, 0ull);
+                stamp_event(A, e, sh.t_start);
+            }
         }
         if (A.counts != nullptr) {
             // first invalid hit of the event (the only event of the call)
@@ -1557,6 +1563,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
                 A.err[0] = 0;
                 A.err[1] = 0x7fffffffffffffffll;
                 write_error_counts(A.counts, HOUGH_ERR_DATA, first);
+                stamp_event(A, e, sh.t_start);
             }
         }
         return;
@@ -1808,7 +1815,8 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
             A.counts[HOUGH_COUNT_RECOUNTS] = recounts;
             A.counts[HOUGH_COUNT_LARGE] = bigs;
             A.counts[HOUGH_COUNT_VOTES] = (long long)votes;
-            A.counts[HOUGH_COUNT_VOTES + 1] = 0;
+            A.counts[HOUGH_COUNT_ORDERED] = 0;
+            stamp_event(A, e, sh.t_start);
         }
         return;
     }
@@ -1816,6 +1824,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
         put_ev_stats(A, e, evals, iter, passes, tiled, sh.n_trunc, sh.n_hotscan, hs_full, recounts, bigs, votes);
+        stamp_event(A, e, sh.t_start);
     }
 }
 
@@ -1974,7 +1983,7 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
         A.counts[HOUGH_COUNT_RECOUNTS] = (long long)tot[kEvRecounts];
         A.counts[HOUGH_COUNT_LARGE] = (long long)tot[kEvLarge];
         A.counts[HOUGH_COUNT_VOTES] = (long long)tot[kEvVotes];
-        A.counts[HOUGH_COUNT_VOTES + 1] = 0;
+        A.counts[HOUGH_COUNT_ORDERED] = A.ordered;
         // leave the error words cleared for the next call
         A.err[0] = 0;
         A.err[1] = 0x7fffffffffffffffll;

@@ -68,6 +68,10 @@ struct Ctx {
     int dump_rows = 0, dump_lds = 0;
     Workspace ws;
     int graphs = 0;  // live captured graphs (they reference the tables)
+    // per-event device clock stamps: caller-owned device buffer of
+    // 2 * ev_clock_events words, written by calls of at most that many events
+    unsigned long long *ev_clock = nullptr;
+    int64_t ev_clock_events = 0;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;

@@ -26,11 +26,11 @@ HOUGH_ERR_DATA = -6
 
 HOUGH_COUNTS = 16
 COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_iters", "passes",
-               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "votes", "r15")
+               "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "votes", "ordered")
 
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
-           "hough_timing", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
+           "hough_timing", "hough_set_event_clock", "hough_clock_rate", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
            "hough_autotune", "hough_server_create", "hough_server_destroy", "hough_server_clock",
            "hough_server_submit", "hough_server_poll", "hough_server_drain", "hough_server_get_stats",
            "hough_refit_gather", "hough_refit_init", "hough_refit_chi2", "hough_refit_grad",
@@ -115,6 +115,10 @@ def load_library(path: str = LIB_PATH):
     lib.hough_set_timing.restype = st
     lib.hough_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), ctypes.c_int]
     lib.hough_timing.restype = st
+    lib.hough_set_event_clock.argtypes = [P, P, I64]
+    lib.hough_set_event_clock.restype = st
+    lib.hough_clock_rate.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.hough_clock_rate.restype = st
     lib.hough_lds_peak.argtypes = [ctypes.c_int, P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.hough_lds_peak.restype = st
     lib.hough_graph_create.argtypes = [P, I32, I64, P, P, P, P, I64, P, I64, P, ctypes.POINTER(P)]
@@ -337,6 +341,20 @@ class HoughFinder:
     def set_timing(self, enable: bool):
         self.lib.hough_set_timing(self._h, 1 if enable else 0)
 
+    def set_event_clock(self, stamps=None):
+        """Per-event clock stamps into the device uint64/int64 tensor
+        `stamps` of 2 * max_events entries ((start, retire) per event) for
+        calls of at most max_events events; None turns them off. The tensor
+        must stay alive while set."""
+        if stamps is None:
+            st = self.lib.hough_set_event_clock(self._h, None, 0)
+        else:
+            assert stamps.is_cuda and stamps.element_size() == 8 and stamps.is_contiguous()
+            st = self.lib.hough_set_event_clock(self._h, ctypes.c_void_p(stamps.data_ptr()), stamps.numel() // 2)
+        if st != HOUGH_OK:
+            raise self._err(st)
+        self._clock_buf = stamps
+
     def timing(self, reset: bool = True):
         ms = ctypes.c_double()
         n = ctypes.c_int64()
@@ -381,6 +399,16 @@ def lds_peak(mode: int, device: int = 0, stream=None) -> float:
     s = stream if stream is not None else torch.cuda.current_stream(device)
     out = ctypes.c_double()
     st = lib.hough_lds_peak(device, ctypes.c_void_p(s.cuda_stream), mode, ctypes.byref(out))
+    if st != HOUGH_OK:
+        raise HoughError(st, lib.hough_last_error(None).decode())
+    return out.value
+
+
+def clock_rate(device: int = 0) -> float:
+    """Ticks per second of the device wall clock the event stamps use."""
+    lib = load_library()
+    out = ctypes.c_double()
+    st = lib.hough_clock_rate(device, ctypes.byref(out))
     if st != HOUGH_OK:
         raise HoughError(st, lib.hough_last_error(None).decode())
     return out.value

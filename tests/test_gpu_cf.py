@@ -10,7 +10,7 @@ import pytest
 
 from oracle import oracle_acc_after, oracle_find, oracle_find_batch
 from paper_2511_02742_amd import eventgen
-from test_gpu_parity import FIELDS, _ocfg, assert_same, finder
+from test_gpu_parity import FIELDS, _ocfg, assert_same, finder, full_size_reference, order_edge_events
 
 pytestmark = pytest.mark.gpu
 
@@ -185,30 +185,26 @@ def test_invalid_hits_reported(gpu_available):
     check(b, "after error")
 
 
-def test_full_size_batch_sampled(gpu_available):
-    # 4096 pileup-50 events in one launch: the oracle on a sample, structure
-    # on every event
+def test_full_size_batch(gpu_available):
+    # 4096 pileup-50 events in one launch, run longest first: every event
+    # byte-equal to the oracle, and the evaluation count derived from it
     b = eventgen.pileup_batch(4096)
     f = finder(**PAPER)
-    cand, hits, info = f.find_host(b.z, b.vane, b.offsets)
-    assert info["status"] == 0
-    ev = cand["event"]
-    assert np.all(np.diff(ev) >= 0)
-    assert np.all(cand["n_hits"] >= 6) and np.all(cand["n_hits"] >= cand["peak_votes"])
-    assert np.array_equal(np.concatenate([[0], np.cumsum(cand["n_hits"])[:-1]]), cand["hit_offset"])
-    ocfg = _ocfg(f.config)
-    for e_id in list(range(0, 4096, 61)) + [4095]:
-        lo, hi = b.offsets[e_id], b.offsets[e_id + 1]
-        want = oracle_find(ocfg, b.z[lo:hi], b.vane[lo:hi], event_id=e_id)
-        sel = np.nonzero(ev == e_id)[0]
-        ce = cand[sel]
-        assert len(ce) == len(want.cand), e_id
-        for fld in FIELDS:
-            if fld != "hit_offset":
-                assert np.array_equal(ce[fld], want.cand[fld]), (e_id, fld)
-        if len(ce):
-            base = ce["hit_offset"][0]
-            assert np.array_equal(hits[base:base + len(want.hit_index)], want.hit_index)
+    got = f.find_host(b.z, b.vane, b.offsets)
+    want = full_size_reference(_ocfg(f.config), b)
+    assert_same(got, want, "coarse-to-fine full-size batch")
+    assert got[2]["ordered"] == 1, got[2]
+    assert got[2]["evals"] == expected_evals(f.config, b.offsets, want.cand)
+
+
+def test_longest_first_order_edge_sizes(gpu_available):
+    # more events than resident coarse-to-fine workgroups (256 threads, about
+    # 17 KB of LDS: 8 per CU, 2048 on the device): ordered, every event once
+    evs = order_edge_events(2600, seed0=13000)
+    got, want = check(eventgen.make_batch(evs), "cf order edges")
+    assert got[2]["ordered"] == 1, got[2]
+    got, _ = check(eventgen.make_batch(evs[:1500]), "cf order edges, 1500 events")
+    assert got[2]["ordered"] == 0, got[2]
 
 
 def test_graph_replays_match_oracle(gpu_available):

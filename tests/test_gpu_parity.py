@@ -121,13 +121,11 @@ def test_every_register_batch_width(gpu_available, assoc_window):
         check_batch(eventgen.make_batch([e]), "width %d alone" % n, assoc_window=assoc_window)
 
 
-def test_longest_first_order_edge_sizes(gpu_available):
-    # a call of more events than resident finder workgroups runs them longest
-    # first: empty and one-hit events, events above 1023 hits (one shared
-    # bucket of the ordering sort) and many events of one size must all come
-    # out once, in event order
+def order_edge_events(n_events, seed0=9500):
+    """Events that stress the longest-first ordering: empty, one-hit, above
+    1023 hits (one shared bucket of the ordering sort) and many of one size."""
     evs = []
-    for i in range(630):
+    for i in range(n_events):
         kind = i % 7
         if kind == 0:
             e = eventgen.make_event(1, 0, noise_frac=0.0)                        # empty
@@ -137,14 +135,25 @@ def test_longest_first_order_edge_sizes(gpu_available):
         elif kind == 2:
             e = eventgen.pileup_event(9500 + i, n_tracks=260)                     # above 1023 hits
         else:
-            e = eventgen.pileup_event(9500 + i, n_tracks=50)
+            e = eventgen.pileup_event(seed0 + i, n_tracks=50)
             e.z, e.vane, e.r, e.track = e.z[:200], e.vane[:200], e.r[:200], e.track[:200]  # one size
         evs.append(e)
     assert max(e.n_hits for e in evs) > 1023
-    # (630 events: more than the 256 finder workgroups of 1024 threads an
-    # MI355X holds at once)
+    return evs
+
+
+def test_longest_first_order_edge_sizes(gpu_available):
+    # a call of more events than resident finder workgroups runs them longest
+    # first; every event must come out once, in event order. (630 events: more
+    # than the 256 finder workgroups of 1024 threads an MI355X holds at once;
+    # the ordered flag fails the test if that stops being so)
+    evs = order_edge_events(630)
     got, want = check_batch(eventgen.make_batch(evs), "order edges")
     assert len(want.cand) > 0
+    assert got[2]["ordered"] == 1, got[2]
+    # a call of no more events than resident workgroups is not ordered
+    got, _ = check_batch(eventgen.make_batch(evs[:200]), "order edges, 200 events")
+    assert got[2]["ordered"] == 0, got[2]
 
 
 def test_uneven_batch(gpu_available):
@@ -298,42 +307,29 @@ def test_recount_iterations_used(gpu_available):
     assert got[2]["recounts"] >= got[2]["iters"] - 16, got[2]
 
 
+_full_ref = {}
+
+
+def full_size_reference(ocfg, b):
+    """The oracle's output for every event of a batch (independent processes
+    over event slices, concatenated: the same arrays as one batch call)."""
+    import os
+    from oracle.oracle import oracle_find_batch_sliced
+    key = (repr(ocfg), len(b.offsets), int(b.offsets[-1]))
+    if key not in _full_ref:
+        _full_ref[key] = oracle_find_batch_sliced(ocfg, b.offsets, b.z, b.vane,
+                                                  workers=min(16, os.cpu_count() or 1))
+    return _full_ref[key]
+
+
 @pytest.mark.parametrize("kw", [{}, {"sweep_groups": 2}])
-def test_full_size_batch_sampled(gpu_available, kw):
-    # 4096 pileup-50 events in one launch (the benchmark configuration):
-    # oracle on a sample, structural properties on every event.
+def test_full_size_batch(gpu_available, kw):
+    # 4096 pileup-50 events in one launch (the benchmark configuration, run
+    # longest event first): every event byte-equal to the oracle
     b = eventgen.pileup_batch(4096)
     f = finder(**kw)
-    cand, hits, info = run_batch(f, b)
-    assert info["status"] == 0
-    ev = cand["event"]
-    assert np.all(np.diff(ev) >= 0)
-    assert np.all(cand["n_hits"] >= 6) and np.all(cand["n_hits"] <= cand["peak_votes"])
-    assert np.array_equal(np.concatenate([[0], np.cumsum(cand["n_hits"])[:-1]]), cand["hit_offset"])
-    ocfg = _ocfg(f.config)
-    for e_id in list(range(0, 4096, 97)) + [4095]:
-        lo, hi = b.offsets[e_id], b.offsets[e_id + 1]
-        want = oracle_find(ocfg, b.z[lo:hi], b.vane[lo:hi], event_id=e_id)
-        sel = np.nonzero(ev == e_id)[0]
-        ce = cand[sel]
-        assert len(ce) == len(want.cand), e_id
-        for fld in FIELDS:
-            if fld == "hit_offset":
-                continue
-            assert np.array_equal(ce[fld], want.cand[fld]), (e_id, fld)
-        if len(ce):
-            base = ce["hit_offset"][0]
-            assert np.array_equal(hits[base:base + len(want.hit_index)], want.hit_index)
-    # hit lists of one event are disjoint and inside the event
-    for e_id in range(0, 4096, 13):
-        sel = np.nonzero(ev == e_id)[0]
-        if len(sel) == 0:
-            continue
-        base = cand["hit_offset"][sel[0]]
-        nh = int(cand["n_hits"][sel].sum())
-        hs = hits[base:base + nh]
-        assert len(np.unique(hs)) == nh
-        assert hs.min() >= 0 and hs.max() < b.offsets[e_id + 1] - b.offsets[e_id]
+    got = run_batch(f, b)
+    assert_same(got, full_size_reference(_ocfg(f.config), b), "full-size batch %s" % kw)
 
 
 def test_empty_batch(gpu_available):
@@ -428,6 +424,67 @@ def test_graph_replays_match_oracle(gpu_available, kw, n_events):
         # eager work on the same context between replays
         check_batch(other, "eager between replays", **kw)
     g.close()
+
+
+@pytest.mark.parametrize("kw", [{}, {"n_theta": 180, "n_rho": 1000, "peak_mode": 2}])
+def test_graph_replays_ordered_call(gpu_available, kw):
+    # a captured call of more events than resident finder workgroups (so the
+    # ordering kernel is captured too), mixed sizes; every replay against the
+    # oracle, eager calls on the same context between replays
+    import torch
+    f = finder(**kw)
+    n_ev = 630 if kw.get("peak_mode", 1) != 2 else 2600
+    b = eventgen.make_batch(order_edge_events(n_ev, seed0=12000))
+    dev = torch.device("cuda", 0)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.vane).to(dev)
+    o = torch.from_numpy(b.offsets).to(dev)
+    want = oracle_find_batch(_ocfg(f.config), b.offsets, b.z, b.vane)
+    other = eventgen.pileup_batch(3, seed0=12100)
+    g = f.capture(z, v, o)
+    for rep in range(3):
+        out = g.launch()
+        torch.cuda.synchronize(dev)
+        got = out.to_host()
+        assert_same(got, want, "ordered replay %d" % rep)
+        assert got[2]["ordered"] == 1, got[2]
+        check_batch(other, "eager between replays", **kw)
+    g.close()
+
+
+def test_event_clock_stamps(gpu_available):
+    # per-event device clock stamps: set for calls up to 128 events, every
+    # event stamped with start <= retire inside the call's span; outputs
+    # unchanged; a larger call writes none; turned off, nothing is written
+    import torch
+    from paper_2511_02742_amd.hough import clock_rate
+    f = finder()
+    dev = torch.device("cuda", 0)
+    rate = clock_rate(0)
+    assert 1e6 <= rate <= 1e10
+    b = eventgen.poisson_batch(96, seed0=12500)
+    stamps = torch.zeros(2 * 128, dtype=torch.int64, device=dev)
+    f.set_event_clock(stamps)
+    try:
+        check_batch(b, "with clock stamps")
+        s = stamps.cpu().numpy().reshape(-1, 2)
+        assert np.all(s[:96, 0] > 0) and np.all(s[:96, 1] >= s[:96, 0]), s[:4]
+        assert np.all(s[96:] == 0)
+        span = (s[:96, 1].max() - s[:96, 0].min()) / rate
+        assert 0 < span < 1.0, span
+        # one-event calls stamp event 0
+        stamps.zero_()
+        check_batch(eventgen.make_batch([b.events[3]]), "one event with clock stamps")
+        s = stamps.cpu().numpy().reshape(-1, 2)
+        assert s[0, 0] > 0 and s[0, 1] >= s[0, 0] and np.all(s[1:] == 0)
+        # a call of more events than the buffer holds writes nothing
+        stamps.zero_()
+        check_batch(eventgen.poisson_batch(200, seed0=12600), "above the stamp capacity")
+        assert int(stamps.abs().sum()) == 0
+    finally:
+        f.set_event_clock(None)
+    check_batch(b, "stamps off")
+    assert int(stamps.abs().sum()) == 0
 
 
 def test_autotune_picks_a_shape_that_matches(gpu_available):
