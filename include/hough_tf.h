@@ -230,6 +230,30 @@ hough_status hough_find(hough_ctx *ctx, void *stream, int32_t n_events, int64_t 
                         int32_t *hit_index, int64_t hit_capacity, int64_t *counts);
 
 /*
+ * hough_find for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, outputs and errors as for hough_find; the caller still owns
+ * every input and output. The finder's workspace is not the context's
+ * (grown with hipMalloc) but a fixed device array of the library, of
+ * HOUGH_NOALLOC_SCRATCH_BYTES (64 MiB) on each device it runs on, held until
+ * the process ends; the call allocates nothing. The workspace needs about
+ * 27 B per hit and 112 B per event plus 64 KiB per large-event slot (one per
+ * finder workgroup resident at once, 16 MiB for the default shape), so about
+ * 1.7 M hits per call fit; a larger call returns HOUGH_ERR_CAPACITY with the
+ * bytes it would need (hough_last_error) and enqueues nothing. Events with
+ * more than 4096 window peaks in one iteration take the tiled sweep here (the
+ * result is the same). Every call on one device shares that device's array
+ * and clears what it needs cleared: calls that overlap on one device (two
+ * streams, two contexts, two host threads) race and must be ordered by the
+ * caller. Not timed by hough_set_timing.
+ */
+#define HOUGH_NOALLOC_SCRATCH_BYTES (64ull << 20)
+hough_status hough_find_noalloc(hough_ctx *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
+                                const int64_t *event_offsets, const float *z, const int16_t *vane,
+                                hough_candidate *cand, int64_t cand_capacity, int32_t *hit_index,
+                                int64_t hit_capacity, int64_t *counts);
+
+/*
  * Debug view of the vote histogram of one event (Sec. 5: the histogram that
  * Eq. (4) fills, one vote per hit and theta bin): acc_out (device
  * uint32[n_theta * n_rho], row-major theta x rho) receives the histogram of

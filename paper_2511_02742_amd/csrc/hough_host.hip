@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -16,10 +17,52 @@
 #include "hough_runtime.h"
 #include "hough_tf.h"
 
+// Scratch of the allocation-free finder entry point (hough_find_noalloc):
+// the finder workspace for one call at a time per device, laid out afresh
+// by each call. Each device holds its own copy until the process ends. In
+// host code the name stands for nothing on the device: its device address
+// comes from hipGetSymbolAddress, per device, at context creation.
+static __device__ __align__(256) unsigned char scratch[HOUGH_NOALLOC_SCRATCH_BYTES];
+
 namespace hough {
 namespace rt {
 
 namespace {
+// Large-event slot lists of the allocation-free entry point: 4096 peak
+// entries each (64 KiB per slot) instead of 32768, so the slots of every
+// resident workgroup fit the scratch; an event with more peaks takes the
+// tiled sweep instead, with the same result.
+constexpr int32_t kNoAllocBigPk = 4096;
+
+// Device address of `scratch` per device (looked up once per device).
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_addr;
+std::vector<hipError_t> g_scratch_err;
+
+// Looks up this device's copy of the scratch with the device current.
+void init_scratch(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= device) {
+        g_scratch_addr.resize(device + 1, nullptr);
+        g_scratch_err.resize(device + 1, hipErrorNotInitialized);
+    }
+    if (g_scratch_addr[device] != nullptr) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_addr[device] = e == hipSuccess ? static_cast<char *>(ptr) : nullptr;
+}
+
+char *scratch_of(int device, hipError_t *err) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (device < 0 || device >= (int)g_scratch_addr.size()) {
+        *err = hipErrorNotInitialized;
+        return nullptr;
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_addr[device];
+}
+
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 static_assert(kHotCap % 4 == 0, "the finder reads its peak list, placed after the hot list, 16 bytes at a time");
@@ -278,17 +321,7 @@ void free_workspace(Workspace &w) {
     w = Workspace();
 }
 
-// Grows workspace w for n_hits hits and n_events events (work queued earlier
-// on stream s may still use the old block, so the stream is synchronised
-// before it is freed).
-hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_t n_events, hipStream_t s) {
-    if (w.base && n_hits <= w.hits && n_events <= w.events) return HOUGH_OK;
-    int64_t nh = std::max<int64_t>(n_hits, std::max<int64_t>(w.hits, 1024));
-    int64_t ne = std::max<int64_t>(n_events, std::max<int64_t>(w.events, 64));
-    if (w.base) {
-        nh = std::max<int64_t>(nh, w.hits + w.hits / 2);
-        ne = std::max<int64_t>(ne, w.events + w.events / 2);
-    }
+size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, char *base, Workspace *w) {
     const int64_t ncand = nh / (int64_t)c.cfg.min_votes + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
@@ -303,47 +336,63 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     // large-event slots: no more workgroups than events, nor than fit the
     // device at once, hold one at a time
     const int32_t slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ne, std::max(c.max_resident, 1)));
-    const int64_t slot_bytes = (int64_t)align256(8 * 2 * (size_t)c.big_pk);
+    const int64_t slot_bytes = (int64_t)align256(8 * 2 * (size_t)big_pk);
     const size_t o_pflags = take(4 * (size_t)slots);
     const size_t o_pool = take((size_t)slots * (size_t)slot_bytes);
+    if (base != nullptr) {
+        w->base = base;
+        w->bytes = off;
+        w->hits = nh;
+        w->events = ne;
+        w->state = reinterpret_cast<int32_t *>(base + o_state);
+        w->aidx = reinterpret_cast<int32_t *>(base + o_aidx);
+        w->aphi = reinterpret_cast<float *>(base + o_aphi);
+        w->az = reinterpret_cast<float *>(base + o_az);
+        w->hits_ws = reinterpret_cast<int32_t *>(base + o_hits);
+        w->cand_ws = reinterpret_cast<hough_candidate *>(base + o_cand);
+        w->ev_ncand = reinterpret_cast<int32_t *>(base + o_enc);
+        w->ev_nhits = reinterpret_cast<int32_t *>(base + o_enh);
+        w->ev_cout = reinterpret_cast<long long *>(base + o_eco);
+        w->ev_hout = reinterpret_cast<long long *>(base + o_eho);
+        w->ev_stats = reinterpret_cast<unsigned long long *>(base + o_evst);
+        w->err = reinterpret_cast<long long *>(base + o_err);
+        w->tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
+        w->g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
+        w->g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
+        w->order = reinterpret_cast<int32_t *>(base + o_order);
+        w->g_hs = ghs_events > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
+        w->pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
+        w->pool = reinterpret_cast<unsigned char *>(base + o_pool);
+        w->pool_slots = slots;
+        w->slot_bytes = slot_bytes;
+        w->big_pk = big_pk;
+    }
+    return off;
+}
+
+// Grows workspace w for n_hits hits and n_events events (work queued earlier
+// on stream s may still use the old block, so the stream is synchronised
+// before it is freed).
+hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_t n_events, hipStream_t s) {
+    if (w.base && n_hits <= w.hits && n_events <= w.events) return HOUGH_OK;
+    int64_t nh = std::max<int64_t>(n_hits, std::max<int64_t>(w.hits, 1024));
+    int64_t ne = std::max<int64_t>(n_events, std::max<int64_t>(w.events, 64));
+    if (w.base) {
+        nh = std::max<int64_t>(nh, w.hits + w.hits / 2);
+        ne = std::max<int64_t>(ne, w.events + w.events / 2);
+    }
+    const size_t bytes = layout_workspace(c, nh, ne, c.big_pk, nullptr, nullptr);
     if (w.base) {
         if (hipStreamSynchronize(s) != hipSuccess) return HOUGH_ERR_DEVICE;
         free_workspace(w);
     }
     void *p = nullptr;
-    if (hipMalloc(&p, off) != hipSuccess) return HOUGH_ERR_OOM;
-    char *base = static_cast<char *>(p);
-    w.base = p;
-    w.bytes = off;
-    w.hits = nh;
-    w.events = ne;
-    w.state = reinterpret_cast<int32_t *>(base + o_state);
-    w.aidx = reinterpret_cast<int32_t *>(base + o_aidx);
-    w.aphi = reinterpret_cast<float *>(base + o_aphi);
-    w.az = reinterpret_cast<float *>(base + o_az);
-    w.hits_ws = reinterpret_cast<int32_t *>(base + o_hits);
-    w.cand_ws = reinterpret_cast<hough_candidate *>(base + o_cand);
-    w.ev_ncand = reinterpret_cast<int32_t *>(base + o_enc);
-    w.ev_nhits = reinterpret_cast<int32_t *>(base + o_enh);
-    w.ev_cout = reinterpret_cast<long long *>(base + o_eco);
-    w.ev_hout = reinterpret_cast<long long *>(base + o_eho);
-    w.ev_stats = reinterpret_cast<unsigned long long *>(base + o_evst);
-    w.err = reinterpret_cast<long long *>(base + o_err);
-    w.tmp_offsets = reinterpret_cast<int64_t *>(base + o_offs);
-    w.g_cnt = reinterpret_cast<int32_t *>(base + o_gcnt);
-    w.g_flag = reinterpret_cast<int32_t *>(base + o_gflag);
-    w.order = reinterpret_cast<int32_t *>(base + o_order);
-    w.g_hs = ghs_events > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
-    w.pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
-    w.pool = reinterpret_cast<unsigned char *>(base + o_pool);
-    w.pool_slots = slots;
-    w.slot_bytes = slot_bytes;
+    if (hipMalloc(&p, bytes) != hipSuccess) return HOUGH_ERR_OOM;
+    layout_workspace(c, nh, ne, c.big_pk, static_cast<char *>(p), &w);
     // error and split-sweep words start cleared; every call
     // leaves them so
-    if (hough::launch_reset(w.err, s) != hipSuccess) return HOUGH_ERR_DEVICE;
-    if (hough::launch_zero_i32(w.g_cnt, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
-    if (hough::launch_zero_i32(w.g_flag, ne, s) != hipSuccess) return HOUGH_ERR_DEVICE;
-    if (hough::launch_zero_i32(w.pool_flags, slots, s) != hipSuccess) return HOUGH_ERR_DEVICE;
+    if (hough::launch_clear_workspace(w.err, w.g_cnt, w.g_flag, ne, w.pool_flags, w.pool_slots, s) != hipSuccess)
+        return HOUGH_ERR_DEVICE;
     return HOUGH_OK;
 }
 
@@ -391,7 +440,7 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     a.pool = w.pool;
     a.pool_flags = w.pool_flags;
     a.pool_slots = w.pool_slots;
-    a.big_pk = c.big_pk;
+    a.big_pk = w.big_pk;
     a.big_sort = c.big_sort;
     a.big_ok = c.big_ok;
     a.roll_off = c.roll_off;
@@ -510,6 +559,7 @@ hough_status make_context(const hough_config *cfg, int device, Ctx **out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(nullptr, HOUGH_ERR_INVALID_ARG, "no such device");
     if (hipSetDevice(device) != hipSuccess) return fail(nullptr, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    init_scratch(device);
     Ctx *c = new (std::nothrow) Ctx();
     if (!c) return fail(nullptr, HOUGH_ERR_OOM, "host allocation failed");
     c->cfg = *cfg;
@@ -631,6 +681,42 @@ hough_status hough_find(hough_ctx *ctx, void *stream, int32_t n_events, int64_t 
     if (st) return fail(c, st, "workspace allocation failed");
     st = enqueue_find(*c, c->ws, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand,
                       hit_index, counts, c->timing, true);
+    if (st) return st;
+    c->last_error.clear();
+    return HOUGH_OK;
+}
+
+hough_status hough_find_noalloc(hough_ctx *ctx, void *stream, int32_t n_events, int64_t n_hits_total,
+                                const int64_t *event_offsets, const float *z, const int16_t *vane,
+                                hough_candidate *cand, int64_t cand_capacity, int32_t *hit_index,
+                                int64_t hit_capacity, int64_t *counts) {
+    Ctx *c = as_ctx(ctx);
+    if (!c) return fail(nullptr, HOUGH_ERR_INVALID_ARG, "bad context");
+    hough_status st = check_find_args(c, n_events, n_hits_total, event_offsets, z, vane, cand, cand_capacity,
+                                      hit_index, hit_capacity, counts);
+    if (st) return st;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipSetDevice failed");
+    hipError_t se = hipSuccess;
+    char *base = scratch_of(c->device, &se);
+    if (base == nullptr)
+        return fail(c, HOUGH_ERR_DEVICE, std::string("scratch address lookup failed: ") + hipGetErrorString(se));
+    const int64_t nh = std::max<int64_t>(n_hits_total, 1), ne = std::max<int32_t>(n_events, 1);
+    const size_t need = layout_workspace(*c, nh, ne, kNoAllocBigPk, nullptr, nullptr);
+    if (need > (size_t)HOUGH_NOALLOC_SCRATCH_BYTES) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "%lld hits in %d events need %zu bytes of scratch; the scratch holds %zu",
+                 (long long)n_hits_total, n_events, need, (size_t)HOUGH_NOALLOC_SCRATCH_BYTES);
+        return fail(c, HOUGH_ERR_CAPACITY, msg);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace w;
+    layout_workspace(*c, nh, ne, kNoAllocBigPk, base, &w);
+    // the scratch holds whatever the last call left there: clear the words
+    // the finder expects at zero
+    if (hough::launch_clear_workspace(w.err, w.g_cnt, w.g_flag, ne, w.pool_flags, w.pool_slots, s) != hipSuccess)
+        return fail(c, HOUGH_ERR_DEVICE, "workspace clearing launch failed");
+    st = enqueue_find(*c, w, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand, hit_index,
+                      counts, false, true);
     if (st) return st;
     c->last_error.clear();
     return HOUGH_OK;

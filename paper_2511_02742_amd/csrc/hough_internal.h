@@ -143,12 +143,14 @@ struct CompactArgs {
 };
 
 // Kernel launchers (hough_kernels.hip). Each returns the launch status.
-hipError_t launch_reset(long long *err, hipStream_t s);  // used once per workspace
 hipError_t launch_find(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t s);
 hipError_t set_sweep_lds_limit(int threads, int lds_bytes);
 int sweep_lds_bytes(int threads, int pitch);
-hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+// Clears the error words, the split-sweep counters and flags of n_events
+// events and the slot flags (one fill kernel).
+hipError_t launch_clear_workspace(long long *err, int32_t *g_cnt, int32_t *g_flag, int64_t n_events,
+                                  int32_t *pool_flags, int32_t slots, hipStream_t s);
 // order[0, n_events): the events by descending hit count (device offsets)
 hipError_t launch_order(const int64_t *offsets, int32_t n_events, int32_t *order, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);

@@ -1880,13 +1880,6 @@ __global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restri
                     g * NW + wave, groups * NW, A.g_hs + (size_t)e * A.hs_cap, A.g_cnt + e, A.hs_cap);
 }
 
-__global__ void k_reset(long long *err) {
-    if (threadIdx.x == 0) {
-        err[0] = 0;
-        err[1] = 0x7fffffffffffffffll;
-    }
-}
-
 __global__ void k_set_offsets(int64_t *offsets, int64_t n) {
     offsets[0] = 0;
     offsets[1] = n;
@@ -2056,11 +2049,6 @@ int find_lds_extra(int wg_threads, int hcap, int pkeep) {
     return 4 * hcap + 8 * (pkeep + hcap) + 4 * wg_threads;
 }
 
-hipError_t launch_reset(long long *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, err);
-    return hipGetLastError();
-}
-
 int sweep_lds_bytes(int threads, int pitch) { return (threads / kWave) * pitch * 4 + 4 * threads; }
 
 hipError_t set_sweep_lds_limit(int threads, int lds_bytes) {
@@ -2134,9 +2122,21 @@ __global__ __launch_bounds__(kOrderBins) void k_order(const int64_t *offsets, in
     }
 }
 
-__global__ void k_zero_i32(int32_t *p, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+// Clears the words every finder call expects at zero: the error words, the
+// split-sweep counters and flags of n_events events and the large-event slot
+// flags (a plain fill kernel, so it may sit in a captured graph).
+__global__ void k_clear_ws(long long *err, int32_t *g_cnt, int32_t *g_flag, int64_t n_events, int32_t *pool_flags,
+                           int32_t slots) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_events; i += stride) {
+        g_cnt[i] = 0;
+        g_flag[i] = 0;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots; i += stride) pool_flags[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        err[0] = 0;
+        err[1] = 0x7fffffffffffffffll;
+    }
 }
 
 hipError_t launch_order(const int64_t *offsets, int32_t n_events, int32_t *order, hipStream_t s) {
@@ -2145,10 +2145,11 @@ hipError_t launch_order(const int64_t *offsets, int32_t n_events, int32_t *order
     return hipGetLastError();
 }
 
-hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
+hipError_t launch_clear_workspace(long long *err, int32_t *g_cnt, int32_t *g_flag, int64_t n_events,
+                                  int32_t *pool_flags, int32_t slots, hipStream_t s) {
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(n_events, slots), 1);
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(k_clear_ws, dim3(grid), dim3(256), 0, s, err, g_cnt, g_flag, n_events, pool_flags, slots);
     return hipGetLastError();
 }
 

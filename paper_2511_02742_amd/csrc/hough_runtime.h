@@ -38,6 +38,7 @@ struct Workspace {
     int32_t *pool_flags = nullptr;
     int32_t pool_slots = 0;
     int64_t slot_bytes = 0;
+    int32_t big_pk = 0;        // peak entries per slot list
 };
 
 struct Ctx {
@@ -100,6 +101,10 @@ void free_context(Ctx *c);
 // Grows w to hold n_hits hits and n_events events (synchronises s first when
 // an old block has to go).
 hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_t n_events, hipStream_t s);
+// Bytes of a workspace for exactly nh hits and ne events whose large-event
+// slots hold big_pk peak entries per list; with base non-NULL, also points
+// w's arrays into base (the caller clears what must start at zero).
+size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, char *base, Workspace *w);
 void free_workspace(Workspace &w);
 // Enqueues one finder call on s (split sweep, finder, compaction); outputs
 // as in hough_find. With longest_first, a call of many events runs its

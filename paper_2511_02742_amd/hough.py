@@ -25,10 +25,11 @@ HOUGH_ERR_INTERNAL = -5
 HOUGH_ERR_DATA = -6
 
 HOUGH_COUNTS = 16
+HOUGH_NOALLOC_SCRATCH_BYTES = 64 << 20   # device scratch of hough_find_noalloc
 COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_iters", "passes",
                "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "votes", "ordered")
 
-EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find",
+EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find", "hough_find_noalloc",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
            "hough_timing", "hough_set_event_clock", "hough_clock_rate", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
            "hough_autotune", "hough_server_create", "hough_server_destroy", "hough_server_clock",
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     lib.hough_output_bounds.restype = st
     lib.hough_find.argtypes = [P, P, I32, I64, P, P, P, P, I64, P, I64, P]
     lib.hough_find.restype = st
+    lib.hough_find_noalloc.argtypes = [P, P, I32, I64, P, P, P, P, I64, P, I64, P]
+    lib.hough_find_noalloc.restype = st
     lib.hough_debug_accumulator.argtypes = [P, P, I64, P, P, I32, P, P]
     lib.hough_debug_accumulator.restype = st
     lib.hough_tables.argtypes = [P, P, P, P, P, P, P]
@@ -252,8 +255,11 @@ class HoughFinder:
                           torch.empty(HOUGH_COUNTS, dtype=torch.int64, device=dev))
 
     def find(self, z, vane, offsets, out: Optional[FindOutput] = None, stream=None,
-             capacities=None) -> FindOutput:
-        """Runs the finder on device tensors z (float32), vane (int16), offsets (int64)."""
+             capacities=None, noalloc: bool = False) -> FindOutput:
+        """Runs the finder on device tensors z (float32), vane (int16), offsets
+        (int64); noalloc selects hough_find_noalloc (the library's fixed
+        device scratch instead of the context's workspace; `out` should then
+        be given, or this call allocates it)."""
         torch = self._torch
         assert z.dtype == torch.float32 and vane.dtype == torch.int16 and offsets.dtype == torch.int64
         assert z.is_contiguous() and vane.is_contiguous() and offsets.is_contiguous()
@@ -262,7 +268,8 @@ class HoughFinder:
         if out is None:
             out = self.alloc_outputs(n_events, n_hits)
         cc, hc = capacities if capacities is not None else (out.cand.shape[0], out.hit_index.numel())
-        st = self.lib.hough_find(self._h, self._stream(stream), n_events, n_hits,
+        fn = self.lib.hough_find_noalloc if noalloc else self.lib.hough_find
+        st = fn(self._h, self._stream(stream), n_events, n_hits,
                                  ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(z.data_ptr()),
                                  ctypes.c_void_p(vane.data_ptr()), ctypes.c_void_p(out.cand.data_ptr()), cc,
                                  ctypes.c_void_p(out.hit_index.data_ptr()), hc,
