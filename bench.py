@@ -258,6 +258,9 @@ def main():
     ap.add_argument("--only-batched", action="store_true",
                     help="the batched headline leg alone (for profiler runs): no oracle, plain, graph, cfg3, "
                          "served, refit or coarse-to-fine legs")
+    ap.add_argument("--finder", choices=("nms", "cf"), default="nms",
+                    help="with --only-batched: the full-grid finder on 1024x1024 (nms) or the coarse-to-fine "
+                         "finder on 180x1000 (cf) on the same events")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first, as the reference kernel for "
                          "FETCH_SIZE / WRITE_SIZE counter scaling")
@@ -326,7 +329,9 @@ def main():
     # ---- launch shape: the autotuner on this batch (its time is reported
     # apart and never counted in events/s)
     tune = None
-    if args.no_autotune:
+    if args.only_batched and args.finder == "cf":
+        f = HoughFinder(0, n_theta=180, n_rho=1000, peak_mode=2)
+    elif args.no_autotune:
         f = HoughFinder(0)
     else:
         tt0 = time.perf_counter()
@@ -356,7 +361,7 @@ def main():
         print(json.dumps({"metric": METRIC, "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
                           "kernel_avg_ms": round(kern_avg_ms, 4), "launch": shape, "autotune": tune,
-                          "only_batched": True}), flush=True)
+                          "finder": args.finder, "only_batched": True}), flush=True)
         return
 
     eff = eq5_efficiency(batch, main_cand, main_hits)

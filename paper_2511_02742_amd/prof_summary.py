@@ -13,8 +13,13 @@ The summary (markdown) states the command lines, the kernel table and the
 traffic figures; a key/value file next to it carries the figures the
 benchmark reports, with the hash of the kernel source they were taken from.
 
+* optionally any number of further ``--pmc`` runs (``--counters DIR``):
+  every counter they hold is reported for the kernel's largest-grid
+  dispatches (median over them), with the ratios named in RATIOS.
+
 python -m paper_2511_02742_amd.prof_summary --trace DIR [--fetch DIR --write DIR --copy-mib M]
-        --name NAME --command "..." [--command "..."] [--kernel k_find_cf --source hough_cf.hip]
+        [--counters DIR ...] --name NAME --command "..." [--command "..."]
+        [--kernel k_find_cf --source hough_cf.hip]
 """
 from __future__ import annotations
 
@@ -100,6 +105,45 @@ def counter_per_dispatch(pmc_dir: str, counter: str):
     return per, names
 
 
+def counters_of_largest_grid(pmc_dir: str, kernel: str):
+    """{counter: median value over the kernel's dispatches of the largest
+    grid} of every counter in one --pmc run, and the number of dispatches."""
+    files = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no counter_collection.csv under %s" % pmc_dir)
+    val = defaultdict(lambda: defaultdict(float))
+    grid = {}
+    for r in csv.DictReader(open(files[0])):
+        if not _is(r["Kernel_Name"], kernel):
+            continue
+        d = int(r["Dispatch_Id"])
+        val[r["Counter_Name"]][d] += float(r["Counter_Value"])
+        grid[d] = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
+    if not grid:
+        return {}, 0
+    gmax = max(grid.values())
+    sel = [d for d, g in grid.items() if g == gmax]
+    return {c: statistics.median(per[d] for d in sel if d in per) for c, per in val.items()}, len(sel)
+
+
+# Ratios reported when both counters were collected: (label, numerator,
+# denominator, scale).
+RATIOS = [
+    ("share of wave time waiting on any dependency (SQ_WAIT_ANY / SQ_WAVE_CYCLES)", "SQ_WAIT_ANY",
+     "SQ_WAVE_CYCLES", 1.0),
+    ("share of wave time issuing any instruction (SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES)", "SQ_ACTIVE_INST_ANY",
+     "SQ_WAVE_CYCLES", 1.0),
+    # SQ_WAVE_CYCLES counts in units of 4 cycles, SQ_BUSY_CU_CYCLES in cycles
+    # (SQ_LEVEL_WAVES reads 0 on this device)
+    ("mean resident waves per busy CU (4 SQ_WAVE_CYCLES / SQ_BUSY_CU_CYCLES)", "SQ_WAVE_CYCLES",
+     "SQ_BUSY_CU_CYCLES", 4.0),
+    ("LDS bank-conflict cycles per LDS-active cycle (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE)",
+     "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", 1.0),
+    ("VALU instructions per LDS instruction (SQ_INSTS_VALU / SQ_INSTS_LDS)", "SQ_INSTS_VALU", "SQ_INSTS_LDS", 1.0),
+    ("VALU share of issued wave instructions (SQ_INSTS_VALU / SQ_INSTS_*)", "SQ_INSTS_VALU", "_ALL_INSTS", 1.0),
+]
+
+
 def traffic(fetch_dir: str, write_dir: str, copy_mib: int, kernel: str = "k_find"):
     """HBM bytes per launch of `kernel` (median over dispatches of the largest
     grid), scaled by the counters of the calibration kernel."""
@@ -127,6 +171,7 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--counters", action="append", default=[], help="a further --pmc run directory")
     ap.add_argument("--name", required=True, help="summary base name under profiles/")
     ap.add_argument("--command", action="append", default=[], help="a command line that produced the data")
     ap.add_argument("--note", default="")
@@ -166,6 +211,24 @@ def main():
                   "| %.0f | %.0f | %.0f |" % (t["fetch_bytes"], t["write_bytes"], t["fetch_bytes"] + t["write_bytes"])]
         kv.update({"fetch_bytes_per_launch": "%.0f" % t["fetch_bytes"],
                    "write_bytes_per_launch": "%.0f" % t["write_bytes"]})
+    if args.counters:
+        allc = {}
+        nd = 0
+        for d in args.counters:
+            c, n = counters_of_largest_grid(d, K)
+            allc.update(c)
+            nd = max(nd, n)
+        insts = [k for k in allc if k.startswith("SQ_INSTS_")]
+        if insts:
+            allc["_ALL_INSTS"] = sum(allc[k] for k in insts)
+        lines += ["", "Counters of the batched %s launch (median over %d largest-grid dispatches, summed over "
+                  "the device):" % (K, nd), "", "| counter | value |", "|---|---|"]
+        for k in sorted(c for c in allc if not c.startswith("_")):
+            lines.append("| %s | %.0f |" % (k, allc[k]))
+            kv["pmc_" + k] = "%.0f" % allc[k]
+        rows = [(lab, allc[a] / allc[b] * sc) for lab, a, b, sc in RATIOS if a in allc and allc.get(b)]
+        if rows:
+            lines += ["", "| ratio | value |", "|---|---|"] + ["| %s | %.4f |" % r for r in rows]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", args.name + ".md"), "w") as f:
         f.write("\n".join(lines) + "\n")
