@@ -549,3 +549,326 @@ int orc_find_batch(const orc_config *c, int32_t n_events, const int64_t *offsets
     out[3] = votes;
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Time-sliced track finding with track extension (Sec. 4: seeds of three
+ * hits on consecutive vanes are extrapolated to neighbouring vanes, inside
+ * 10 ns windows that slide by 5 ns, and candidates flagged in one window are
+ * continued first in the next; Sec. 5: the same steps per window, with the
+ * Hough seeds of each window).
+ *
+ * Readings where the paper is silent (each one also stated in the design
+ * notes):
+ *   - a timeline's hits are sorted by time; window w holds the hits with
+ *     lo_w <= t < lo_w + width, lo_w = float(w) * step (float arithmetic);
+ *     windows are processed in order w = 0, 1, ...; a hit already in a track
+ *     is no longer in any window's pool;
+ *   - per window, first the tracks flagged in the previous window are
+ *     continued (ascending track id; each extended at its upper-vane end,
+ *     then at its lower-vane end), then the Hough finder runs on the pool
+ *     (the unused hits of the window, in hit order) and each candidate, in
+ *     emission order, seeds a track from its still unused hits;
+ *   - the seed: on each vane, the candidate's unused hit of lowest index;
+ *     the first vane v (v = 0, 1, ...) such that vanes v, v+1 and v+2
+ *     (modulo the vane count) have one and neighbouring ones differ in time
+ *     by at most gate_t gives the three seed hits;
+ *   - extrapolation: a track's hits lie on consecutive vanes; from its end
+ *     hit e3 and the two before it, e2 and e1, the next vane's hit is
+ *     predicted by the three-point (quadratic) extrapolation
+ *     x_hat = (x1 - 3 x2) + 3 x3 of r and of z, in float in that order;
+ *     the candidates are the pool hits on that vane with |r - r_hat| <=
+ *     gate_r, |z - z_hat| <= gate_z and |t - t(e3)| <= gate_t; the one of
+ *     smallest |r - r_hat| + |z - z_hat| (float) joins the track, ties to the
+ *     lower hit index; the end stops at the first vane without one, or when
+ *     the track holds max_track_hits hits;
+ *   - the continuation flag of a track after window w: it gained hits in
+ *     window w (created there, or continued) and its latest hit time is at
+ *     least lo_(w+1), i.e. it reaches into the next window;
+ *   - a track is reported with its hits in vane order from its lower-vane
+ *     end (timeline-local indices), in creation order.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    float window_ns, step_ns;
+    float gate_r, gate_z, gate_t;
+    int32_t max_track_hits;
+    int32_t reserved[2];
+} orc_tw_config;
+
+typedef struct {            /* 48 bytes */
+    int32_t timeline, track, window, n_hits;
+    int64_t hit_offset;
+    int32_t vane_first, vane_last;
+    int32_t theta_bin, rho_bin;
+    int32_t last_window, carried;
+} orc_track;
+
+typedef struct {
+    const orc_tw_config *tw;
+    int n_vanes;
+    int64_t n;
+    const float *r, *z, *t;
+    const int16_t *vane;
+    float lo, hi;            /* current window [lo, hi) */
+    int32_t *used, *up, *down;
+    int32_t *end_up, *end_down, *nh, *win, *last_win, *carried, *flag, *tb, *rb;
+    float *tmax;
+} orc_tw_state;
+
+static int orc_tw_in_pool(const orc_tw_state *S, int64_t h)
+{
+    return S->used[h] < 0 && S->t[h] >= S->lo && S->t[h] < S->hi;
+}
+
+/* Extends track k at one end (d = +1: upper vane, -1: lower vane) through
+ * the window's pool; returns the hits added. */
+static int orc_tw_extend(orc_tw_state *S, int32_t k, int d)
+{
+    int added = 0;
+    while (S->nh[k] < S->tw->max_track_hits) {
+        const int32_t e3 = d > 0 ? S->end_up[k] : S->end_down[k];
+        const int32_t e2 = d > 0 ? S->down[e3] : S->up[e3];
+        const int32_t e1 = d > 0 ? S->down[e2] : S->up[e2];
+        const int target = (S->vane[e3] + d + S->n_vanes) % S->n_vanes;
+        const float r_hat = (S->r[e1] - 3.0f * S->r[e2]) + 3.0f * S->r[e3];
+        const float z_hat = (S->z[e1] - 3.0f * S->z[e2]) + 3.0f * S->z[e3];
+        int64_t best = -1;
+        float best_s = 0.0f;
+        for (int64_t h = 0; h < S->n; ++h) {
+            if (!orc_tw_in_pool(S, h) || S->vane[h] != target) continue;
+            const float dr = fabsf(S->r[h] - r_hat), dz = fabsf(S->z[h] - z_hat);
+            const float dt = fabsf(S->t[h] - S->t[e3]);
+            if (!(dr <= S->tw->gate_r && dz <= S->tw->gate_z && dt <= S->tw->gate_t)) continue;
+            const float s = dr + dz;
+            if (best < 0 || s < best_s) {
+                best = h;
+                best_s = s;
+            }
+        }
+        if (best < 0) break;
+        if (d > 0) {
+            S->up[e3] = (int32_t)best;
+            S->down[best] = e3;
+            S->end_up[k] = (int32_t)best;
+        } else {
+            S->down[e3] = (int32_t)best;
+            S->up[best] = e3;
+            S->end_down[k] = (int32_t)best;
+        }
+        S->used[best] = k;
+        S->nh[k] += 1;
+        if (S->t[best] > S->tmax[k]) S->tmax[k] = S->t[best];
+        ++added;
+    }
+    return added;
+}
+
+static int64_t orc_tw_first_bad(const orc_config *c, int64_t n, const float *r, const float *z,
+                                const int16_t *vane, const float *t)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (vane[i] < 0 || vane[i] >= c->n_vanes || !(fabsf(z[i]) <= ORC_Z_LIMIT) || !isfinite(r[i]) ||
+            !isfinite(t[i]) || t[i] < 0.0f || (i > 0 && t[i] < t[i - 1]))
+            return i;
+    }
+    return -1;
+}
+
+/* One timeline. tracks / hit_index receive its tracks (creation order) and
+ * their hits (vane order from the lower end, timeline-local); out[0] =
+ * tracks, out[1] = hits in tracks, out[2] = Hough candidates over all
+ * windows, out[3] = windows in which a flagged track gained hits (summed
+ * over tracks). */
+int orc_tw_find(const orc_config *c, const orc_tw_config *tw, int32_t timeline_id, int64_t n, const float *r,
+                const float *z, const int16_t *vane, const float *t, int32_t n_windows, orc_track *tracks,
+                int64_t track_cap, int32_t *hit_index, int64_t hit_cap, int64_t *out)
+{
+    int st = orc_check_config(c);
+    if (st) return st;
+    if (!tw || !out || n < 0 || n_windows < 0 || tw->max_track_hits < 3 || !(tw->step_ns > 0.0f) ||
+        !(tw->window_ns >= tw->step_ns) || c->n_vanes < 3 || c->n_vanes > 1024)
+        return ORC_ERR_ARG;
+    if (orc_tw_first_bad(c, n, r, z, vane, t) >= 0) return ORC_ERR_DATA;
+    const int64_t kcap = n / 3 + 1;
+    orc_tw_state S;
+    memset(&S, 0, sizeof S);
+    S.tw = tw;
+    S.n_vanes = c->n_vanes;
+    S.n = n;
+    S.r = r;
+    S.z = z;
+    S.t = t;
+    S.vane = vane;
+    const int64_t nn = n > 0 ? n : 1;
+    S.used = malloc(sizeof(int32_t) * nn);
+    S.up = malloc(sizeof(int32_t) * nn);
+    S.down = malloc(sizeof(int32_t) * nn);
+    int32_t *k_arr = malloc(sizeof(int32_t) * 10 * kcap);
+    S.tmax = malloc(sizeof(float) * kcap);
+    float *pz = malloc(sizeof(float) * nn);
+    int16_t *pv = malloc(sizeof(int16_t) * nn);
+    int64_t *pidx = malloc(sizeof(int64_t) * nn);
+    orc_candidate *cand = malloc(sizeof(orc_candidate) * (nn / (c->min_votes ? c->min_votes : 1) + 1));
+    int32_t *chits = malloc(sizeof(int32_t) * nn);
+    int32_t *walk = malloc(sizeof(int32_t) * nn);
+    if (!S.used || !S.up || !S.down || !k_arr || !S.tmax || !pz || !pv || !pidx || !cand || !chits || !walk) {
+        st = ORC_ERR_OOM;
+        goto done;
+    }
+    S.end_up = k_arr;
+    S.end_down = k_arr + kcap;
+    S.nh = k_arr + 2 * kcap;
+    S.win = k_arr + 3 * kcap;
+    S.last_win = k_arr + 4 * kcap;
+    S.carried = k_arr + 5 * kcap;
+    S.flag = k_arr + 6 * kcap;
+    S.tb = k_arr + 7 * kcap;
+    S.rb = k_arr + 8 * kcap;
+    for (int64_t i = 0; i < n; ++i) S.used[i] = S.up[i] = S.down[i] = -1;
+    int32_t nk = 0;
+    int64_t n_cand_total = 0, n_carry = 0;
+    for (int32_t w = 0; w < n_windows; ++w) {
+        S.lo = (float)w * tw->step_ns;
+        S.hi = S.lo + tw->window_ns;
+        const float next_lo = (float)(w + 1) * tw->step_ns;
+        /* 1. continue the tracks flagged in the previous window */
+        for (int32_t k = 0; k < nk; ++k) {
+            if (!S.flag[k]) continue;
+            const int gained = orc_tw_extend(&S, k, +1) + orc_tw_extend(&S, k, -1);
+            if (gained > 0) {
+                S.carried[k] += 1;
+                S.last_win[k] = w;
+                ++n_carry;
+            }
+            S.flag[k] = gained > 0 && S.tmax[k] >= next_lo;
+        }
+        /* 2. Hough seeds on the unused hits of the window */
+        int64_t np = 0;
+        for (int64_t h = 0; h < n; ++h)
+            if (orc_tw_in_pool(&S, h)) {
+                pz[np] = z[h];
+                pv[np] = vane[h];
+                pidx[np] = h;
+                ++np;
+            }
+        if (np == 0) continue;
+        int64_t fo[4];
+        st = orc_find(c, 0, np, pz, pv, cand, np / c->min_votes + 1, chits, np, NULL, fo);
+        if (st) goto done;
+        n_cand_total += fo[0];
+        for (int64_t ci = 0; ci < fo[0]; ++ci) {
+            /* lowest unused candidate hit on each vane */
+            int64_t first[1024];
+            for (int v = 0; v < c->n_vanes && v < 1024; ++v) first[v] = -1;
+            for (uint32_t q = 0; q < cand[ci].n_hits; ++q) {
+                const int64_t h = pidx[chits[cand[ci].hit_offset + q]];
+                if (S.used[h] >= 0) continue;
+                const int v = vane[h];
+                if (first[v] < 0 || h < first[v]) first[v] = h;
+            }
+            int v0 = -1;
+            for (int v = 0; v < c->n_vanes && v0 < 0; ++v) {
+                const int64_t ha = first[v], hb = first[(v + 1) % c->n_vanes], hc = first[(v + 2) % c->n_vanes];
+                if (ha >= 0 && hb >= 0 && hc >= 0 && fabsf(t[hb] - t[ha]) <= tw->gate_t &&
+                    fabsf(t[hc] - t[hb]) <= tw->gate_t)
+                    v0 = v;
+            }
+            if (v0 < 0) continue;
+            const int32_t a = (int32_t)first[v0], b = (int32_t)first[(v0 + 1) % c->n_vanes],
+                          d = (int32_t)first[(v0 + 2) % c->n_vanes];
+            const int32_t k = nk++;
+            S.up[a] = b;
+            S.down[b] = a;
+            S.up[b] = d;
+            S.down[d] = b;
+            S.used[a] = S.used[b] = S.used[d] = k;
+            S.end_down[k] = a;
+            S.end_up[k] = d;
+            S.nh[k] = 3;
+            S.win[k] = w;
+            S.last_win[k] = w;
+            S.carried[k] = 0;
+            S.tb[k] = cand[ci].theta_bin;
+            S.rb[k] = cand[ci].rho_bin;
+            S.tmax[k] = t[a];
+            if (t[b] > S.tmax[k]) S.tmax[k] = t[b];
+            if (t[d] > S.tmax[k]) S.tmax[k] = t[d];
+            orc_tw_extend(&S, k, +1);
+            orc_tw_extend(&S, k, -1);
+            S.flag[k] = S.tmax[k] >= next_lo;
+        }
+    }
+    /* output: tracks in creation order, hits from the lower-vane end */
+    if (nk > track_cap) { st = ORC_ERR_CAPACITY; goto done; }
+    int64_t nh_tot = 0;
+    for (int32_t k = 0; k < nk; ++k) nh_tot += S.nh[k];
+    if (nh_tot > hit_cap) { st = ORC_ERR_CAPACITY; goto done; }
+    int64_t off = 0;
+    for (int32_t k = 0; k < nk; ++k) {
+        orc_track *T = &tracks[k];
+        T->timeline = timeline_id;
+        T->track = k;
+        T->window = S.win[k];
+        T->n_hits = S.nh[k];
+        T->hit_offset = off;
+        T->vane_first = vane[S.end_down[k]];
+        T->vane_last = vane[S.end_up[k]];
+        T->theta_bin = S.tb[k];
+        T->rho_bin = S.rb[k];
+        T->last_window = S.last_win[k];
+        T->carried = S.carried[k];
+        int32_t h = S.end_down[k], m = 0;
+        while (h >= 0) {
+            walk[m++] = h;
+            h = S.up[h];
+        }
+        memcpy(hit_index + off, walk, sizeof(int32_t) * (size_t)m);
+        off += m;
+    }
+    out[0] = nk;
+    out[1] = off;
+    out[2] = n_cand_total;
+    out[3] = n_carry;
+    st = ORC_OK;
+done:
+    free(S.used);
+    free(S.up);
+    free(S.down);
+    free(k_arr);
+    free(S.tmax);
+    free(pz);
+    free(pv);
+    free(pidx);
+    free(cand);
+    free(chits);
+    free(walk);
+    return st;
+}
+
+/* Several timelines (CSR offsets); tracks of timeline b follow those of
+ * b - 1, hit_offset counts over the whole output; out[0..3] are sums, and
+ * the first failing timeline's status is returned. */
+int orc_tw_find_batch(const orc_config *c, const orc_tw_config *tw, int32_t n_tl, const int64_t *offsets,
+                      const float *r, const float *z, const int16_t *vane, const float *t, int32_t n_windows,
+                      orc_track *tracks, int64_t track_cap, int32_t *hit_index, int64_t hit_cap, int64_t *out)
+{
+    if (!out || n_tl < 0 || !offsets) return ORC_ERR_ARG;
+    int64_t nt = 0, nh = 0, ncand = 0, ncarry = 0;
+    for (int32_t b = 0; b < n_tl; ++b) {
+        const int64_t lo = offsets[b], n = offsets[b + 1] - offsets[b];
+        int64_t o[4];
+        int st = orc_tw_find(c, tw, b, n, r + lo, z + lo, vane + lo, t + lo, n_windows, tracks + nt,
+                             track_cap - nt, hit_index + nh, hit_cap - nh, o);
+        if (st) return st;
+        for (int64_t k = 0; k < o[0]; ++k) tracks[nt + k].hit_offset += nh;
+        nt += o[0];
+        nh += o[1];
+        ncand += o[2];
+        ncarry += o[3];
+    }
+    out[0] = nt;
+    out[1] = nh;
+    out[2] = ncand;
+    out[3] = ncarry;
+    return ORC_OK;
+}

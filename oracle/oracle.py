@@ -35,6 +35,34 @@ class _CConfig(ctypes.Structure):
                 ("coarse_rho", ctypes.c_int32)]
 
 
+track_dtype = np.dtype([("timeline", "<i4"), ("track", "<i4"), ("window", "<i4"), ("n_hits", "<i4"),
+                        ("hit_offset", "<i8"), ("vane_first", "<i4"), ("vane_last", "<i4"),
+                        ("theta_bin", "<i4"), ("rho_bin", "<i4"), ("last_window", "<i4"), ("carried", "<i4")])
+assert track_dtype.itemsize == 48
+
+
+class _CTwConfig(ctypes.Structure):
+    _fields_ = [("window_ns", ctypes.c_float), ("step_ns", ctypes.c_float), ("gate_r", ctypes.c_float),
+                ("gate_z", ctypes.c_float), ("gate_t", ctypes.c_float), ("max_track_hits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+@dataclasses.dataclass
+class TwConfig:
+    """Time windows and track extension (window width and step in ns, the
+    extrapolation gates in mm and ns, the longest track)."""
+    window_ns: float = 10.0
+    step_ns: float = 5.0
+    gate_r: float = 10.0
+    gate_z: float = 4.0
+    gate_t: float = 2.0
+    max_track_hits: int = 64
+
+    def c(self) -> _CTwConfig:
+        return _CTwConfig(self.window_ns, self.step_ns, self.gate_r, self.gate_z, self.gate_t,
+                          self.max_track_hits)
+
+
 @dataclasses.dataclass
 class OracleConfig:
     n_theta: int = 1024
@@ -93,6 +121,10 @@ def _load():
         lib.orc_acc_after.restype = ctypes.c_int
         lib.orc_find_batch.argtypes = [cfgp, ctypes.c_int32, P, P, P, P, I64, P, I64, P]
         lib.orc_find_batch.restype = ctypes.c_int
+        twp = ctypes.POINTER(_CTwConfig)
+        lib.orc_tw_find_batch.argtypes = [cfgp, twp, ctypes.c_int32, P, P, P, P, P, ctypes.c_int32, P, I64, P,
+                                          I64, P]
+        lib.orc_tw_find_batch.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -259,3 +291,32 @@ def oracle_find_batch_sliced(cfg: OracleConfig, offsets, z, vane, workers: int =
         votes += vt
     return FindResult(np.concatenate(cands), np.concatenate(hits).astype(np.int32), np.zeros(0, np.int32),
                       n_iters, votes)
+
+
+@dataclasses.dataclass
+class TrackResult:
+    tracks: np.ndarray      # structured, track_dtype
+    hit_index: np.ndarray   # int32, timeline-local, vane order from each track's lower end
+    n_candidates: int       # Hough candidates over all windows
+    n_carried: int          # track-windows in which a flagged track gained hits
+
+
+def oracle_tw_find_batch(cfg: OracleConfig, tw: TwConfig, offsets, r, z, vane, t, n_windows: int) -> TrackResult:
+    """Time-sliced track finding with track extension over CSR timelines."""
+    z, vane = _hits(z, vane)
+    r = np.ascontiguousarray(r, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_tl = offsets.shape[0] - 1
+    n = int(offsets[-1]) if offsets.shape[0] else 0
+    kcap = n // 3 + n_tl + 1
+    tracks = np.zeros(kcap, track_dtype)
+    hits = np.zeros(max(n, 1), np.int32)
+    out = np.zeros(4, np.int64)
+    c, w = cfg.c(), tw.c()
+    st = _load().orc_tw_find_batch(ctypes.byref(c), ctypes.byref(w), n_tl, _ptr(offsets), _ptr(r), _ptr(z),
+                                   _ptr(vane), _ptr(t), int(n_windows), _ptr(tracks), kcap, _ptr(hits),
+                                   max(n, 1), _ptr(out))
+    if st:
+        raise OracleError(st)
+    return TrackResult(tracks[:out[0]].copy(), hits[:out[1]].copy(), int(out[2]), int(out[3]))

@@ -28,6 +28,15 @@ Event recipe (one numpy PCG64 stream per event, ``default_rng(seed)``):
   uniform r and z, snapped the same way;
 * hits are ordered track by track in arc order, then noise, then shuffled by
   one seeded permutation.
+
+Timeline recipe (time-sliced track finding; ``make_timeline``): muon decays
+at times drawn as a Poisson process of a given rate (decays/ns, as the
+paper's Table 1 quotes its rates) over a span; each decay emits one positron
+drawn as above, whose hit at turning angle a is recorded at time
+t_decay + R a sqrt(1 + tan^2 lambda) / c (the positron moves at c, no
+timing smearing), stored float32 in ns; noise hits (1 % of the signal) are
+uniform in time over the span and in space as above; all hits are sorted by
+time (stable: decay order, then arc order, noise last among equal times).
 """
 from __future__ import annotations
 
@@ -48,6 +57,7 @@ R_MIN_MM, R_MAX_MM = 90.0, 290.0
 Z_MAX_MM = 200.0
 PITCH_MM = 0.19
 MAX_TURNING = 3.0 * math.pi        # 1.5 turns
+C_MM_PER_NS = 299.792458
 
 _N_R_STRIPS = int(math.ceil((R_MAX_MM - R_MIN_MM) / PITCH_MM))
 _N_Z_STRIPS = int(math.ceil((2.0 * Z_MAX_MM) / PITCH_MM))
@@ -271,3 +281,106 @@ def hit_histogram(batch: Batch) -> dict:
     return {"n_events": int(n.size), "hits_total": int(n.sum()), "hits_min": int(n.min()),
             "hits_mean": float(n.mean()), "hits_max": int(n.max()),
             "hits_p50": float(np.percentile(n, 50)), "hits_p99": float(np.percentile(n, 99))}
+
+
+# ---------------------------------------------------------------------------
+# Timelines: decays spread over time, for the time-sliced finder
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Timeline:
+    """Time-ordered hits of muon decays spread over a time span."""
+
+    r: np.ndarray          # float32 [n]
+    z: np.ndarray          # float32 [n]
+    vane: np.ndarray       # int16   [n]
+    t: np.ndarray          # float32 [n]  hit time, ns, non-decreasing
+    track: np.ndarray      # int32   [n]  generating decay, -1 for noise
+    seed: int
+    rate_per_ns: float
+    span_ns: float
+    t_decay: np.ndarray    # float64 [n_decays]
+    p: np.ndarray          # |p| MeV/c per decay
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.z.shape[0])
+
+
+@dataclasses.dataclass
+class TimelineBatch:
+    r: np.ndarray
+    z: np.ndarray
+    vane: np.ndarray
+    t: np.ndarray
+    offsets: np.ndarray
+    timelines: List[Timeline]
+
+    @property
+    def n_timelines(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.offsets[-1])
+
+    def n_windows(self, window_ns: float = 10.0, step_ns: float = 5.0) -> int:
+        """Windows [k step, k step + window) that can hold a hit: up to the
+        last hit time of any timeline."""
+        if self.n_hits == 0:
+            return 0
+        return int(math.floor(float(self.t.max()) / step_ns)) + 1
+
+
+def make_timeline(seed: int, rate_per_ns: float, span_ns: float, noise_frac: float = 0.01) -> Timeline:
+    """Decays at Poisson times of the given rate over [0, span_ns)."""
+    rng = np.random.default_rng(seed)
+    nd = int(rng.poisson(rate_per_ns * span_ns))
+    t_dec = np.sort(rng.uniform(0.0, span_ns, nd))
+    phi0 = rng.uniform(0.0, 2.0 * math.pi, nd)
+    z0 = rng.normal(0.0, Z0_SIGMA_MM, nd)
+    p = rng.uniform(P_MIN, P_MAX, nd)
+    beta = rng.uniform(0.0, 2.0 * math.pi, nd)
+    tanl = rng.uniform(-TAN_MAX, TAN_MAX, nd)
+    pt = p / np.sqrt(1.0 + tanl * tanl)
+    if nd > 0:
+        ti, a, r, z, v = _track_crossings(phi0, z0, pt, tanl, beta)
+        radius = pt / (GEV_PER_T_M * B_TESLA)
+        t = t_dec[ti] + radius[ti] * a * np.sqrt(1.0 + tanl[ti] ** 2) / C_MM_PER_NS
+        order = np.lexsort((a, ti))
+        ti, r, z, v, t = ti[order], r[order], z[order], v[order], t[order]
+    else:
+        ti = np.zeros(0, np.int64)
+        r = z = t = np.zeros(0)
+        v = np.zeros(0, np.int64)
+    n_sig = ti.shape[0]
+    n_noise = int(math.floor(noise_frac * n_sig + 0.5))
+    nv = rng.integers(0, N_VANES, n_noise)
+    nr = rng.uniform(R_MIN_MM, R_MAX_MM, n_noise)
+    nz = rng.uniform(-Z_MAX_MM, Z_MAX_MM, n_noise)
+    nt_ = rng.uniform(0.0, span_ns, n_noise)
+    r_all = np.concatenate([r, nr])
+    z_all = np.concatenate([z, nz])
+    v_all = np.concatenate([v, nv])
+    tr_all = np.concatenate([ti, np.full(n_noise, -1)])
+    t_all = np.concatenate([t, nt_]).astype(np.float32)
+    order = np.argsort(t_all, kind="stable")
+    return Timeline(r=_snap(r_all[order], R_MIN_MM, _N_R_STRIPS).astype(np.float32),
+                    z=_snap(z_all[order], -Z_MAX_MM, _N_Z_STRIPS).astype(np.float32),
+                    vane=v_all[order].astype(np.int16), t=t_all[order], track=tr_all[order].astype(np.int32),
+                    seed=int(seed), rate_per_ns=float(rate_per_ns), span_ns=float(span_ns), t_decay=t_dec, p=p)
+
+
+def make_timeline_batch(timelines: Sequence[Timeline]) -> TimelineBatch:
+    counts = np.array([tl.n_hits for tl in timelines], dtype=np.int64)
+    offsets = np.zeros(len(timelines) + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    cat = (lambda k, dt: np.concatenate([getattr(tl, k) for tl in timelines]).astype(dt)
+           if timelines else np.zeros(0, dt))
+    return TimelineBatch(r=cat("r", np.float32), z=cat("z", np.float32), vane=cat("vane", np.int16),
+                         t=cat("t", np.float32), offsets=offsets, timelines=list(timelines))
+
+
+def timeline_batch(n_timelines: int, rate_per_ns: float, span_ns: float, seed0: int = 3_000_000) -> TimelineBatch:
+    """``n_timelines`` timelines with seeds seed0 .. seed0 + n - 1."""
+    return make_timeline_batch([make_timeline(seed0 + i, rate_per_ns, span_ns) for i in range(n_timelines)])
