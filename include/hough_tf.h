@@ -453,6 +453,89 @@ hough_status hough_server_drain(hough_server *server, double timeout_s);
 hough_status hough_server_get_stats(const hough_server *server, hough_server_stats *stats);
 
 /*
+ * Time-sliced track finding with track extension (paper Sec. 4: a seed of
+ * three hits on consecutive vanes is extrapolated to neighbouring vanes to
+ * pick up further hits, inside a 10 ns time window; the window then moves
+ * on by 5 ns, and candidates flagged in one window are continued first in
+ * the next; Sec. 5: per window, the Hough transform of its hits gives the
+ * seeds). Input: n_timelines independent timelines, CSR offsets (device
+ * int64[n_timelines + 1]) over device hit arrays r, z (mm, float), vane
+ * (int16) and t (ns, float), each timeline sorted by time (t >= 0, finite).
+ * Window w holds the hits with lo_w <= t < lo_w + window_ns, lo_w =
+ * float(w) * step_ns; windows 0 .. n_windows - 1 are processed in order.
+ * Per window and timeline:
+ *   1. continuation: every track flagged in the previous window (ascending
+ *      track id) is extended at its upper-vane end, then at its lower-vane
+ *      end, through the window's unused hits (below);
+ *   2. seeds: the context's Hough finder (its configuration: bins, T, peak
+ *      mode) runs on the window's unused hits in hit order; each candidate,
+ *      in emission order, takes on each vane its unused hit of lowest index;
+ *      the first vane v (0, 1, ...) such that v, v+1, v+2 (modulo n_vanes)
+ *      have one, with neighbouring times at most gate_t_ns apart, gives the
+ *      three seed hits of a new track, which is then extended at both ends;
+ *   3. extension of an end: from its end hit e3 and the two before it (e2,
+ *      e1) the next vane's hit is predicted as x_hat = (x1 - 3 x2) + 3 x3 for
+ *      r and z (float, in this order); among the window's unused hits on that
+ *      vane with |r - r_hat| <= gate_r_mm, |z - z_hat| <= gate_z_mm and
+ *      |t - t(e3)| <= gate_t_ns, the one of least |r - r_hat| + |z - z_hat|
+ *      (ties: lower index) joins; the end stops at the first vane without
+ *      one or at max_track_hits hits;
+ *   4. flag: a track that gained hits in window w (created or continued) and
+ *      whose latest hit time is at least lo_(w+1) is continued in w + 1.
+ * Outputs (device, caller-owned): tracks (hough_track[track_capacity],
+ * track_capacity >= n_hits_total / 3) in (timeline, creation) order,
+ * hit_index (int32[hit_capacity], hit_capacity >= n_hits_total): each
+ * track's hits as timeline-local indices in vane order from its lower end;
+ * counts (int64[HOUGH_COUNTS], HOUGH_TW_COUNT_*). Invalid hits (vane out of
+ * range, non-finite r/t, |z| > HOUGH_Z_LIMIT, t < 0, t decreasing) and bad
+ * offsets are found on the device: counts[2] = HOUGH_ERR_DATA or
+ * HOUGH_ERR_INVALID_ARG, counts[3] = the first bad global hit, no tracks.
+ * A window event of more than HOUGH_MAX_EVENT_HITS unused hits ends the call
+ * with HOUGH_ERR_CAPACITY in counts[2]. Host-checked errors:
+ * HOUGH_ERR_INVALID_ARG (bad pointers, sizes or tw configuration, n_vanes
+ * outside 3..1024), HOUGH_ERR_CAPACITY (outputs too small), HOUGH_ERR_OOM.
+ * The context's workspace grows on demand (hipMalloc) as for hough_find.
+ */
+typedef struct {
+    float window_ns;        /* window width (10)                                   */
+    float step_ns;          /* window step (5), 0 < step_ns <= window_ns            */
+    float gate_r_mm;        /* extrapolation gate in r (10)                         */
+    float gate_z_mm;        /* extrapolation gate in z (4)                          */
+    float gate_t_ns;        /* time gate between neighbouring hits of a track (2)   */
+    int32_t max_track_hits; /* longest track, 3..1024 (64)                          */
+    int32_t reserved[2];    /* must be 0                                            */
+} hough_tw_config;
+
+typedef struct {            /* 48 bytes, one per track                              */
+    int32_t timeline;       /* timeline index within the call                       */
+    int32_t track;          /* creation index within the timeline                   */
+    int32_t window;         /* window that created it                               */
+    int32_t n_hits;
+    int64_t hit_offset;     /* first entry of its hits in hit_index                 */
+    int32_t vane_first;     /* vane of its lower-vane end hit                       */
+    int32_t vane_last;      /* vane of its upper-vane end hit                       */
+    int32_t theta_bin;      /* the Hough peak that seeded it                        */
+    int32_t rho_bin;
+    int32_t last_window;    /* last window in which it gained hits                  */
+    int32_t carried;        /* windows after its creation in which it gained hits   */
+} hough_track;
+
+#define HOUGH_TW_COUNT_TRACKS 0
+#define HOUGH_TW_COUNT_HITS 1
+#define HOUGH_TW_COUNT_STATUS 2
+#define HOUGH_TW_COUNT_DETAIL 3
+#define HOUGH_TW_COUNT_WINDOWS 4      /* windows processed                            */
+#define HOUGH_TW_COUNT_CANDIDATES 5   /* Hough candidates over all windows            */
+#define HOUGH_TW_COUNT_CONTINUED 6    /* (track, window) continuations that gained hits */
+
+/* Fills *tw with the defaults above. */
+hough_status hough_tw_config_default(hough_tw_config *tw);
+hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *tw, int32_t n_timelines,
+                           int64_t n_hits_total, const int64_t *offsets, const float *r, const float *z,
+                           const int16_t *vane, const float *t, int32_t n_windows, hough_track *tracks,
+                           int64_t track_capacity, int32_t *hit_index, int64_t hit_capacity, int64_t *counts);
+
+/*
  * Helix refit of track candidates (a continuous fit of each candidate's hits;
  * the paper fits its seeds with a Kalman filter, Sec. 3, and names a GPU fit
  * as future work). Stateless calls on the caller's stream; every pointer is

@@ -12,7 +12,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhough_tf.so")
 SOURCES = [os.path.join(CSRC, "hough_kernels.hip"), os.path.join(CSRC, "hough_host.hip"),
            os.path.join(CSRC, "hough_serve.hip"), os.path.join(CSRC, "hough_refit.hip"),
-           os.path.join(CSRC, "hough_cf.hip"), os.path.join(CSRC, "hough_probe.hip")]
+           os.path.join(CSRC, "hough_cf.hip"), os.path.join(CSRC, "hough_probe.hip"),
+           os.path.join(CSRC, "hough_tw.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

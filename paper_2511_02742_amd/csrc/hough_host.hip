@@ -462,10 +462,11 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
 hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
                           const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
                           hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed,
-                          bool longest_first) {
+                          bool longest_first, bool total_is_bound) {
     hough::FindArgs a = find_args(c, w);
     a.n_events = n_events;
     a.n_total = n_total;
+    a.total_is_bound = total_is_bound ? 1 : 0;
     a.offsets = offsets;
     a.z = z;
     a.vane = vane;
@@ -611,6 +612,7 @@ void free_context(Ctx *c) {
         (void)hipEventDestroy(pr.second);
     }
     free_workspace(c->ws);
+    if (c->tw_base) (void)hipFree(c->tw_base);
     if (c->d_tables) (void)hipFree(c->d_tables);
     c->magic = 0;
     delete c;

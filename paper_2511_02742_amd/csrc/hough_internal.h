@@ -46,6 +46,7 @@ struct FindArgs {
     // inputs (device)
     int32_t n_events;
     int64_t n_total;
+    int32_t total_is_bound;  // 1: offsets[n_events] may be below n_total (offsets built on the device)
     const int64_t *offsets;
     const float *z;
     const int16_t *vane;

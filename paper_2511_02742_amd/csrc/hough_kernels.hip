@@ -1490,7 +1490,7 @@ __global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restric
         int bad = 0;
         if (b < 0 || n64 < 0 || b + n64 > A.n_total) bad = HOUGH_ERR_INVALID_ARG;
         if (e == 0 && b != 0) bad = HOUGH_ERR_INVALID_ARG;
-        if (e == A.n_events - 1 && b + n64 != A.n_total) bad = HOUGH_ERR_INVALID_ARG;
+        if (e == A.n_events - 1 && b + n64 != A.n_total && !A.total_is_bound) bad = HOUGH_ERR_INVALID_ARG;
         if (!bad && n64 > HOUGH_MAX_EVENT_HITS) {
             bad = HOUGH_ERR_CAPACITY;
             atomicMin(&A.err[1], (long long)b);

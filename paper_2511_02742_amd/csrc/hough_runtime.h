@@ -73,6 +73,9 @@ struct Ctx {
     // 2 * ev_clock_events words, written by calls of at most that many events
     unsigned long long *ev_clock = nullptr;
     int64_t ev_clock_events = 0;
+    // time-sliced finder state (grown on demand by hough_tw_find)
+    void *tw_base = nullptr;
+    size_t tw_bytes = 0;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pairs;
@@ -108,11 +111,13 @@ size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, ch
 void free_workspace(Workspace &w);
 // Enqueues one finder call on s (split sweep, finder, compaction); outputs
 // as in hough_find. With longest_first, a call of many events runs its
-// longest events first (an ordering kernel ahead of the finder).
+// longest events first (an ordering kernel ahead of the finder). With
+// total_is_bound, n_total only bounds offsets[n_events] (offsets written on
+// the device, as the time-sliced finder's window events are).
 hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
                           const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
                           hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed,
-                          bool longest_first);
+                          bool longest_first, bool total_is_bound = false);
 
 }  // namespace rt
 }  // namespace hough

@@ -30,6 +30,7 @@ COUNT_NAMES = ("candidates", "hits", "status", "detail", "evals", "iters", "max_
                "tiled", "truncations", "hot_scans", "hotset_full", "recounts", "large", "votes", "ordered")
 
 EXPORTS = ("hough_config_default", "hough_create", "hough_destroy", "hough_output_bounds", "hough_find", "hough_find_noalloc",
+           "hough_tw_config_default", "hough_tw_find",
            "hough_debug_accumulator", "hough_tables", "hough_launch_shape", "hough_set_timing",
            "hough_timing", "hough_set_event_clock", "hough_clock_rate", "hough_graph_create", "hough_graph_launch", "hough_graph_destroy",
            "hough_autotune", "hough_server_create", "hough_server_destroy", "hough_server_clock",
@@ -53,6 +54,32 @@ class HoughConfig(ctypes.Structure):
                 ("wg_threads", ctypes.c_int32), ("sweep_groups", ctypes.c_int32),
                 ("sweep_threads", ctypes.c_int32), ("coarse_theta", ctypes.c_int32),
                 ("coarse_rho", ctypes.c_int32)]
+
+
+class TwConfig(ctypes.Structure):
+    """hough_tw_config: time windows and track extension."""
+    _fields_ = [("window_ns", ctypes.c_float), ("step_ns", ctypes.c_float), ("gate_r_mm", ctypes.c_float),
+                ("gate_z_mm", ctypes.c_float), ("gate_t_ns", ctypes.c_float), ("max_track_hits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+track_dtype = np.dtype([("timeline", "<i4"), ("track", "<i4"), ("window", "<i4"), ("n_hits", "<i4"),
+                        ("hit_offset", "<i8"), ("vane_first", "<i4"), ("vane_last", "<i4"),
+                        ("theta_bin", "<i4"), ("rho_bin", "<i4"), ("last_window", "<i4"), ("carried", "<i4")])
+assert track_dtype.itemsize == 48
+TW_COUNT_NAMES = ("tracks", "hits", "status", "detail", "windows", "candidates", "continued")
+
+
+def tw_config(**overrides) -> TwConfig:
+    """The library's default time-window configuration with overrides."""
+    lib = load_library()
+    tw = TwConfig()
+    st = lib.hough_tw_config_default(ctypes.byref(tw))
+    if st != HOUGH_OK:
+        raise HoughError(st, "hough_tw_config_default")
+    for k, v in overrides.items():
+        setattr(tw, k, v)
+    return tw
 
 
 class ServerConfig(ctypes.Structure):
@@ -108,6 +135,10 @@ def load_library(path: str = LIB_PATH):
     lib.hough_find.restype = st
     lib.hough_find_noalloc.argtypes = [P, P, I32, I64, P, P, P, P, I64, P, I64, P]
     lib.hough_find_noalloc.restype = st
+    lib.hough_tw_config_default.argtypes = [P]
+    lib.hough_tw_config_default.restype = st
+    lib.hough_tw_find.argtypes = [P, P, P, I32, I64, P, P, P, P, P, I32, P, I64, P, I64, P]
+    lib.hough_tw_find.restype = st
     lib.hough_debug_accumulator.argtypes = [P, P, I64, P, P, I32, P, P]
     lib.hough_debug_accumulator.restype = st
     lib.hough_tables.argtypes = [P, P, P, P, P, P, P]
@@ -327,6 +358,52 @@ class HoughFinder:
         l = ctypes.c_int32()  # noqa: E741
         self.lib.hough_launch_shape(self._h, ctypes.byref(t), ctypes.byref(w), ctypes.byref(l))
         return {"tile_rows": t.value, "wg_threads": w.value, "lds_bytes": l.value}
+
+    def tw_find(self, r, z, vane, t, offsets, n_windows: int, tw: Optional[TwConfig] = None, stream=None,
+                outputs=None):
+        """Time-sliced track finding (hough_tw_find) on device tensors r, z
+        (float32), vane (int16), t (float32, sorted per timeline) and CSR
+        offsets (int64). Returns (tracks uint8 [cap, 48], hit_index int32,
+        counts int64) device tensors; `outputs` reuses such a triple."""
+        torch = self._torch
+        assert r.dtype == torch.float32 and z.dtype == torch.float32 and t.dtype == torch.float32
+        assert vane.dtype == torch.int16 and offsets.dtype == torch.int64
+        for x in (r, z, vane, t, offsets):
+            assert x.is_contiguous()
+        n = z.numel()
+        if tw is None:
+            tw = tw_config()
+        dev = torch.device("cuda", self.device)
+        if outputs is None:
+            outputs = (torch.empty((max(n // 3, 1), 48), dtype=torch.uint8, device=dev),
+                       torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                       torch.empty(HOUGH_COUNTS, dtype=torch.int64, device=dev))
+        tr, hi, cnt = outputs
+        st = self.lib.hough_tw_find(self._h, self._stream(stream), ctypes.byref(tw), offsets.numel() - 1, n,
+                                    ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                    ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(vane.data_ptr()),
+                                    ctypes.c_void_p(t.data_ptr()), int(n_windows), ctypes.c_void_p(tr.data_ptr()),
+                                    tr.shape[0], ctypes.c_void_p(hi.data_ptr()), hi.numel(),
+                                    ctypes.c_void_p(cnt.data_ptr()))
+        if st != HOUGH_OK:
+            raise self._err(st)
+        return outputs
+
+    def tw_find_host(self, batch, n_windows: Optional[int] = None, tw: Optional[TwConfig] = None):
+        """Runs tw_find on a host TimelineBatch; returns (tracks as a
+        structured array, hit indices, counts dict)."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        if n_windows is None:
+            n_windows = batch.n_windows(tw.window_ns if tw else 10.0, tw.step_ns if tw else 5.0)
+        args = [torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+                for a in (batch.r, batch.z, batch.vane, batch.t, batch.offsets)]
+        tr, hi, cnt = self.tw_find(*args, n_windows=n_windows, tw=tw)
+        torch.cuda.synchronize(dev)
+        info = dict(zip(TW_COUNT_NAMES, (int(x) for x in cnt.cpu().numpy())))
+        nt, nh = info["tracks"], info["hits"]
+        tracks = tr[:nt].cpu().numpy().reshape(-1).view(track_dtype).copy() if nt else np.zeros(0, track_dtype)
+        return tracks, hi[:nh].cpu().numpy().copy(), info
 
     def capture(self, z, vane, offsets, out: Optional[FindOutput] = None) -> "FindGraph":
         """Captures the batched launch for these device tensors (see hough_graph_create)."""

@@ -207,3 +207,31 @@ def test_lds_peak_rejects_bad_arguments_without_a_device():
     out = C.c_double()
     assert lib.hough_lds_peak(0, None, 2, C.byref(out)) == hough.HOUGH_ERR_INVALID_ARG
     assert lib.hough_lds_peak(0, None, 0, None) == hough.HOUGH_ERR_INVALID_ARG
+
+
+def test_tw_struct_layouts_and_defaults(tmp_path):
+    import subprocess
+    from paper_2511_02742_amd import hough
+    src = tmp_path / "tw.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"hough_tf.h\"\n"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(hough_tw_config),"
+        " offsetof(hough_tw_config, max_track_hits), sizeof(hough_track), offsetof(hough_track, hit_offset),"
+        " offsetof(hough_track, carried)); return 0;}\n")
+    exe = tmp_path / "tw"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(hough.TwConfig), hough.TwConfig.max_track_hits.offset, hough.track_dtype.itemsize,
+                   hough.track_dtype.fields["hit_offset"][1], hough.track_dtype.fields["carried"][1]]
+    tw = hough.tw_config()
+    assert (tw.window_ns, tw.step_ns, tw.gate_r_mm, tw.gate_z_mm, tw.gate_t_ns, tw.max_track_hits) == \
+        (10.0, 5.0, 10.0, 4.0, 2.0, 64)
+
+
+def test_tw_find_rejects_bad_arguments_without_a_device():
+    from paper_2511_02742_amd import hough
+    lib = hough.load_library()
+    tw = hough.tw_config()
+    # a bad context is refused before anything else
+    assert lib.hough_tw_find(None, None, ctypes.byref(tw), 1, 0, ctypes.c_void_p(8), None, None, None, None, 1,
+                             None, 0, None, 0, ctypes.c_void_p(8)) == hough.HOUGH_ERR_INVALID_ARG
