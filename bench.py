@@ -255,6 +255,9 @@ def main():
                     help="pure candidates also fitted by the float64 oracle for the parameter error")
     ap.add_argument("--no-coarse-fine", action="store_true",
                     help="skip the coarse-to-fine leg (the paper's 18 x 100 -> 10 x 10 histograms)")
+    ap.add_argument("--tw-timelines", type=int, default=64,
+                    help="timelines of 10^4 decays per rate in the time-sliced leg (0: skip it)")
+    ap.add_argument("--tw-rates", default="6.0,0.6,0.06", help="decay rates (per ns) of the time-sliced leg")
     ap.add_argument("--only-batched", action="store_true",
                     help="the batched headline leg alone (for profiler runs): no oracle, plain, graph, cfg3, "
                          "served, refit or coarse-to-fine legs")
@@ -271,6 +274,7 @@ def main():
         sys.exit(2)
     if args.only_batched:
         args.no_cpu_baseline = True
+        args.tw_timelines = 0
         args.serve_events = 0
         args.refit_events = 0
         args.no_coarse_fine = True
@@ -304,6 +308,7 @@ def main():
             for name, mode in (("coarse_fine", 2), ("argmax", 0), ("nms", 1)):
                 jobs.append(("cf_" + name, OracleConfig(n_theta=180, n_rho=1000, peak_mode=mode), batch))
         refs = oracle_references(jobs, log)
+    tw_in = tw_inputs(args, log) if args.tw_timelines > 0 else None
 
     import torch
 
@@ -461,6 +466,7 @@ def main():
                 "kernel_evals_per_launch": info["evals"],
                 "lds_frac": lds["frac"], "lds_frac_vote_pattern": lds["frac_vote_pattern"]}
 
+    tw = tw_bench(args, tw_in, log) if tw_in else None
     served = serve_bench(args, f, log) if args.serve_events > 0 else None
     refit = refit_bench(args, f, log) if args.refit_events > 0 else None
     coarse_fine = None if args.no_coarse_fine else coarse_fine_bench(args, batch, z, vane, offs, log, peak_vote,
@@ -493,11 +499,109 @@ def main():
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "poisson20": poisson,
+        "time_windows": tw,
         "served": served,
         "refit": refit,
         "coarse_fine": coarse_fine,
     }
     print(json.dumps(rec), flush=True)
+
+
+TW_DECAYS = 10000        # decays per timeline (the size of the paper's Table 1 runs)
+TW_CHECKED = 2           # timelines per rate also run by the oracle
+
+
+def _tw_oracle_job(job):
+    from oracle import OracleConfig, TwConfig, oracle_tw_find_batch
+    rate, offsets, r, z, vane, t, n_windows = job
+    t0 = time.perf_counter()
+    res = oracle_tw_find_batch(OracleConfig(), TwConfig(), offsets, r, z, vane, t, n_windows)
+    return rate, res, time.perf_counter() - t0
+
+
+def tw_inputs(args, log):
+    """Timelines of the time-sliced leg, and the oracle on the first ones of
+    each rate (independent processes, one per job; before the GPU is used)."""
+    import multiprocessing as mp
+    from paper_2511_02742_amd import eventgen
+    rates = [float(x) for x in args.tw_rates.split(",") if x]
+    t0 = time.perf_counter()
+    batches = {rate: eventgen.timeline_batch(args.tw_timelines, rate, TW_DECAYS / rate,
+                                            seed0=4_000_000 + 1000 * int(round(rate * 100)))
+               for rate in rates}
+    log("time-sliced leg: generated %d timelines x %d rates in %.1f s" % (args.tw_timelines, len(rates),
+                                                                        time.perf_counter() - t0))
+    refs = {}
+    if not args.no_cpu_baseline:
+        jobs = []
+        for rate, b in batches.items():
+            k = min(TW_CHECKED, b.n_timelines)
+            hi = int(b.offsets[k])
+            jobs.append((rate, b.offsets[:k + 1].copy(), b.r[:hi].copy(), b.z[:hi].copy(), b.vane[:hi].copy(),
+                         b.t[:hi].copy(), b.n_windows()))
+        with mp.get_context("spawn").Pool(len(jobs)) as pool:
+            for rate, res, sec in pool.map(_tw_oracle_job, jobs):
+                refs[rate] = (res, sec)
+                log("time-sliced oracle, %g decays/ns: %d tracks in %.1f s" % (rate, len(res.tracks), sec))
+    return batches, refs
+
+
+def tw_bench(args, tw_in, log):
+    """Time-sliced track finding (10 ns windows sliding by 5 ns, Hough seeds
+    per window, three-hit seeds extended across vanes, flagged tracks
+    continued) on timelines of 10^4 decays at the paper's decay rates:
+    decays/s and windows/s of one call over all timelines, the first
+    timelines byte-checked against the oracle, and the oracle's own rate on
+    one core."""
+    import numpy as np
+    import torch
+    from paper_2511_02742_amd.hough import TW_COUNT_NAMES, HoughFinder, track_dtype, tw_config
+    batches, refs = tw_in
+    dev = torch.device("cuda", 0)
+    f = HoughFinder(0)
+    tw = tw_config()
+    out = {"workload": "%d timelines per rate, %d muon decays each (Poisson times over 10^4 / rate ns), "
+                       "50-track-equivalent geometry, 1%% noise; 10 ns windows, 5 ns step; 1024x1024 Hough "
+                       "seeds, T=6, nms w=1" % (args.tw_timelines, TW_DECAYS), "rates": []}
+    for rate, b in batches.items():
+        nw = b.n_windows()
+        ts = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (b.r, b.z, b.vane, b.t, b.offsets)]
+        outs = None
+        reps = 1 if nw > 10000 else 3
+        times = []
+        for i in range(reps + 1):
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()
+            outs = f.tw_find(*ts, n_windows=nw, tw=tw, outputs=outs)
+            torch.cuda.synchronize(dev)
+            if i > 0:
+                times.append(time.perf_counter() - t0)
+        sec = float(np.median(times))
+        info = dict(zip(TW_COUNT_NAMES, (int(x) for x in outs[2].cpu().numpy())))
+        assert info["status"] == 0, info
+        n_dec = sum(len(tl.t_decay) for tl in b.timelines)
+        ent = {"decays_per_ns": rate, "timelines": b.n_timelines, "decays": n_dec, "hits": b.n_hits,
+               "windows_per_timeline": nw, "seconds_per_call": round(sec, 4),
+               "decays_per_s": round(n_dec / sec, 1), "windows_per_s": round(b.n_timelines * nw / sec, 1),
+               "tracks": info["tracks"], "track_hits": info["hits"], "hough_candidates": info["candidates"],
+               "continuations": info["continued"]}
+        if rate in refs:
+            res, osec = refs[rate]
+            nt, nh = len(res.tracks), len(res.hit_index)
+            g_tr = outs[0][:nt].cpu().numpy().reshape(-1).view(track_dtype)
+            g_hi = outs[1][:nh].cpu().numpy()
+            k = min(TW_CHECKED, b.n_timelines)
+            ok = (np.array_equal(g_tr.view(np.uint8), res.tracks.view(np.uint8)) and np.array_equal(g_hi, res.hit_index)
+                  and (nt == info["tracks"] or int(outs[0][nt:nt + 1].cpu().numpy().reshape(-1).view(track_dtype)
+                                                   ["timeline"][0]) >= k))
+            ent["parity"] = {"timelines": k, "tracks": nt, "hits": nh, "byte_equal": bool(ok)}
+            dk = sum(len(tl.t_decay) for tl in b.timelines[:k])
+            ent["cpu_baseline"] = {"value": round(dk / osec, 1), "unit": "decays/s", "cores": 1, "kind": "oracle",
+                                   "sample": "the first %d timelines (%d decays), one thread, %.1f s" % (k, dk, osec)}
+        log("time-sliced leg, %g decays/ns: %s" % (rate, ent))
+        out["rates"].append(ent)
+        del ts, outs
+    return out
 
 
 def serve_bench(args, finder, log):
