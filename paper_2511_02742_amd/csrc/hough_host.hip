@@ -935,17 +935,31 @@ hough_status hough_autotune(const hough_config *base, int device, void *stream, 
     if (hipSetDevice(device) != hipSuccess) return fail(nullptr, HOUGH_ERR_DEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     // candidate launch shapes: the finder's workgroup size, and the split
-    // first sweep's workgroups per event and threads
+    // first sweep's workgroups per event and threads, on the automatic tile
+    // (as many rows as the LDS holds: one workgroup per CU); then the
+    // finder's workgroup size on smaller tiles (own theta rows per tile),
+    // which leave LDS for two or more events' workgroups per CU
     std::vector<hough_config> cands;
-    const int wgs[] = {1024, 512};
+    const int wgs[] = {1024, 512, 256};
     const int sweeps[][2] = {{0, 0}, {1, 256}, {1, 512}, {2, 256}, {2, 512}, {4, 256}, {8, 256}};
     for (int wg : wgs)
         for (auto &sw : sweeps) {
+            if (wg == 256 && sw[0] != 0) continue;
             hough_config cfg = *base;
             cfg.tile_rows = 0;
             cfg.wg_threads = wg;
             cfg.sweep_groups = sw[0];
             cfg.sweep_threads = sw[1];
+            cands.push_back(cfg);
+        }
+    const int tiles[] = {14, 6};
+    for (int wg : wgs)
+        for (int tr : tiles) {
+            hough_config cfg = *base;
+            cfg.tile_rows = tr;
+            cfg.wg_threads = wg;
+            cfg.sweep_groups = 0;
+            cfg.sweep_threads = 0;
             cands.push_back(cfg);
         }
     const int64_t ccap = std::max<int64_t>(n_hits_total / (int64_t)base->min_votes, 1);

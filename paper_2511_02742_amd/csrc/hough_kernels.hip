@@ -1463,8 +1463,12 @@ __device__ void put_ev_stats(const FindArgs &A, int e, unsigned long long evals,
     p[kEvVotes * ne] = votes;
 }
 
+// At most 128 VGPRs at every width (four waves per SIMD): a 512-thread
+// finder whose tile leaves half the LDS free then shares a CU with another
+// event's workgroup, and a 256-thread one with up to three.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_find(FindArgs A, const float2 *__restrict__ cs) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_find(FindArgs A,
+                                                                                   const float2 *__restrict__ cs) {
     constexpr int NW = NT / kWave;
     unsigned char *const lds = reinterpret_cast<unsigned char *>(g_lds);
     __shared__ Shared sh;

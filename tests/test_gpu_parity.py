@@ -290,7 +290,8 @@ def test_large_events(gpu_available, pileup, n_events):
 
 
 @pytest.mark.parametrize("kw", [{"sweep_groups": 4}, {"wg_threads": 512}, {"peak_mode": 0, "max_iters": 12},
-                                {"nms_radius": 2}, {"assoc_window": 1}])
+                                {"nms_radius": 2}, {"assoc_window": 1}, {"wg_threads": 512, "tile_rows": 14},
+                                {"wg_threads": 256, "tile_rows": 6}])
 def test_large_event_variants(gpu_available, kw):
     b = eventgen.pileup_batch(3, n_tracks=150, seed0=7300)
     got, want = check_batch(b, "pileup 150 " + str(kw), **kw)
@@ -322,10 +323,11 @@ def full_size_reference(ocfg, b):
     return _full_ref[key]
 
 
-@pytest.mark.parametrize("kw", [{}, {"sweep_groups": 2}])
+@pytest.mark.parametrize("kw", [{}, {"sweep_groups": 2}, {"wg_threads": 512, "tile_rows": 14}])
 def test_full_size_batch(gpu_available, kw):
     # 4096 pileup-50 events in one launch (the benchmark configuration, run
     # longest event first): every event byte-equal to the oracle
+    # ({wg_threads 512, tile_rows 14}: two events' workgroups per CU)
     b = eventgen.pileup_batch(4096)
     f = finder(**kw)
     got = run_batch(f, b)
@@ -496,7 +498,7 @@ def test_autotune_picks_a_shape_that_matches(gpu_available):
     v = torch.from_numpy(b.vane).to(dev)
     o = torch.from_numpy(b.offsets).to(dev)
     best, ms, tried = autotune(z, v, o, repeats=1)
-    assert tried >= 8 and ms > 0
+    assert tried >= 20 and ms > 0
     f = HoughFinder(0, config=best)
     got = f.find_host(b.z, b.vane, b.offsets)
     assert_same(got, oracle_find_batch(_ocfg(f.config), b.offsets, b.z, b.vane), "autotuned")
