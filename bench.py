@@ -714,10 +714,13 @@ def serve_bench(args, finder, log):
                    "max_lanes_busy": st1["max_lanes_busy"], "mismatches": mism}
             log("served %s: %s" % ("burst" if rate == float("inf") else "%.0f/s" % rate, ent))
             res.append(ent)
-        dev_bytes = srv.stats()["device_bytes"]
+        sst = srv.stats()
     return {"workload": "mixed pileup {1,10,25,50,100} tracks + 1%% noise, pool of %d seeded events "
                         "(seeds 2000000..), Poisson arrivals" % P,
-            "lanes": args.serve_lanes, "device_bytes": dev_bytes, "mean_hits": round(float(lens.mean()), 1),
+            "lanes": args.serve_lanes, "device_arena_bytes": sst["device_bytes"],
+            "max_device_bytes_in_use": sst["max_device_bytes_in_use"], "mean_hits": round(float(lens.mean()), 1),
+            "admission": "arrived requests, oldest first, while the launch's device block fits the arena's "
+                         "largest free block",
             "rates": res}
 
 

@@ -353,17 +353,20 @@ hough_status hough_lds_peak(int device, void *stream, int mode, double *lane_ato
 /*
  * Served form: a request loop with continuous batching.
  *
- * A server owns a context of its own, a dispatcher thread and `lanes`
- * launch slots. Each lane has its own stream and resident device memory
- * (input buffer and finder workspace for max_batch_hits hits and
- * max_batch_events events) plus pinned host memory the device writes the
- * results into. Requests (one event each: host arrays) wait in an admission
- * queue in arrival order. Whenever a lane is free the dispatcher admits the
- * queued requests that have arrived, oldest first, as long as they fit the
- * lane's memory, copies them to the device in one transfer and enqueues the
- * finder on the lane's stream; requests that arrive while lanes are busy are
- * admitted by the next lane that frees, so the launches of several lanes
- * overlap on the device. A finished launch is split into per-request results
+ * A server owns a context of its own, a dispatcher thread, `lanes` launch
+ * slots and one resident device arena of device_bytes. Each lane has its
+ * own stream and pinned host memory (input staging and the results the
+ * device writes, for up to max_batch_hits hits and max_batch_events events).
+ * Requests (one event each: host arrays) wait in an admission queue in
+ * arrival order. Whenever a lane is free the dispatcher admits the queued
+ * requests that have arrived, oldest first, as long as the launch's device
+ * memory (its inputs and a finder workspace laid out for exactly those
+ * events and hits) fits the arena's largest free block, takes that block,
+ * copies the requests to the device in one transfer and enqueues the finder
+ * on the lane's stream; the block returns to the arena when the launch
+ * finishes. Requests that arrive while lanes are busy are admitted by the
+ * next lane that frees, so the launches of several lanes overlap on the
+ * device and the memory in use follows the admitted work. A finished launch is split into per-request results
  * that hough_server_poll hands out. A request's result is exactly what a
  * one-event hough_find on the same hits returns (candidates with event 0 and
  * hit_offset from 0, hit indices local to the request).
@@ -374,11 +377,15 @@ hough_status hough_lds_peak(int device, void *stream, int mode, double *lane_ato
 typedef struct {
     int32_t lanes;            /* launch slots in flight at once, 1..8 (0: 3)            */
     int32_t max_batch_events; /* requests per launch, >= 1 (0: 4096)                    */
-    int64_t max_batch_hits;   /* hits per launch: each lane's device memory; also the
+    int64_t max_batch_hits;   /* hits per launch (each lane's pinned buffers); also the
                                  largest request accepted (0: 1 << 20)                  */
     int64_t queue_hits;       /* hits the admission queue holds (0: 1 << 26)            */
     int32_t queue_events;     /* requests the admission queue holds (0: 1 << 20)        */
-    int32_t reserved[3];      /* must be 0                                              */
+    int32_t reserved;         /* must be 0                                              */
+    int64_t device_bytes;     /* device arena shared by the lanes' launches (0: lanes x
+                                 the bytes of one launch of max_batch_events events and
+                                 max_batch_hits hits); a request whose launch alone
+                                 needs more is refused at submission                    */
 } hough_server_config;
 
 typedef struct {              /* 72 bytes, one per finished request                    */
@@ -408,9 +415,11 @@ typedef struct {
     int64_t pending_events;   /* waiting for admission now                             */
     int64_t max_pending_events;
     int64_t max_lanes_busy;   /* most lanes in flight at once                          */
-    int64_t device_bytes;     /* resident device memory of all lanes                   */
+    int64_t device_bytes;     /* the device arena                                      */
     int64_t results_waiting;  /* finished results not yet polled                       */
-    int64_t reserved[5];
+    int64_t device_bytes_in_use;      /* arena bytes held by launches in flight now     */
+    int64_t max_device_bytes_in_use;  /* the most held at once                          */
+    int64_t reserved[3];
 } hough_server_stats;
 
 /* Creates a server for config `cfg` on `device` (scfg may be NULL for the
@@ -428,8 +437,8 @@ double hough_server_clock(const hough_server *server);
  * before the call returns), the tag tags[r] (NULL: r) and the arrival time
  * t_arrival[r] (NULL: now). A request is not admitted before its arrival
  * time, so a stream can be queued ahead of time. Requests with an invalid
- * hit or more than max_batch_hits hits become results with an error status
- * at once. *n_accepted receives how many requests, from the first, were
+ * hit, more than max_batch_hits hits, or a launch of their own larger than
+ * the device arena become results with an error status at once. *n_accepted receives how many requests, from the first, were
  * taken; it is less than n only when the queue is full (back-pressure: submit
  * the rest later). Returns HOUGH_ERR_INVALID_ARG for bad pointers or offsets.
  */

@@ -1,15 +1,20 @@
-// Served form: an admission queue, a dispatcher thread and a few launch
-// lanes with resident device memory (continuous batching of streamed events).
+// Served form: an admission queue, a dispatcher thread, a few launch lanes
+// and one resident device arena (continuous batching of streamed events).
 //
-// Each lane is one launch in flight: its own stream, a device input buffer
-// and a finder workspace sized for max_batch_hits / max_batch_events, and
-// pinned host memory the finder's compaction writes the results into (no
-// copy back). The dispatcher loops: it harvests every lane whose completion
-// event has fired, then fills every free lane with the queued requests that
-// have arrived (oldest first, while they fit the lane), one host-to-device
-// copy and one finder enqueue per lane. Requests that arrive while the lanes
-// are busy join the next free lane, so launches of several lanes overlap on
-// the device and a lane never waits for a fixed batch size.
+// Each lane is one launch in flight: its own stream and pinned host memory
+// (input staging, and the outputs the finder's compaction writes directly,
+// with no copy back). A launch's device memory, its inputs and the finder
+// workspace laid out for exactly its events and hits, is a block of the
+// arena, taken when the launch is admitted and returned when it finishes.
+// The dispatcher loops: it harvests every lane whose completion event has
+// fired (freeing its block), then fills every free lane with the queued
+// requests that have arrived, oldest first, while their launch's block fits
+// the arena's largest free block (and the lane's pinned buffers); one
+// host-to-device copy, one clearing kernel and one finder enqueue per lane.
+// Requests that arrive while the lanes are busy join the next free lane, so
+// launches of several lanes overlap on the device, a lane never waits for a
+// fixed batch size, and the device memory in use is what the admitted
+// launches need, not a fixed share per lane.
 
 #include <hip/hip_runtime.h>
 
@@ -20,12 +25,14 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
 #include <thread>
 #include <vector>
 
+#include "hough_internal.h"
 #include "hough_runtime.h"
 #include "hough_tf.h"
 
@@ -52,13 +59,61 @@ struct Result {
     std::vector<int32_t> hits;
 };
 
+// First-fit allocator over one device block; only the dispatcher thread
+// allocates and frees.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_blocks;  // offset -> bytes, coalesced
+    size_t in_use = 0;
+
+    void reset() {
+        free_blocks.clear();
+        if (size) free_blocks[0] = size;
+        in_use = 0;
+    }
+    size_t largest() const {
+        size_t m = 0;
+        for (const auto &f : free_blocks) m = std::max(m, f.second);
+        return m;
+    }
+    bool take(size_t bytes, size_t *off) {
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, o2 = it->first + bytes;
+            free_blocks.erase(it);
+            if (rest) free_blocks[o2] = rest;
+            in_use += bytes;
+            return true;
+        }
+        return false;
+    }
+    void give(size_t off, size_t bytes) {
+        auto it = free_blocks.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_blocks.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_blocks.erase(nx);
+        }
+        if (it != free_blocks.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_blocks.erase(it);
+            }
+        }
+        in_use -= bytes;
+    }
+};
+
 struct Lane {
     int id = 0;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    Workspace ws;
-    char *d_in = nullptr;      // device: offsets | z | vane of one launch
-    char *h_in = nullptr;      // pinned staging of the same bytes
+    Workspace ws;              // pointers into the launch's arena block
+    size_t blk_off = 0, blk_bytes = 0;
+    char *h_in = nullptr;      // pinned staging: offsets | z | vane of one launch
     size_t in_bytes = 0;
     char *h_out = nullptr;     // pinned, written by the device: counts | cand | hit_index
     int64_t *counts = nullptr;
@@ -77,6 +132,7 @@ struct Server {
     hough_server_config sc{};
     Clock::time_point t0;
     std::vector<Lane> lanes;
+    Arena arena;
 
     std::mutex mq;             // queue, its counters, stats
     std::condition_variable cv;
@@ -96,6 +152,14 @@ struct Server {
 
     size_t input_bytes(int64_t events, int64_t hits) const {
         return align16(align16(8 * (size_t)(events + 1)) + 4 * (size_t)hits) + 2 * (size_t)hits;
+    }
+
+    // Device bytes of one launch: its inputs, then the finder workspace for
+    // exactly these events and hits.
+    size_t block_bytes(int64_t events, int64_t hits) const {
+        const size_t in = (input_bytes(events, hits) + 255) & ~(size_t)255;
+        return in + hough::rt::layout_workspace(*ctx, std::max<int64_t>(hits, 1), std::max<int64_t>(events, 1),
+                                                ctx->big_pk, nullptr, nullptr);
     }
 
     // Packs the requests into the lane's staging buffer, copies them to the
@@ -121,15 +185,24 @@ struct Server {
         }
         offs[ne] = o;
         const size_t bytes = vo + 2 * (size_t)nh;
-        if (hipMemcpyAsync(L.d_in, L.h_in, bytes, hipMemcpyHostToDevice, L.stream) != hipSuccess)
+        char *d_in = arena.base + L.blk_off;
+        const size_t in_al = (input_bytes(ne, nh) + 255) & ~(size_t)255;
+        hough::rt::layout_workspace(*ctx, std::max<int64_t>(nh, 1), std::max<int64_t>(ne, 1), ctx->big_pk,
+                                    d_in + in_al, &L.ws);
+        if (hipMemcpyAsync(d_in, L.h_in, bytes, hipMemcpyHostToDevice, L.stream) != hipSuccess)
+            return HOUGH_ERR_DEVICE;
+        // the block held another launch's data: clear the words the finder
+        // expects at zero
+        if (hough::launch_clear_workspace(L.ws.err, L.ws.g_cnt, L.ws.g_flag, L.ws.events, L.ws.pool_flags,
+                                          L.ws.pool_slots, L.stream) != hipSuccess)
             return HOUGH_ERR_DEVICE;
         // no longest-first ordering here: the lanes' launches overlap on the
         // device, and ordered overlapping launches of thousands of mixed
         // events (every lane's large events at once) ran slower than unordered
         hough_status s = hough::rt::enqueue_find(*ctx, L.ws, L.stream, (int32_t)ne, nh,
-                                                 reinterpret_cast<const int64_t *>(L.d_in),
-                                                 reinterpret_cast<const float *>(L.d_in + zo),
-                                                 reinterpret_cast<const int16_t *>(L.d_in + vo), ctx->cfg.max_iters,
+                                                 reinterpret_cast<const int64_t *>(d_in),
+                                                 reinterpret_cast<const float *>(d_in + zo),
+                                                 reinterpret_cast<const int16_t *>(d_in + vo), ctx->cfg.max_iters,
                                                  L.cand, L.hits, L.counts, false, false);
         if (s) return s;
         if (hipEventRecord(L.done, L.stream) != hipSuccess) return HOUGH_ERR_DEVICE;
@@ -138,21 +211,36 @@ struct Server {
         return HOUGH_OK;
     }
 
-    // Takes the arrived requests that fit a lane, oldest first.
+    // Takes the arrived requests, oldest first, while their launch's device
+    // block fits the arena's largest free block and the lane's pinned buffers.
     bool admit(Lane &L) {
         double t;
         {
             std::lock_guard<std::mutex> g(mq);
             t = now();
             int64_t hits = 0;
+            const size_t room = arena.largest();
             while (!queue.empty() && (int64_t)L.reqs.size() < sc.max_batch_events) {
                 Request &r = queue.front();
-                if (r.t_arrival > t || hits + r.n > sc.max_batch_hits) break;
+                if (r.t_arrival > t || hits + r.n > sc.max_batch_hits ||
+                    block_bytes((int64_t)L.reqs.size() + 1, hits + r.n) > room)
+                    break;
                 hits += r.n;
                 L.reqs.push_back(std::move(r));
                 queue.pop_front();
             }
             if (L.reqs.empty()) return false;
+            L.blk_bytes = block_bytes((int64_t)L.reqs.size(), hits);
+            if (!arena.take(L.blk_bytes, &L.blk_off)) {
+                // cannot happen (the block fits the largest free one): put the
+                // requests back in front, in order
+                for (auto it = L.reqs.rbegin(); it != L.reqs.rend(); ++it) queue.push_front(std::move(*it));
+                L.reqs.clear();
+                L.blk_bytes = 0;
+                return false;
+            }
+            st.device_bytes_in_use = (int64_t)arena.in_use;
+            st.max_device_bytes_in_use = std::max<int64_t>(st.max_device_bytes_in_use, st.device_bytes_in_use);
             q_hits -= hits;
             st.pending_events -= (int64_t)L.reqs.size();
             st.launches += 1;
@@ -206,6 +294,9 @@ struct Server {
         }
         {
             std::lock_guard<std::mutex> g(mq);
+            if (L.blk_bytes) arena.give(L.blk_off, L.blk_bytes);
+            L.blk_bytes = 0;
+            st.device_bytes_in_use = (int64_t)arena.in_use;
             st.completed += (int64_t)L.reqs.size();
             --lanes_busy;
         }
@@ -267,8 +358,6 @@ const Server *as_server(const hough_server *p) {
 
 void free_lane(Lane &L) {
     if (L.stream) (void)hipStreamSynchronize(L.stream);
-    hough::rt::free_workspace(L.ws);
-    if (L.d_in) (void)hipFree(L.d_in);
     if (L.h_in) (void)hipHostFree(L.h_in);
     if (L.h_out) (void)hipHostFree(L.h_out);
     if (L.done) (void)hipEventDestroy(L.done);
@@ -284,6 +373,7 @@ void free_server(Server *s) {
     }
     if (s->ctx) (void)hipSetDevice(s->ctx->device);
     for (Lane &L : s->lanes) free_lane(L);
+    if (s->arena.base) (void)hipFree(s->arena.base);
     if (s->ctx) hough::rt::free_context(s->ctx);
     s->magic = 0;
     delete s;
@@ -294,10 +384,7 @@ hough_status make_lane(Server &s, Lane &L, int id) {
     L.id = id;
     if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess) return HOUGH_ERR_DEVICE;
     if (hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) return HOUGH_ERR_DEVICE;
-    hough_status st = hough::rt::ensure_workspace(*s.ctx, L.ws, c.max_batch_hits, c.max_batch_events, L.stream);
-    if (st) return st;
     L.in_bytes = s.input_bytes(c.max_batch_events, c.max_batch_hits);
-    if (hipMalloc(&L.d_in, L.in_bytes) != hipSuccess) return HOUGH_ERR_OOM;
     if (hipHostMalloc(reinterpret_cast<void **>(&L.h_in), L.in_bytes, hipHostMallocDefault) != hipSuccess)
         return HOUGH_ERR_OOM;
     const int64_t ncand = c.max_batch_hits / (int64_t)s.ctx->cfg.min_votes + 1;
@@ -315,8 +402,6 @@ hough_status make_lane(Server &s, Lane &L, int id) {
     L.counts = reinterpret_cast<int64_t *>(L.h_out);
     L.cand = reinterpret_cast<hough_candidate *>(L.h_out + o_cand);
     L.hits = reinterpret_cast<int32_t *>(L.h_out + o_hits);
-    if (hipStreamSynchronize(L.stream) != hipSuccess) return HOUGH_ERR_DEVICE;
-    s.st.device_bytes += (int64_t)(L.ws.bytes + L.in_bytes);
     return HOUGH_OK;
 }
 
@@ -345,10 +430,9 @@ hough_status hough_server_create(const hough_config *cfg, int device, const houg
     if (c.queue_hits == 0) c.queue_hits = (int64_t)1 << 26;
     if (c.queue_events == 0) c.queue_events = 1 << 20;
     if (c.lanes < 1 || c.lanes > kMaxLanes || c.max_batch_events < 1 || c.max_batch_hits < 1 ||
-        c.max_batch_hits > 0x7fffffffLL || c.queue_hits < 1 || c.queue_events < 1)
+        c.max_batch_hits > 0x7fffffffLL || c.queue_hits < 1 || c.queue_events < 1 || c.reserved != 0 ||
+        c.device_bytes < 0)
         return HOUGH_ERR_INVALID_ARG;
-    for (int r : c.reserved)
-        if (r != 0) return HOUGH_ERR_INVALID_ARG;
     Server *s = new (std::nothrow) Server();
     if (!s) return HOUGH_ERR_OOM;
     s->sc = c;
@@ -359,6 +443,19 @@ hough_status hough_server_create(const hough_config *cfg, int device, const houg
         return st;
     }
     s->ctx = ctx;
+    // the device arena: by default what each lane would need for its
+    // largest launch, times the lanes
+    const size_t arena = c.device_bytes > 0 ? (size_t)c.device_bytes
+                                            : (size_t)c.lanes * s->block_bytes(c.max_batch_events, c.max_batch_hits);
+    s->sc.device_bytes = (int64_t)arena;
+    if (hipSetDevice(device) != hipSuccess || hipMalloc(reinterpret_cast<void **>(&s->arena.base), arena) != hipSuccess) {
+        s->arena.base = nullptr;
+        free_server(s);
+        return HOUGH_ERR_OOM;
+    }
+    s->arena.size = arena;
+    s->arena.reset();
+    s->st.device_bytes = (int64_t)arena;
     s->lanes.resize(c.lanes);
     for (int i = 0; i < c.lanes; ++i) {
         st = make_lane(*s, s->lanes[i], i);
@@ -418,7 +515,8 @@ hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t
             const uint64_t tag = tags ? tags[r] : (uint64_t)r;
             const double ta = t_arrival ? t_arrival[r] : t;
             hough_status bad = HOUGH_OK;
-            if (cnt > s->sc.max_batch_hits || cnt > HOUGH_MAX_EVENT_HITS)
+            if (cnt > s->sc.max_batch_hits || cnt > HOUGH_MAX_EVENT_HITS ||
+                s->block_bytes(1, cnt) > s->arena.size)
                 bad = HOUGH_ERR_CAPACITY;
             else if (!valid_hits(*s, z, vane, b, cnt))
                 bad = HOUGH_ERR_DATA;

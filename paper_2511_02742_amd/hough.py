@@ -85,7 +85,8 @@ def tw_config(**overrides) -> TwConfig:
 class ServerConfig(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("max_batch_events", ctypes.c_int32),
                 ("max_batch_hits", ctypes.c_int64), ("queue_hits", ctypes.c_int64),
-                ("queue_events", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("queue_events", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
 
 
 served_dtype = np.dtype([("tag", "<u8"), ("status", "<i4"), ("n_hits", "<i4"), ("n_candidates", "<i4"),
@@ -96,7 +97,7 @@ assert served_dtype.itemsize == 72
 
 SERVER_STAT_NAMES = ("submitted", "refused", "completed", "launches", "launched_events", "launched_hits",
                      "pending_events", "max_pending_events", "max_lanes_busy", "device_bytes",
-                     "results_waiting")
+                     "results_waiting", "device_bytes_in_use", "max_device_bytes_in_use")
 
 
 class HoughError(RuntimeError):
@@ -543,12 +544,13 @@ class HoughServer:
     back as host arrays."""
 
     def __init__(self, device: int = 0, lanes: int = 0, max_batch_events: int = 0,
-                 max_batch_hits: int = 0, queue_hits: int = 0, queue_events: int = 0, **cfg_overrides):
+                 max_batch_hits: int = 0, queue_hits: int = 0, queue_events: int = 0, device_bytes: int = 0,
+                 **cfg_overrides):
         self._lib = load_library()
         self.config = default_config(**cfg_overrides)
         sc = ServerConfig()
         sc.lanes, sc.max_batch_events, sc.max_batch_hits = lanes, max_batch_events, max_batch_hits
-        sc.queue_hits, sc.queue_events = queue_hits, queue_events
+        sc.queue_hits, sc.queue_events, sc.device_bytes = queue_hits, queue_events, device_bytes
         h = ctypes.c_void_p()
         st = self._lib.hough_server_create(ctypes.byref(self.config), device, ctypes.byref(sc), ctypes.byref(h))
         if st != HOUGH_OK:

@@ -92,11 +92,12 @@ def test_server_struct_layouts_match_header(tmp_path):
     src = tmp_path / "slayout.c"
     src.write_text(
         "#include <stdio.h>\n#include <stddef.h>\n#include \"hough_tf.h\"\n"
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(hough_server_config),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(hough_server_config),"
         " offsetof(hough_server_config, max_batch_hits), offsetof(hough_server_config, queue_events),"
         " sizeof(hough_served), offsetof(hough_served, cand_offset), offsetof(hough_served, t_done),"
         " sizeof(hough_server_stats), offsetof(hough_server_stats, device_bytes),"
-        " offsetof(hough_server_stats, results_waiting)); return 0;}\n")
+        " offsetof(hough_server_stats, results_waiting), offsetof(hough_server_config, device_bytes),"
+        " offsetof(hough_server_stats, max_device_bytes_in_use)); return 0;}\n")
     exe = tmp_path / "slayout"
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
@@ -104,7 +105,8 @@ def test_server_struct_layouts_match_header(tmp_path):
     want = [ctypes.sizeof(hough.ServerConfig), hough.ServerConfig.max_batch_hits.offset,
             hough.ServerConfig.queue_events.offset, sd.itemsize, sd.fields["cand_offset"][1],
             sd.fields["t_done"][1], 16 * 8, 8 * hough.SERVER_STAT_NAMES.index("device_bytes"),
-            8 * hough.SERVER_STAT_NAMES.index("results_waiting")]
+            8 * hough.SERVER_STAT_NAMES.index("results_waiting"), hough.ServerConfig.device_bytes.offset,
+            8 * hough.SERVER_STAT_NAMES.index("max_device_bytes_in_use")]
     assert got == want
 
 
@@ -119,7 +121,11 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert lib.hough_server_create(ctypes.byref(cfg), 0, ctypes.byref(bad), ctypes.byref(h)) == \
         hough.HOUGH_ERR_INVALID_ARG
     bad = hough.ServerConfig()
-    bad.reserved[1] = 1
+    bad.reserved = 1
+    assert lib.hough_server_create(ctypes.byref(cfg), 0, ctypes.byref(bad), ctypes.byref(h)) == \
+        hough.HOUGH_ERR_INVALID_ARG
+    bad = hough.ServerConfig()
+    bad.device_bytes = -1
     assert lib.hough_server_create(ctypes.byref(cfg), 0, ctypes.byref(bad), ctypes.byref(h)) == \
         hough.HOUGH_ERR_INVALID_ARG
     assert not h.value

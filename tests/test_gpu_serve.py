@@ -161,3 +161,33 @@ def test_served_poll_reports_a_result_too_large(gpu_available):
         assert st == HOUGH_ERR_CAPACITY and k.value == 0
         got = _collect(srv, 1)
     assert got[0].status == 0 and len(got[0].cand) > 1
+
+
+def test_served_admission_by_device_memory(gpu_available):
+    # a 2 MiB device arena: a launch's block (its inputs and a workspace for
+    # exactly its events and hits, about 0.5 MiB of large-event slot per
+    # event here) limits how many requests a launch takes and how many
+    # launches run at once; results stay byte-identical to one-event calls,
+    # and a request whose launch alone exceeds the arena is refused
+    from paper_2511_02742_amd.hough import HOUGH_ERR_CAPACITY, HoughFinder, HoughServer
+    batch = eventgen.mixed_pileup_batch(120, levels=(1, 10, 25, 50), seed0=4_100_000)
+    arena = 2 << 20
+    f = HoughFinder(0)
+    with HoughServer(0, lanes=3, device_bytes=arena) as srv:
+        assert srv.submit(batch.z, batch.vane, batch.offsets, tags=np.arange(120, dtype=np.uint64)) == 120
+        got = _collect(srv, 120)
+        st = srv.stats()
+        huge = eventgen.make_batch([eventgen.pileup_event(4_200_000 + i, n_tracks=150) for i in range(130)])
+        n_big = 100_000
+        assert huge.n_hits >= n_big
+        assert srv.submit(huge.z[:n_big], huge.vane[:n_big], np.array([0, n_big], np.int64),
+                          tags=np.array([999], np.uint64)) == 1
+        refused = _collect(srv, 1)[999]
+    assert st["device_bytes"] == arena
+    assert 0 < st["max_device_bytes_in_use"] <= arena and st["device_bytes_in_use"] == 0
+    assert st["launches"] >= 120 // 3 and st["launched_events"] == 120
+    assert refused.status == HOUGH_ERR_CAPACITY and refused.rec["lane"] == -1
+    for e in range(120):
+        z, v = _event(batch, e)
+        cand, hits, _ = f.find_host(z, v, np.array([0, len(z)], np.int64))
+        _same(got[e], cand, hits, ("arena", e))
