@@ -1,4 +1,9 @@
-"""Builds the gfx950 shared library ``libhough_tf.so`` in-tree with hipcc."""
+"""Builds the gfx950 shared library ``libhough_tf.so`` in-tree with hipcc.
+
+``build_library(phase_clocks=True)`` builds the measurement variant
+``libhough_tf_phases.so`` instead: the same library compiled with
+HOUGH_PHASE_CLOCKS, whose finder records its cycles per phase for every
+event into the event-clock buffer (see ``phase_clocks.py``)."""
 from __future__ import annotations
 
 import os
@@ -10,6 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhough_tf.so")
+LIB_PHASES = os.path.join(PKG, "libhough_tf_phases.so")
 SOURCES = [os.path.join(CSRC, "hough_kernels.hip"), os.path.join(CSRC, "hough_host.hip"),
            os.path.join(CSRC, "hough_serve.hip"), os.path.join(CSRC, "hough_refit.hip"),
            os.path.join(CSRC, "hough_cf.hip"), os.path.join(CSRC, "hough_probe.hip"),
@@ -37,16 +43,18 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build_library(verbose: bool = False) -> str:
+def build_library(verbose: bool = False, phase_clocks: bool = False) -> str:
     """Compiles the library (always) and returns its path."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + SOURCES
+    out = LIB_PHASES if phase_clocks else LIB
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + (["-DHOUGH_PHASE_CLOCKS"] if phase_clocks else []) + \
+        ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build_library(verbose="-v" in sys.argv))
+    print(build_library(verbose="-v" in sys.argv, phase_clocks="--phase-clocks" in sys.argv))

@@ -135,8 +135,28 @@ __device__ __forceinline__ int next_pow2(int v) {
     return p;
 }
 
+// Phases of k_find whose cycles the HOUGH_PHASE_CLOCKS build records per
+// event (the library built with that switch, a measurement aid; the default
+// build has no trace of it).
+enum FindPhase {
+    kPhAlive = 0,    // alive list and the register batch load
+    kPhSweep,        // row-stream sweep, hot-set recount or split-sweep hot list
+    kPhPeaks,        // window test and peak sort on the hot set
+    kPhAssoc,        // association (match masks, claims, emission)
+    kPhBigSweep,     // large event: banded sweep with the window test
+    kPhBigOrder,     // large event: peak ordering
+    kPhBigAssoc,     // large event: association
+    kPhTiled,        // tiled sweep fallback, its peaks and association
+    kPhRest,         // everything else (setup, validation, iteration ends)
+    kPhases
+};
+
 struct Shared {
     unsigned long long t_start;  // wall clock at the workgroup's start (event clock stamps)
+#ifdef HOUGH_PHASE_CLOCKS
+    unsigned long long t_ph;            // cycle counter at the last phase mark
+    unsigned long long ph[kPhases];     // cycles per phase
+#endif
     int hotc[2];
     int hs_cnt;
     int pcnt;
@@ -1438,6 +1458,23 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     }
 }
 
+// Charges the cycles since the last mark to phase k (thread 0; the marks sit
+// after a workgroup barrier, so thread 0's counter stands for the group).
+#ifdef HOUGH_PHASE_CLOCKS
+#define HOUGH_PHASE_MARK(k)                                                                                    \
+    do {                                                                                                       \
+        if (threadIdx.x == 0) {                                                                                \
+            const unsigned long long t_ = clock64();                                                          \
+            sh.ph[(k)] += t_ - sh.t_ph;                                                                        \
+            sh.t_ph = t_;                                                                                      \
+        }                                                                                                      \
+    } while (0)
+#else
+#define HOUGH_PHASE_MARK(k) \
+    do {                    \
+    } while (0)
+#endif
+
 __device__ void write_error_counts(int64_t *counts, long long status, long long detail) {
     counts[HOUGH_COUNT_CANDIDATES] = 0;
     counts[HOUGH_COUNT_HITS] = 0;
@@ -1466,6 +1503,21 @@ __device__ void put_ev_stats(const FindArgs &A, int e, unsigned long long evals,
 // At most 128 VGPRs at every width (four waves per SIMD): a 512-thread
 // finder whose tile leaves half the LDS free then shares a CU with another
 // event's workgroup, and a 256-thread one with up to three.
+// The event's clock stamps; in the HOUGH_PHASE_CLOCKS build, instead, its
+// cycles per phase (ev_clock[16 e + k], phase k; rest of the event's cycles
+// included in kPhRest).
+__device__ __forceinline__ void put_phases(const FindArgs &A, int e, Shared &sh) {
+#ifdef HOUGH_PHASE_CLOCKS
+    if (A.ev_clock != nullptr) {
+        const unsigned long long t_ = clock64();
+        sh.ph[kPhRest] += t_ - sh.t_ph;
+        for (int k = 0; k < kPhases; ++k) A.ev_clock[16 * (size_t)e + k] = sh.ph[k];
+    }
+#else
+    stamp_event(A, e, sh.t_start);
+#endif
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_find(FindArgs A,
                                                                                    const float2 *__restrict__ cs) {
@@ -1491,6 +1543,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
     if (threadIdx.x == 0) {
         if (A.ev_clock != nullptr) sh.t_start = wall_clock64();
+#ifdef HOUGH_PHASE_CLOCKS
+        sh.t_ph = clock64();
+        for (int k = 0; k < kPhases; ++k) sh.ph[k] = 0ull;
+#endif
         int bad = 0;
         if (b < 0 || n64 < 0 || b + n64 > A.n_total) bad = HOUGH_ERR_INVALID_ARG;
         if (e == 0 && b != 0) bad = HOUGH_ERR_INVALID_ARG;
@@ -1586,6 +1642,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int bigs = 0;          // iterations run in the large-event path
     HitRegs h;
     for (;;) {
+        HOUGH_PHASE_MARK(kPhRest);
         if (A.max_iters > 0 && iter >= A.max_iters) break;
         if (threadIdx.x == 0) sh.rlive = 0;  // live bins of a recount in this iteration
         // alive list, in ascending hit order (written with the validation
@@ -1625,6 +1682,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (threadIdx.x == 0) sh.nalive = n_alive;
         const int ncand0 = sh.ncand;
         if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
+        HOUGH_PHASE_MARK(kPhAlive);
 
         bool any = false;
         bool done = false;
@@ -1689,13 +1747,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                     votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                 }
+                HOUGH_PHASE_MARK(kPhSweep);
                 if (hs_valid) {
                     const int npk = hotset_peaks<NT>(A, L, n_hs, sh);
+                    HOUGH_PHASE_MARK(kPhPeaks);
                     if (npk >= 0) {
                         done = true;
                         if (npk > 0) {
                             any = true;
                             associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh, nullptr);
+                            HOUGH_PHASE_MARK(kPhAssoc);
                         }
                     }
                 }
@@ -1720,8 +1781,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         sh.best = 0ull;
                     }
                     __syncthreads();
+                    HOUGH_PHASE_MARK(kPhRest);
                     band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
                     sync_global();
+                    HOUGH_PHASE_MARK(kPhBigSweep);
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                     votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
                     int npk = -1;
@@ -1735,6 +1798,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             npk = order_peaks<NT>(A, L, S, sh.pcnt, sh);
                         }
                     }
+                    HOUGH_PHASE_MARK(kPhBigOrder);
                     if (npk >= 0) {
                         done = true;
                         if (npk > 0) {
@@ -1743,6 +1807,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             // borrowed them), the rest still in LDS
                             load_batch(A, b, n_alive, 0, h);
                             associate<NT>(A, cs, e, b, iter, L, S.srt, A.hs_off, h, nbatch, npk, sh, xh);
+                            HOUGH_PHASE_MARK(kPhBigAssoc);
                         }
                     } else {
                         ++hs_full;
@@ -1756,6 +1821,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             votes += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
         }
         unsigned long long ceil_key = ~0ull;
+        if (!done) HOUGH_PHASE_MARK(kPhRest);
         for (; !done;) {
             ++passes;
             ++tiled;
@@ -1785,6 +1851,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             any = true;
             const unsigned long long drop = sh.maxdrop;
             associate<NT>(A, cs, e, b, iter, L, L.pbuf, A.tile_bytes, h, nbatch, npk, sh, nullptr);
+            HOUGH_PHASE_MARK(kPhTiled);
             if (drop == 0ull) break;
             ceil_key = drop;
         }
@@ -1820,7 +1887,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             A.counts[HOUGH_COUNT_LARGE] = bigs;
             A.counts[HOUGH_COUNT_VOTES] = (long long)votes;
             A.counts[HOUGH_COUNT_ORDERED] = 0;
-            stamp_event(A, e, sh.t_start);
+            put_phases(A, e, sh);
         }
         return;
     }
@@ -1828,7 +1895,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
         put_ev_stats(A, e, evals, iter, passes, tiled, sh.n_trunc, sh.n_hotscan, hs_full, recounts, bigs, votes);
-        stamp_event(A, e, sh.t_start);
+        put_phases(A, e, sh);
     }
 }
 
