@@ -244,6 +244,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timings and the oracle references (no parity check then)")
     ap.add_argument("--no-autotune", action="store_true", help="headline on the library's default shape")
+    ap.add_argument("--launch", default="",
+                    help="WG,TILE: headline on this finder workgroup size and tile rows instead of the autotuner's "
+                         "pick (for profiler runs of one shape)")
     ap.add_argument("--serve-events", type=int, default=1000000,
                     help="requests per offered rate in the served-stream leg (0: skip it)")
     ap.add_argument("--serve-rates", default="20000,50000,100000")
@@ -336,6 +339,9 @@ def main():
     tune = None
     if args.only_batched and args.finder == "cf":
         f = HoughFinder(0, n_theta=180, n_rho=1000, peak_mode=2)
+    elif args.launch:
+        wg, tr = (int(x) for x in args.launch.split(","))
+        f = HoughFinder(0, wg_threads=wg, tile_rows=tr)
     elif args.no_autotune:
         f = HoughFinder(0)
     else:
