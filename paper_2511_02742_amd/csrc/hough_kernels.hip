@@ -1637,7 +1637,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     bool first = true;
     int n_hs = 0;          // entries of the hot set
     bool hs_valid = false; // the hot set holds every bin >= T of the current histogram
-    bool big = false;      // large event: hot set and peaks in a device-memory slot
+    bool big = false;      // large-event path this iteration: peaks in a device-memory slot
+    bool big_lds = false;  // the hot set or the peak list outgrew LDS: the event stays large
     int slot = -1;
     int bigs = 0;          // iterations run in the large-event path
     HitRegs h;
@@ -1686,9 +1687,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
         bool any = false;
         bool done = false;
-        // an event with more than one register batch of alive hits is large;
-        // it stays large (its hot set lives in its slot)
-        if (nbatch > 1) big = true;
+        // an iteration with more than one register batch of alive hits takes
+        // the large-event path; once fewer hits are left the next one sweeps
+        // row by row again (a fresh histogram either way), unless the hot set
+        // or the peak list outgrew LDS in an earlier iteration
+        big = big_lds || nbatch > 1;
         // (the LDS-resident hits are read in whole 64-hit chunks, at most
         // 56 of them: the banded sweep flags hot votes in 64 bits)
         if (A.stream_ok && n_alive <= kChunks * kWave + min(A.hs_cap & ~(kWave - 1), 56 * kWave)) {
@@ -1763,6 +1766,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 if (!done) {
                     // more bins at or above T, or more peaks, than LDS holds
                     big = true;
+                    big_lds = true;
                     hs_valid = false;
                 }
             }
