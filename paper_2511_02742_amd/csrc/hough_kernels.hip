@@ -148,6 +148,13 @@ enum FindPhase {
     kPhBigAssoc,     // large event: association
     kPhTiled,        // tiled sweep fallback, its peaks and association
     kPhRest,         // everything else (setup, validation, iteration ends)
+    // association, any path (charged here instead of kPhAssoc / kPhBigAssoc):
+    kPhAsPrep,       // claimed-hit masks and the peaks' coordinates
+    kPhAsMask,       // match masks
+    kPhAsClaim,      // claims
+    kPhAsEmit,       // emission order and candidate records
+    kPhAsLists,      // hit lists
+    kPhRecount,      // hot-set recount (charged here instead of kPhSweep)
     kPhases
 };
 
@@ -177,6 +184,23 @@ struct Shared {
     int rollc[16 * kMaxLists];  // fill of each wave's row lists (banded sweep)
     int rlive;       // live bins the last recount tested
 };
+
+// Charges the cycles since the last mark to phase k (thread 0; the marks sit
+// after a workgroup barrier, so thread 0's counter stands for the group).
+#ifdef HOUGH_PHASE_CLOCKS
+#define HOUGH_PHASE_MARK(k)                                                                                    \
+    do {                                                                                                       \
+        if (threadIdx.x == 0) {                                                                                \
+            const unsigned long long t_ = clock64();                                                          \
+            sh.ph[(k)] += t_ - sh.t_ph;                                                                        \
+            sh.t_ph = t_;                                                                                      \
+        }                                                                                                      \
+    } while (0)
+#else
+#define HOUGH_PHASE_MARK(k) \
+    do {                    \
+    } while (0)
+#endif
 
 // LDS layout of k_find (dynamic part):
 //   [0, tile_bytes)        tile rows, reused by the association phase
@@ -1317,6 +1341,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     __syncthreads();
 
     for (int p0 = 0; p0 < npk; p0 += pb) {
+        HOUGH_PHASE_MARK(kPhAsPrep);
         const int nb = min(pb, npk - p0);
         // coordinates and (cos, sin) of this pass's peaks
         if (p0 == 0 && nb0 <= NT) {
@@ -1385,6 +1410,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             if (nbatch > 1) __syncthreads();
         }
         __syncthreads();
+        HOUGH_PHASE_MARK(kPhAsMask);
         // B: which peaks claim which hits
         if (W <= kClaimBlockW)
             claim_block(A, icl, M, pst, W, nb);
@@ -1393,6 +1419,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         else
             claim_serial<NT>(A, icl, M, pst, W, nb);
         __syncthreads();
+        HOUGH_PHASE_MARK(kPhAsClaim);
         // emission order = key order of the taken peaks
         if (wave == 0) {
             int nemit = 0;
@@ -1440,6 +1467,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             }
         }
         __syncthreads();
+        HOUGH_PHASE_MARK(kPhAsEmit);
         // C: hit lists (ascending alive-list position = ascending hit index)
         for (int t = wave; t < nemit * W; t += NW) {
             const int ei = t / W;
@@ -1455,25 +1483,10 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             }
         }
         __syncthreads();
+        HOUGH_PHASE_MARK(kPhAsLists);
     }
 }
 
-// Charges the cycles since the last mark to phase k (thread 0; the marks sit
-// after a workgroup barrier, so thread 0's counter stands for the group).
-#ifdef HOUGH_PHASE_CLOCKS
-#define HOUGH_PHASE_MARK(k)                                                                                    \
-    do {                                                                                                       \
-        if (threadIdx.x == 0) {                                                                                \
-            const unsigned long long t_ = clock64();                                                          \
-            sh.ph[(k)] += t_ - sh.t_ph;                                                                        \
-            sh.t_ph = t_;                                                                                      \
-        }                                                                                                      \
-    } while (0)
-#else
-#define HOUGH_PHASE_MARK(k) \
-    do {                    \
-    } while (0)
-#endif
 
 __device__ void write_error_counts(int64_t *counts, long long status, long long detail) {
     counts[HOUGH_COUNT_CANDIDATES] = 0;
@@ -1735,6 +1748,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #undef HOUGH_RECOUNT_CASE
                     ++recounts;
                     __syncthreads();
+                    HOUGH_PHASE_MARK(kPhRecount);
                     evals += (unsigned long long)sh.rlive * (unsigned long long)(h.nch * kWave);
                 } else {
                     // row-stream sweep; a hot set larger than LDS holds

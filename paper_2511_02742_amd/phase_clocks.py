@@ -18,8 +18,9 @@ import sys
 
 import numpy as np
 
-PHASES = ("alive list", "sweep / recount", "window test + sort", "association", "large: banded sweep",
-          "large: peak order", "large: association", "tiled fallback", "rest")
+PHASES = ("alive list", "sweep / recount", "window test + sort", "association (other)", "large: banded sweep",
+          "large: peak order", "large: association (other)", "tiled fallback", "rest", "assoc: claimed masks",
+          "assoc: match masks", "assoc: claims", "assoc: emission", "assoc: hit lists", "recount")
 
 
 def main():
