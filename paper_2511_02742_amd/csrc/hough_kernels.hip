@@ -44,6 +44,10 @@ constexpr int kWave = 64;
 // Dynamic LDS of every kernel here (the allocation starts at this symbol);
 // indexing it keeps LDS addresses 32-bit.
 extern __shared__ __align__(16) uint32_t g_lds[];
+// Byte address of g_lds[w] in the LDS address space.
+__device__ __forceinline__ uint32_t lds_byte(uint32_t w) {
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint32_t *)(g_lds + w);
+}
 constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
 constexpr int kMaxLists = 5;  // row lists of the banded sweep: 2 w + 1 for w <= 2
 constexpr int kClaimBlockW = 8;  // alive-hit words up to which claims are resolved in registers
@@ -103,6 +107,176 @@ __device__ __forceinline__ bool rho_in(float phi, float z, float c, float s, flo
     float rho = a + b;
     float u = (rho - rho_min) * inv_w;
     return u >= lo && u < hi_excl;
+}
+
+// Adds 1 to the LDS words at byte addresses a[0, N) and returns their old
+// values in o. All N atomics are issued before a single wait, so the wave
+// keeps N of them in flight; the wait is part of the same statement, so no
+// result register is read or given to another value before it is written.
+template <int N>
+__device__ __forceinline__ void lds_inc_rtn(const uint32_t (&a)[N], uint32_t (&o)[N]);
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<1>(const uint32_t (&a)[1], uint32_t (&o)[1]) {
+    asm volatile("ds_add_rtn_u32 %0, %1, %2\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0])
+                 : "v"(a[0]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<2>(const uint32_t (&a)[2], uint32_t (&o)[2]) {
+    asm volatile("ds_add_rtn_u32 %0, %2, %4\n\t"
+                 "ds_add_rtn_u32 %1, %3, %4\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1])
+                 : "v"(a[0]), "v"(a[1]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<3>(const uint32_t (&a)[3], uint32_t (&o)[3]) {
+    asm volatile("ds_add_rtn_u32 %0, %3, %6\n\t"
+                 "ds_add_rtn_u32 %1, %4, %6\n\t"
+                 "ds_add_rtn_u32 %2, %5, %6\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<4>(const uint32_t (&a)[4], uint32_t (&o)[4]) {
+    asm volatile("ds_add_rtn_u32 %0, %4, %8\n\t"
+                 "ds_add_rtn_u32 %1, %5, %8\n\t"
+                 "ds_add_rtn_u32 %2, %6, %8\n\t"
+                 "ds_add_rtn_u32 %3, %7, %8\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<5>(const uint32_t (&a)[5], uint32_t (&o)[5]) {
+    asm volatile("ds_add_rtn_u32 %0, %5, %10\n\t"
+                 "ds_add_rtn_u32 %1, %6, %10\n\t"
+                 "ds_add_rtn_u32 %2, %7, %10\n\t"
+                 "ds_add_rtn_u32 %3, %8, %10\n\t"
+                 "ds_add_rtn_u32 %4, %9, %10\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<6>(const uint32_t (&a)[6], uint32_t (&o)[6]) {
+    asm volatile("ds_add_rtn_u32 %0, %6, %12\n\t"
+                 "ds_add_rtn_u32 %1, %7, %12\n\t"
+                 "ds_add_rtn_u32 %2, %8, %12\n\t"
+                 "ds_add_rtn_u32 %3, %9, %12\n\t"
+                 "ds_add_rtn_u32 %4, %10, %12\n\t"
+                 "ds_add_rtn_u32 %5, %11, %12\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<7>(const uint32_t (&a)[7], uint32_t (&o)[7]) {
+    asm volatile("ds_add_rtn_u32 %0, %7, %14\n\t"
+                 "ds_add_rtn_u32 %1, %8, %14\n\t"
+                 "ds_add_rtn_u32 %2, %9, %14\n\t"
+                 "ds_add_rtn_u32 %3, %10, %14\n\t"
+                 "ds_add_rtn_u32 %4, %11, %14\n\t"
+                 "ds_add_rtn_u32 %5, %12, %14\n\t"
+                 "ds_add_rtn_u32 %6, %13, %14\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(1u)
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_inc_rtn<8>(const uint32_t (&a)[8], uint32_t (&o)[8]) {
+    asm volatile("ds_add_rtn_u32 %0, %8, %16\n\t"
+                 "ds_add_rtn_u32 %1, %9, %16\n\t"
+                 "ds_add_rtn_u32 %2, %10, %16\n\t"
+                 "ds_add_rtn_u32 %3, %11, %16\n\t"
+                 "ds_add_rtn_u32 %4, %12, %16\n\t"
+                 "ds_add_rtn_u32 %5, %13, %16\n\t"
+                 "ds_add_rtn_u32 %6, %14, %16\n\t"
+                 "ds_add_rtn_u32 %7, %15, %16\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]), "v"(1u)
+                 : "memory");
+}
+
+// Adds v[i] to the LDS word at byte address a[i], for i in [0, N), and
+// returns the old values in o; issued and waited for like lds_inc_rtn.
+template <int N>
+__device__ __forceinline__ void lds_add_rtn(const uint32_t (&a)[N], const uint32_t (&v)[N], uint32_t (&o)[N]);
+
+template <>
+__device__ __forceinline__ void lds_add_rtn<1>(const uint32_t (&a)[1], const uint32_t (&v)[1], uint32_t (&o)[1]) {
+    asm volatile("ds_add_rtn_u32 %0, %1, %2\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0])
+                 : "v"(a[0]), "v"(v[0])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_add_rtn<2>(const uint32_t (&a)[2], const uint32_t (&v)[2], uint32_t (&o)[2]) {
+    asm volatile("ds_add_rtn_u32 %0, %2, %4\n\t"
+                 "ds_add_rtn_u32 %1, %3, %5\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1])
+                 : "v"(a[0]), "v"(a[1]), "v"(v[0]), "v"(v[1])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_add_rtn<3>(const uint32_t (&a)[3], const uint32_t (&v)[3], uint32_t (&o)[3]) {
+    asm volatile("ds_add_rtn_u32 %0, %3, %6\n\t"
+                 "ds_add_rtn_u32 %1, %4, %7\n\t"
+                 "ds_add_rtn_u32 %2, %5, %8\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(v[0]), "v"(v[1]), "v"(v[2])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_add_rtn<4>(const uint32_t (&a)[4], const uint32_t (&v)[4], uint32_t (&o)[4]) {
+    asm volatile("ds_add_rtn_u32 %0, %4, %8\n\t"
+                 "ds_add_rtn_u32 %1, %5, %9\n\t"
+                 "ds_add_rtn_u32 %2, %6, %10\n\t"
+                 "ds_add_rtn_u32 %3, %7, %11\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3])
+                 : "memory");
+}
+
+template <>
+__device__ __forceinline__ void lds_add_rtn<8>(const uint32_t (&a)[8], const uint32_t (&v)[8], uint32_t (&o)[8]) {
+    asm volatile("ds_add_rtn_u32 %0, %8, %16\n\t"
+                 "ds_add_rtn_u32 %1, %9, %17\n\t"
+                 "ds_add_rtn_u32 %2, %10, %18\n\t"
+                 "ds_add_rtn_u32 %3, %11, %19\n\t"
+                 "ds_add_rtn_u32 %4, %12, %20\n\t"
+                 "ds_add_rtn_u32 %5, %13, %21\n\t"
+                 "ds_add_rtn_u32 %6, %14, %22\n\t"
+                 "ds_add_rtn_u32 %7, %15, %23\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]), "=&v"(o[7])
+                 : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7])
+                 : "memory");
 }
 
 __device__ __forceinline__ unsigned long long bin_key(uint32_t count, uint32_t flat) {
@@ -398,18 +572,22 @@ __device__ __forceinline__ void stream_rows(const FindArgs &A, const float2 *__r
             t.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
             t.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
             uint32_t addr[NCH];
+            uint32_t ba[NCH];
             uint32_t old[NCH];
             bool hot[NCH];
+            bool inr[NCH];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
                 // with SAFE every hit is in range and only the last chunk can
                 // be partly filled
-                const bool in = SAFE ? (c + 1 < NCH || valid[c]) : (valid[c] && (unsigned)k < (unsigned)A.n_rho);
-                addr[c] = (SAFE && c + 1 < NCH) ? row_w + (uint32_t)k : (in ? row_w + (uint32_t)k : dummy_w);
-                old[c] = atomicAdd(&g_lds[addr[c]], 1u);
-                hot[c] = in && old[c] == tm1;
+                inr[c] = SAFE ? (c + 1 < NCH || valid[c]) : (valid[c] && (unsigned)k < (unsigned)A.n_rho);
+                addr[c] = (SAFE && c + 1 < NCH) ? row_w + (uint32_t)k : (inr[c] ? row_w + (uint32_t)k : dummy_w);
+                ba[c] = lds_byte(addr[c]);
             }
+            lds_inc_rtn<NCH>(ba, old);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) hot[c] = inr[c] && old[c] == tm1;
             bool any = false;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) any = any || hot[c];
@@ -845,19 +1023,20 @@ __device__ __forceinline__ void band_big(const FindArgs &A, const float2 *__rest
             // LDS chunk x) and collected once the row is done
             unsigned long long hot = 0ull;
             {
-                uint32_t olds[kChunks];
+                uint32_t olds[kChunks], ba[kChunks];
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) {
                     const int k = rho_bin(h.phi[c], h.z[c], t.x, t.y, A.rho_min, A.inv_w);
-                    olds[c] = atomicAdd(&g_lds[valid[c] ? row_w + (uint32_t)k : dummy_w], 1u);
+                    ba[c] = lds_byte(valid[c] ? row_w + (uint32_t)k : dummy_w);
                 }
+                lds_inc_rtn<kChunks>(ba, olds);
 #pragma unroll
                 for (int c = 0; c < kChunks; ++c) hot |= (unsigned long long)(valid[c] && olds[c] == tm1) << c;
             }
             for (int xb = 0; xb < nx; xb += kChunks) {
                 // eight LDS chunks at a time: loads, then votes
                 float2 pz[kChunks];
-                uint32_t olds[kChunks];
+                uint32_t olds[kChunks], ba[kChunks];
 #pragma unroll
                 for (int u = 0; u < kChunks; ++u)
                     pz[u] = xb + u < nx ? xh[(xb + u) * kWave + lane] : make_float2(0.0f, 0.0f);
@@ -865,8 +1044,9 @@ __device__ __forceinline__ void band_big(const FindArgs &A, const float2 *__rest
                 for (int u = 0; u < kChunks; ++u) {
                     const bool v = xb + u < nx && kChunks * kWave + (xb + u) * kWave + lane < n_alive;
                     const int k = rho_bin(pz[u].x, pz[u].y, t.x, t.y, A.rho_min, A.inv_w);
-                    olds[u] = atomicAdd(&g_lds[v ? row_w + (uint32_t)k : dummy_w], 1u);
+                    ba[u] = lds_byte(v ? row_w + (uint32_t)k : dummy_w);
                 }
+                lds_inc_rtn<kChunks>(ba, olds);
 #pragma unroll
                 for (int u = 0; u < kChunks; ++u) {
                     const bool v = xb + u < nx && kChunks * kWave + (xb + u) * kWave + lane < n_alive;
@@ -913,6 +1093,215 @@ __device__ __forceinline__ void band_big(const FindArgs &A, const float2 *__rest
     // rows whose window reaches past the last row of the grid
     if (A.peak_mode == 1)
         for (int jt = max(r0, jhi - w); jt < r1; ++jt) band_test(A, roll, rc, nl, cap, jt, pk, sh);
+}
+
+// LDS byte offset of band_ring's third ring rows and row lists: after the
+// nx LDS-resident hit chunks, up to the end of the tile.
+__device__ __forceinline__ int ring_off(const FindArgs &A, int nx) {
+    return A.hs_off + ((nx * kWave * 8 + 15) & ~15);
+}
+
+// Whether band_ring can run: a 3 x 3 window, 16-bit counts, and room for
+// the third ring row of every wave and row lists of at least 32 bins.
+template <int NT>
+__device__ __forceinline__ bool band_ring_ok(const FindArgs &A, int n_alive, int nx) {
+    constexpr int NW = NT / kWave;
+    const int room = A.roll_off + A.roll_bytes - ring_off(A, nx);
+    return A.nms_radius == 1 && n_alive < 65536 && room - NW * (A.pitch / 2) * 4 >= 12 * NW * 32;
+}
+
+// Votes of U hit chunks (LDS-resident hits xh, chunks x0 .. x0 + U - 1) into
+// the 16-bit row at word R; bins lifted to T are appended to the row list.
+template <int U>
+__device__ __forceinline__ void ring_votes_x(const FindArgs &A, const float2 *xh, int x0, int nx, int n_alive,
+                                             float c, float sn, uint32_t R, uint32_t dummy_w, uint32_t *lst,
+                                             int *lc, int cap) {
+    const int lane = lane_id();
+    const uint32_t tm1 = A.min_votes - 1u;
+    float2 pz[U];
+    bool v[U];
+    int k[U];
+    uint32_t ba[U], val[U], old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        v[u] = x0 + u < nx && kChunks * kWave + (x0 + u) * kWave + lane < n_alive;
+        pz[u] = x0 + u < nx ? xh[(x0 + u) * kWave + lane] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        k[u] = rho_bin(pz[u].x, pz[u].y, c, sn, A.rho_min, A.inv_w);
+        ba[u] = lds_byte(v[u] ? R + ((uint32_t)k[u] >> 1) : dummy_w);
+        val[u] = 1u << ((k[u] & 1) << 4);
+    }
+    lds_add_rtn<U>(ba, val, old);
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        v[u] = v[u] && ((old[u] >> ((k[u] & 1) << 4)) & 0xffffu) == tm1;
+        any = any || v[u];
+    }
+    if (__ballot(any) != 0ull) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u]) {
+                const int s = atomicAdd(lc, 1);
+                if (s < cap) lst[s] = (uint32_t)k[u];
+            }
+        }
+    }
+}
+
+// Window test of the bins >= T of row jt (list lst[0, n)) against the
+// 16-bit counts of rows jt - 1, jt, jt + 1 (words Rp, Rc, Rn); a neighbour
+// with a lower flat index (row above, or left) wins ties.
+__device__ __forceinline__ void ring_test(const FindArgs &A, const uint32_t *lst, int n, uint32_t Rp, uint32_t Rc,
+                                          uint32_t Rn, int jt, unsigned long long *pk, Shared &sh) {
+    const uint16_t *rp = reinterpret_cast<const uint16_t *>(g_lds + Rp);
+    const uint16_t *rc = reinterpret_cast<const uint16_t *>(g_lds + Rc);
+    const uint16_t *rn = reinterpret_cast<const uint16_t *>(g_lds + Rn);
+    const bool up = jt > 0, dn = jt + 1 < A.n_theta;
+    for (int x = lane_id(); x < n; x += kWave) {
+        const int k = (int)lst[x];
+        const bool lf = k > 0, rt = k + 1 < A.n_rho;
+        const uint32_t c = rc[k];
+        const uint32_t a0 = up && lf ? rp[k - 1] : 0u, a1 = up ? rp[k] : 0u, a2 = up && rt ? rp[k + 1] : 0u;
+        const uint32_t b0 = lf ? rc[k - 1] : 0u, b2 = rt ? rc[k + 1] : 0u;
+        const uint32_t c0 = dn && lf ? rn[k - 1] : 0u, c1 = dn ? rn[k] : 0u, c2 = dn && rt ? rn[k + 1] : 0u;
+        const bool peak = a0 < c && a1 < c && a2 < c && b0 < c && b2 <= c && c0 <= c && c1 <= c && c2 <= c;
+        if (peak) {
+            const int slot = atomicAdd(&sh.pcnt, 1);
+            if (slot < A.big_pk) pk[slot] = bin_key(c, (uint32_t)(jt * A.n_rho + k));
+        }
+    }
+}
+
+// Banded row-stream sweep of a large event for a 3 x 3 window with 16-bit
+// counts (two bins per LDS word; an event on this path has fewer than 2^16
+// alive hits, so a count never carries into its neighbour). Wave w streams
+// its band of rows [r0, r1) plus one row on either side and keeps the
+// histograms of its last three rows: two in its row buffer, one after the
+// LDS-resident hits. A row's votes append the bins they lift to T to the row's list;
+// once row j is in, the listed bins of row j - 1 are window-tested by reading
+// their eight neighbours' counts directly, and the histogram of row j - 2 is
+// cleared for row j + 1. Same peaks as band_big with w = 1; argmax mode
+// takes the largest key of the listed bins instead.
+template <int NT>
+__device__ __forceinline__ void band_ring(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L,
+                                          const HitRegs &h, const float2 *xh, int nx, int n_alive,
+                                          unsigned long long *pk, Shared &sh) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    const uint32_t tm1 = A.min_votes - 1u;
+    const int hw = A.pitch / 2;  // words of a 16-bit row (pitch is a multiple of 4)
+    const int roff = ring_off(A, nx);
+    const uint32_t ring0 = (uint32_t)(wave * A.pitch);
+    const uint32_t ring2 = (uint32_t)(roff / 4 + wave * hw);
+    const int cap = (A.roll_off + A.roll_bytes - roff - NW * hw * 4) / (12 * NW);
+    uint32_t *lists = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.tile) + roff +
+                                                   NW * hw * 4) + wave * 3 * cap;
+    int *rc = &sh.rollc[wave * kMaxLists];
+    const uint32_t dummy_w = (uint32_t)(L.dummy - L.tile) + threadIdx.x;
+    bool valid[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) valid[c] = c < h.nch && c * kWave + lane < n_alive;
+    // the three rows start at zero (8-byte stores: hw is even, the rows are
+    // 8-byte aligned)
+    {
+        uint2 *q0 = reinterpret_cast<uint2 *>(g_lds + ring0);
+        uint2 *q2 = reinterpret_cast<uint2 *>(g_lds + ring2);
+        for (int x = lane; x < hw; x += kWave) q0[x] = make_uint2(0u, 0u);
+        for (int x = lane; x < hw / 2; x += kWave) q2[x] = make_uint2(0u, 0u);
+        if (lane < 3) rc[lane] = 0;
+    }
+    const int bw = (A.n_theta + NW - 1) / NW;
+    const int r0 = wave * bw;
+    const int r1 = min(A.n_theta, r0 + bw);
+    if (r0 >= r1) return;
+    const int jlo = max(r0 - 1, 0);
+    const int jhi = min(r1 + 1, A.n_theta);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    for (int jb = jlo; jb < jhi; jb += kWave) {
+        const int nr = min(kWave, jhi - jb);
+        const float2 mine = lane < nr ? cs[jb + lane] : make_float2(0.0f, 0.0f);
+        for (int i = 0; i < nr; ++i) {
+            const int j = jb + i;
+            const int cur = j % 3;
+            const uint32_t R = cur == 2 ? ring2 : ring0 + (uint32_t)(cur * hw);
+            uint32_t *lst = lists + cur * cap;
+            int *lc = &rc[cur];
+            const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
+            const float sn = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
+            {
+                int k[kChunks];
+                uint32_t ba[kChunks], val[kChunks], old[kChunks];
+#pragma unroll
+                for (int ch = 0; ch < kChunks; ++ch) {
+                    k[ch] = rho_bin(h.phi[ch], h.z[ch], c, sn, A.rho_min, A.inv_w);
+                    ba[ch] = lds_byte(valid[ch] ? R + ((uint32_t)k[ch] >> 1) : dummy_w);
+                    val[ch] = 1u << ((k[ch] & 1) << 4);
+                }
+                lds_add_rtn<kChunks>(ba, val, old);
+                bool hot[kChunks];
+                bool any = false;
+#pragma unroll
+                for (int ch = 0; ch < kChunks; ++ch) {
+                    hot[ch] = valid[ch] && ((old[ch] >> ((k[ch] & 1) << 4)) & 0xffffu) == tm1;
+                    any = any || hot[ch];
+                }
+                if (__ballot(any) != 0ull) {
+#pragma unroll
+                    for (int ch = 0; ch < kChunks; ++ch) {
+                        if (hot[ch]) {
+                            const int s = atomicAdd(lc, 1);
+                            if (s < cap) lst[s] = (uint32_t)k[ch];
+                        }
+                    }
+                }
+            }
+            for (int x0 = 0; x0 < nx; x0 += 4) {
+                switch (min(4, nx - x0)) {
+                case 1: ring_votes_x<1>(A, xh, x0, nx, n_alive, c, sn, R, dummy_w, lst, lc, cap); break;
+                case 2: ring_votes_x<2>(A, xh, x0, nx, n_alive, c, sn, R, dummy_w, lst, lc, cap); break;
+                case 3: ring_votes_x<3>(A, xh, x0, nx, n_alive, c, sn, R, dummy_w, lst, lc, cap); break;
+                default: ring_votes_x<4>(A, xh, x0, nx, n_alive, c, sn, R, dummy_w, lst, lc, cap); break;
+                }
+            }
+            // every vote of row j is in (a wave's LDS operations are
+            // performed in order)
+            const int n = *lc;
+            if (n > cap && lane == 0) sh.big_ovf = 1;
+            if (A.peak_mode == 0) {
+                const uint16_t *r16 = reinterpret_cast<const uint16_t *>(g_lds + R);
+                for (int x = lane; x < min(n, cap); x += kWave) {
+                    const uint32_t kk = lst[x];
+                    atomicMax(&sh.best, bin_key(r16[kk], (uint32_t)(j * A.n_rho) + kk));
+                }
+            }
+            const int jt = j - 1;
+            if (A.peak_mode == 1 && jt >= r0 && jt < r1) {
+                const int pc = jt % 3, pp = (jt + 2) % 3;
+                const uint32_t Rc = pc == 2 ? ring2 : ring0 + (uint32_t)(pc * hw);
+                const uint32_t Rp = pp == 2 ? ring2 : ring0 + (uint32_t)(pp * hw);
+                ring_test(A, lists + pc * cap, min(rc[pc], cap), Rp, Rc, R, jt, pk, sh);
+            }
+            if (j + 1 < jhi) {
+                // row j - 2 (if any) is done with: its buffer takes row j + 1
+                const int nx3 = (j + 1) % 3;
+                uint2 *q = reinterpret_cast<uint2 *>(g_lds + (nx3 == 2 ? ring2 : ring0 + (uint32_t)(nx3 * hw)));
+                for (int x = lane; x < hw / 2; x += kWave) q[x] = make_uint2(0u, 0u);
+                if (lane == 0) rc[nx3] = 0;
+            }
+        }
+    }
+    // the band's last row when it is the grid's last row (no row below)
+    const int jt = jhi - 1;
+    if (A.peak_mode == 1 && jt >= r0 && jt < r1) {
+        const int pc = jt % 3, pp = (jt + 2) % 3;
+        const uint32_t Rc = pc == 2 ? ring2 : ring0 + (uint32_t)(pc * hw);
+        const uint32_t Rp = pp == 2 ? ring2 : ring0 + (uint32_t)(pp * hw);
+        ring_test(A, lists + pc * cap, min(rc[pc], cap), Rp, Rc, Rc, jt, pk, sh);
+    }
 }
 
 // Orders a large event's npk peak keys (in S.pk) by key: a counting sort on
@@ -1800,7 +2189,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     }
                     __syncthreads();
                     HOUGH_PHASE_MARK(kPhRest);
-                    band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
+                    if (band_ring_ok<NT>(A, n_alive, nx))
+                        band_ring<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
+                    else
+                        band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
                     sync_global();
                     HOUGH_PHASE_MARK(kPhBigSweep);
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
