@@ -51,6 +51,7 @@ __device__ __forceinline__ uint32_t lds_byte(uint32_t w) {
 constexpr int kChunks = 8;  // register-resident hit chunks per wave (512 hits)
 constexpr int kMaxLists = 5;  // row lists of the banded sweep: 2 w + 1 for w <= 2
 constexpr int kClaimBlockW = 8;  // alive-hit words up to which claims are resolved in registers
+constexpr int kSegCounts = 128;  // vote counts T .. T + 127 ordered by order_segments
 
 __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1101,13 +1102,15 @@ __device__ __forceinline__ int ring_off(const FindArgs &A, int nx) {
     return A.hs_off + ((nx * kWave * 8 + 15) & ~15);
 }
 
-// Whether band_ring can run: a 3 x 3 window, 16-bit counts, and room for
-// the third ring row of every wave and row lists of at least 32 bins.
+// Whether band_ring can run: a 3 x 3 window, 16-bit counts, room for the
+// third ring row of every wave and row lists of at least 32 bins, and for
+// order_segments' count tables below the LDS-resident hits.
 template <int NT>
 __device__ __forceinline__ bool band_ring_ok(const FindArgs &A, int n_alive, int nx) {
     constexpr int NW = NT / kWave;
     const int room = A.roll_off + A.roll_bytes - ring_off(A, nx);
-    return A.nms_radius == 1 && n_alive < 65536 && room - NW * (A.pitch / 2) * 4 >= 12 * NW * 32;
+    return A.nms_radius == 1 && n_alive < 65536 && room - NW * (A.pitch / 2) * 4 >= 12 * NW * 32 &&
+           4 * (2 * (n_alive + 1) + NW * kSegCounts) <= A.hs_off;
 }
 
 // Votes of U hit chunks (LDS-resident hits xh, chunks x0 .. x0 + U - 1) into
@@ -1153,24 +1156,49 @@ __device__ __forceinline__ void ring_votes_x(const FindArgs &A, const float2 *xh
 
 // Window test of the bins >= T of row jt (list lst[0, n)) against the
 // 16-bit counts of rows jt - 1, jt, jt + 1 (words Rp, Rc, Rn); a neighbour
-// with a lower flat index (row above, or left) wins ties.
+// with a lower flat index (row above, or left) wins ties. The peaks go to
+// the wave's segment seg[fill[0] ...] in ascending k (the wave's rows come in
+// ascending order, so the segment is in flat-index order; a list of more
+// than 64 bins is first ordered by k into tmp, so that its 64-bin rounds
+// come in k order too); nseg counts the wave's peaks (a full segment keeps
+// counting but stores no more).
 __device__ __forceinline__ void ring_test(const FindArgs &A, const uint32_t *lst, int n, uint32_t Rp, uint32_t Rc,
-                                          uint32_t Rn, int jt, unsigned long long *pk, Shared &sh) {
+                                          uint32_t Rn, int jt, unsigned long long *seg, int segcap, int &nseg,
+                                          uint32_t *tmp) {
     const uint16_t *rp = reinterpret_cast<const uint16_t *>(g_lds + Rp);
     const uint16_t *rc = reinterpret_cast<const uint16_t *>(g_lds + Rc);
     const uint16_t *rn = reinterpret_cast<const uint16_t *>(g_lds + Rn);
     const bool up = jt > 0, dn = jt + 1 < A.n_theta;
-    for (int x = lane_id(); x < n; x += kWave) {
-        const int k = (int)lst[x];
+    if (n > kWave) {
+        // rank of each bin among the row's bins by k (distinct)
+        for (int x = lane_id(); x - lane_id() < n; x += kWave) {
+            const uint32_t kx = x < n ? lst[x] : 0u;
+            int r = 0;
+            for (int y = 0; y < n; ++y) r += lst[y] < kx ? 1 : 0;
+            if (x < n) tmp[r] = kx;
+        }
+        lst = tmp;
+    }
+    for (int x0 = 0; x0 < n; x0 += kWave) {
+        const int x = x0 + lane_id();
+        const bool act = x < n;
+        const int k = act ? (int)lst[x] : 0;
         const bool lf = k > 0, rt = k + 1 < A.n_rho;
         const uint32_t c = rc[k];
         const uint32_t a0 = up && lf ? rp[k - 1] : 0u, a1 = up ? rp[k] : 0u, a2 = up && rt ? rp[k + 1] : 0u;
         const uint32_t b0 = lf ? rc[k - 1] : 0u, b2 = rt ? rc[k + 1] : 0u;
         const uint32_t c0 = dn && lf ? rn[k - 1] : 0u, c1 = dn ? rn[k] : 0u, c2 = dn && rt ? rn[k + 1] : 0u;
-        const bool peak = a0 < c && a1 < c && a2 < c && b0 < c && b2 <= c && c0 <= c && c1 <= c && c2 <= c;
-        if (peak) {
-            const int slot = atomicAdd(&sh.pcnt, 1);
-            if (slot < A.big_pk) pk[slot] = bin_key(c, (uint32_t)(jt * A.n_rho + k));
+        const bool peak = act && a0 < c && a1 < c && a2 < c && b0 < c && b2 <= c && c0 <= c && c1 <= c && c2 <= c;
+        const unsigned long long pm = __ballot(peak);
+        if (pm != 0ull) {
+            // rank of each peak among this round's peaks by k (distinct)
+            int r = 0;
+            for (unsigned long long m = pm; m != 0ull; m &= m - 1ull) {
+                const int kl = __builtin_amdgcn_readlane(k, __ffsll((long long)m) - 1);
+                r += kl < k ? 1 : 0;
+            }
+            if (peak && nseg + r < segcap) seg[nseg + r] = bin_key(c, (uint32_t)(jt * A.n_rho + k));
+            nseg += __popcll(pm);
         }
     }
 }
@@ -1183,8 +1211,10 @@ __device__ __forceinline__ void ring_test(const FindArgs &A, const uint32_t *lst
 // LDS-resident hits. A row's votes append the bins they lift to T to the row's list;
 // once row j is in, the listed bins of row j - 1 are window-tested by reading
 // their eight neighbours' counts directly, and the histogram of row j - 2 is
-// cleared for row j + 1. Same peaks as band_big with w = 1; argmax mode
-// takes the largest key of the listed bins instead.
+// cleared for row j + 1. Same peaks as band_big with w = 1, but wave w
+// writes its peaks to its own segment pk[w * big_pk / NW ...] in flat-index
+// order and leaves their number in rc[3] (rc[4] set: the segment overflowed);
+// argmax mode takes the largest key of the listed bins instead.
 template <int NT>
 __device__ __forceinline__ void band_ring(const FindArgs &A, const float2 *__restrict__ cs, const Lds &L,
                                           const HitRegs &h, const float2 *xh, int nx, int n_alive,
@@ -1217,7 +1247,12 @@ __device__ __forceinline__ void band_ring(const FindArgs &A, const float2 *__res
     const int bw = (A.n_theta + NW - 1) / NW;
     const int r0 = wave * bw;
     const int r1 = min(A.n_theta, r0 + bw);
+    if (lane == 0) {
+        rc[3] = 0;
+        rc[4] = 0;
+    }
     if (r0 >= r1) return;
+    int nseg = 0;
     const int jlo = max(r0 - 1, 0);
     const int jhi = min(r1 + 1, A.n_theta);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1283,7 +1318,8 @@ __device__ __forceinline__ void band_ring(const FindArgs &A, const float2 *__res
                 const int pc = jt % 3, pp = (jt + 2) % 3;
                 const uint32_t Rc = pc == 2 ? ring2 : ring0 + (uint32_t)(pc * hw);
                 const uint32_t Rp = pp == 2 ? ring2 : ring0 + (uint32_t)(pp * hw);
-                ring_test(A, lists + pc * cap, min(rc[pc], cap), Rp, Rc, R, jt, pk, sh);
+                ring_test(A, lists + pc * cap, min(rc[pc], cap), Rp, Rc, R, jt, pk + (size_t)wave * (A.big_pk / NW),
+                          A.big_pk / NW, nseg, lists + pp * cap);
             }
             if (j + 1 < jhi) {
                 // row j - 2 (if any) is done with: its buffer takes row j + 1
@@ -1300,7 +1336,12 @@ __device__ __forceinline__ void band_ring(const FindArgs &A, const float2 *__res
         const int pc = jt % 3, pp = (jt + 2) % 3;
         const uint32_t Rc = pc == 2 ? ring2 : ring0 + (uint32_t)(pc * hw);
         const uint32_t Rp = pp == 2 ? ring2 : ring0 + (uint32_t)(pp * hw);
-        ring_test(A, lists + pc * cap, min(rc[pc], cap), Rp, Rc, Rc, jt, pk, sh);
+        ring_test(A, lists + pc * cap, min(rc[pc], cap), Rp, Rc, Rc, jt, pk + (size_t)wave * (A.big_pk / NW),
+                  A.big_pk / NW, nseg, lists + pp * cap);
+    }
+    if (lane == 0) {
+        rc[3] = nseg;
+        rc[4] = nseg > A.big_pk / NW ? 1 : 0;
     }
 }
 
@@ -1370,6 +1411,99 @@ __device__ __forceinline__ int order_peaks(const FindArgs &A, const Lds &L, cons
     }
     sync_global();
     return npk;
+}
+
+// Orders the peak segments band_ring left (wave w's nseg_w keys at
+// S.pk + w * big_pk / NW, each in flat-index order, so their concatenation in
+// wave order is) into S.srt by key: descending vote count, then ascending
+// flat index. A counting sort on the count that keeps the flat order: each
+// count's run start from the histogram; each wave's place inside a run from
+// the earlier waves' counts of that count. Returns the number of peaks, or
+// -1 when a segment overflowed or a count reaches T + kSegCounts.
+template <int NT>
+__device__ __forceinline__ int order_segments(const FindArgs &A, const Lds &L, const Slot &S, Shared &sh) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    const int segcap = A.big_pk / NW;
+    const int cmax = sh.nalive;
+    int *hist = reinterpret_cast<int *>(L.tile);   // [cmax + 1]
+    int *cur = hist + (cmax + 1);                  // [cmax + 1] run starts
+    int *wh = cur + (cmax + 1);                    // [NW][kSegCounts] counts T .. per wave
+    for (int i = threadIdx.x; i <= cmax; i += NT) hist[i] = 0;
+    for (int i = threadIdx.x; i < NW * kSegCounts; i += NT) wh[i] = 0;
+    if (threadIdx.x == 0) sh.best = 0ull;
+    __syncthreads();
+    // (a full segment's peaks beyond segcap were not stored: the result is
+    // then dropped, and only stored keys are read)
+    int npk = 0;
+    bool ovf = false;
+    for (int w = 0; w < NW; ++w) {
+        npk += min(sh.rollc[w * kMaxLists + 3], segcap);
+        ovf = ovf || sh.rollc[w * kMaxLists + 4] != 0;
+    }
+    const uint32_t T = A.min_votes;
+    {
+        // this wave's segment: totals per count, its own counts, the largest
+        const int n = min(sh.rollc[wave * kMaxLists + 3], segcap);
+        const unsigned long long *seg = S.pk + (size_t)wave * segcap;
+        uint32_t mx = 0u;
+        for (int x = lane; x < n; x += kWave) {
+            const uint32_t c = (uint32_t)(seg[x] >> 32);
+            atomicAdd(&hist[c], 1);
+            if (c - T < (uint32_t)kSegCounts) atomicAdd(&wh[wave * kSegCounts + (int)(c - T)], 1);
+            mx = c > mx ? c : mx;
+        }
+        mx = (uint32_t)wave_max64((unsigned long long)mx);
+        if (lane == 0 && mx != 0u) atomicMax(&sh.best, (unsigned long long)mx);
+    }
+    __syncthreads();
+    // a count beyond the per-wave tables: the caller sorts another way
+    const bool wide = sh.best >= (unsigned long long)(T + kSegCounts);
+    if (wave == 0 && !wide) {
+        // run starts in descending count order
+        int run = 0;
+        for (int top = cmax; top >= 0; top -= kWave) {
+            const int c = top - lane;
+            const int v = c >= 0 ? hist[c] : 0;
+            const int incl = wave_incl_scan(v);
+            if (c >= 0) cur[c] = run + incl - v;
+            run += __builtin_amdgcn_readlane(incl, kWave - 1);
+        }
+    }
+    __syncthreads();
+    // wave w's cursor for count T + r: the run start plus the earlier waves'
+    // peaks of that count
+    for (int r = threadIdx.x; r < kSegCounts && !wide; r += NT) {
+        int off = (uint32_t)(T + r) <= (uint32_t)cmax ? cur[T + r] : 0;
+        for (int w = 0; w < NW; ++w) {
+            const int v = wh[w * kSegCounts + r];
+            wh[w * kSegCounts + r] = off;
+            off += v;
+        }
+    }
+    __syncthreads();
+    {
+        const int n = wide ? 0 : min(sh.rollc[wave * kMaxLists + 3], segcap);
+        const unsigned long long *seg = S.pk + (size_t)wave * segcap;
+        for (int x0 = 0; x0 < n; x0 += kWave) {
+            const bool v = x0 + lane < n;
+            const unsigned long long key = v ? seg[x0 + lane] : 0ull;
+            const uint32_t c = (uint32_t)(key >> 32);
+            unsigned long long rem = __ballot(v);
+            while (rem != 0ull) {
+                const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)c, __ffsll((long long)rem) - 1);
+                const unsigned long long m = __ballot(v && c == c0);
+                int *cp = &wh[wave * kSegCounts + (int)(c0 - T)];
+                const int base = *cp;
+                if (v && c == c0) S.srt[base + mbcnt64(m)] = key;
+                if (lane == 0) *cp = base + __popcll(m);
+                rem &= ~m;
+            }
+        }
+    }
+    sync_global();
+    return ovf || wide ? -1 : npk;
 }
 
 // One pass of the histogram over all theta rows for the current alive list.
@@ -2189,7 +2323,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     }
                     __syncthreads();
                     HOUGH_PHASE_MARK(kPhRest);
-                    if (band_ring_ok<NT>(A, n_alive, nx))
+                    const bool ring = band_ring_ok<NT>(A, n_alive, nx);
+                    if (ring)
                         band_ring<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
                     else
                         band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
@@ -2204,6 +2339,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             if (threadIdx.x == 0) S.srt[0] = best;
                             sync_global();
                             npk = best != 0ull ? 1 : 0;
+                        } else if (ring) {
+                            npk = order_segments<NT>(A, L, S, sh);
                         } else if (sh.pcnt <= A.big_pk) {
                             npk = order_peaks<NT>(A, L, S, sh.pcnt, sh);
                         }
