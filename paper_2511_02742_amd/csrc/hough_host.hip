@@ -462,7 +462,7 @@ hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
 hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
                           const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
                           hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed,
-                          bool longest_first, bool total_is_bound) {
+                          bool longest_first, bool total_is_bound, bool ws_only) {
     hough::FindArgs a = find_args(c, w);
     a.n_events = n_events;
     a.n_total = n_total;
@@ -471,7 +471,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     a.z = z;
     a.vane = vane;
     a.max_iters = max_iters;
-    const bool single = n_events == 1;
+    const bool single = n_events == 1 && !ws_only;
     if (single) {
         a.counts = counts;
         a.cand_ws = cand;
@@ -508,7 +508,7 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         (void)hipEventRecord(e1, s);
         c.ev_pairs.emplace_back(e0, e1);
     }
-    if (single) return HOUGH_OK;
+    if (single || ws_only) return HOUGH_OK;
     hough::CompactArgs ca{};
     ca.n_events = n_events;
     ca.n_total = n_total;

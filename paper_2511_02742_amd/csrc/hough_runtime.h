@@ -113,11 +113,15 @@ void free_workspace(Workspace &w);
 // as in hough_find. With longest_first, a call of many events runs its
 // longest events first (an ordering kernel ahead of the finder). With
 // total_is_bound, n_total only bounds offsets[n_events] (offsets written on
-// the device, as the time-sliced finder's window events are).
+// the device, as the time-sliced finder's window events are). With
+// ws_only, the call stops after the finder: every event's candidates and
+// hit lists stay in w (cand_ws at offsets[e] / T, hits_ws at offsets[e],
+// ev_ncand, and the status in w.err, which the caller clears), a one-event
+// call included; cand, hit_index and counts are not used.
 hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events, int64_t n_total,
                           const int64_t *offsets, const float *z, const int16_t *vane, int32_t max_iters,
                           hough_candidate *cand, int32_t *hit_index, int64_t *counts, bool timed,
-                          bool longest_first, bool total_is_bound = false);
+                          bool longest_first, bool total_is_bound = false, bool ws_only = false);
 
 }  // namespace rt
 }  // namespace hough

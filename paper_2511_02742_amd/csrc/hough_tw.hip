@@ -5,16 +5,18 @@
 //
 // Layout: a batch of independent timelines (CSR offsets over time-sorted
 // hits). Windows are processed in order; every step works on window w of
-// all timelines at once:
-//   k_tw_carry    one wave per timeline: continues the tracks flagged in
-//                 window w - 1, in track order;
-//   k_tw_count / k_tw_scan / k_tw_scatter
-//                 the unused hits of window w of every timeline, compacted
-//                 into one event per timeline (CSR built on the device);
-//   the batched Hough finder on those events (the library's own kernels);
-//   k_tw_seed     one wave per timeline: each candidate, in emission order,
-//                 seeds a track from three of its unused hits on consecutive
-//                 vanes, which is then extended at both ends.
+// all timelines at once, in three launches:
+//   k_tw_step     one wave per timeline: the seeds of window w - 1 (each
+//                 Hough candidate of that window, in emission order, seeds a
+//                 track from three of its unused hits on consecutive vanes,
+//                 which is then extended at both ends); the continuation of
+//                 the tracks flagged in window w - 1, in track order; the
+//                 unused hits of window w counted, and the last workgroup to
+//                 finish turns the counts into the window events' offsets;
+//   k_tw_scatter  those hits compacted into one event per timeline;
+//   the Hough finder on those events (the library's own kernel), its
+//                 candidates and hit lists left in its workspace, where the
+//                 next step's seeds read them.
 // A track's hits are a doubly linked list over the hit arrays (the hit on
 // the next and on the previous vane); tracks are written out at the end.
 // An extension step scans the window's hits (a contiguous range of the
@@ -63,9 +65,15 @@ struct TwArgs {
     float *wz;
     int16_t *wv;
     int32_t *widx;                   // global hit index of each window-event hit
-    const hough_candidate *wcand;
-    const int32_t *whits;
-    const int64_t *wcounts;
+    int32_t *ticket;                 // workgroups of k_tw_step done with window w
+    // the finder's workspace: event e's candidates at fcand[woff[e] / T],
+    // ev_ncand[e] of them, hit lists (event-local indices) at fhits[woff[e]],
+    // and its status words
+    const hough_candidate *fcand;
+    const int32_t *fhits;
+    const int32_t *fncand;
+    long long *ferr;
+    uint32_t min_votes;
     long long *err;                  // [status (min), first bad global hit (min)]
     // outputs
     hough_track *tracks;
@@ -188,6 +196,7 @@ __global__ void k_tw_init(TwArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         A.err[0] = 0;
         A.err[1] = LLONG_MAX;
+        *A.ticket = 0;
     }
 }
 
@@ -213,12 +222,12 @@ __global__ __launch_bounds__(256) void k_tw_validate(TwArgs A) {
     }
 }
 
-// Continues the tracks flagged in the previous window (one wave per timeline).
-__global__ __launch_bounds__(64) void k_tw_carry(TwArgs A) {
+// Continues the tracks flagged in window w - 1 into window w (one wave per
+// timeline).
+__device__ void tw_carry(const TwArgs &A, int b, int w) {
     if (A.err[0] != 0) return;
-    const int b = blockIdx.x;
     const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, A.w), hi = lo + A.window_ns, next_lo = window_lo(A, A.w + 1);
+    const float lo = window_lo(A, w), hi = lo + A.window_ns, next_lo = window_lo(A, w + 1);
     int64_t wa, we;
     window_range(A, base, n, lo, hi, &wa, &we);
     const int64_t s0 = slot0(A, b, base);
@@ -237,7 +246,7 @@ __global__ __launch_bounds__(64) void k_tw_carry(TwArgs A) {
             if (lane() == 0) {
                 if (gained > 0) {
                     A.carried[k] += 1;
-                    A.last_win[k] = A.w;
+                    A.last_win[k] = w;
                     A.tl_carry[b] += 1;
                 }
                 A.flag[k] = (gained > 0 && A.tmax[k] >= next_lo) ? 1 : 0;
@@ -249,49 +258,33 @@ __global__ __launch_bounds__(64) void k_tw_carry(TwArgs A) {
     if (lane() == 0) A.carry_lo[b] = first_flagged < 0 ? ntr : first_flagged;
 }
 
-__global__ __launch_bounds__(256) void k_tw_count(TwArgs A) {
-    const int b = blockIdx.x;
-    if (A.err[0] != 0) {
-        if (threadIdx.x == 0) A.wcnt[b] = 0;
-        return;
-    }
+// The unused hits of window w of timeline b (one wave).
+__device__ int32_t tw_count(const TwArgs &A, int b, int w) {
+    if (A.err[0] != 0) return 0;
     const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, A.w), hi = lo + A.window_ns;
+    const float lo = window_lo(A, w), hi = lo + A.window_ns;
     int64_t wa, we;
     window_range(A, base, n, lo, hi, &wa, &we);
-    __shared__ int s_cnt;
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    int c = 0;
-    for (int64_t h = wa + threadIdx.x; h < we; h += blockDim.x) c += A.used[h] < 0 ? 1 : 0;
-    atomicAdd(&s_cnt, c);
-    __syncthreads();
-    if (threadIdx.x == 0) A.wcnt[b] = s_cnt;
+    int64_t c = 0;
+    for (int64_t h = wa + lane(); h < we; h += 64) c += A.used[h] < 0 ? 1 : 0;
+    return (int32_t)wave_sum_i64(c);
 }
 
-// Exclusive prefix sums of the window events' sizes (one block).
-__global__ __launch_bounds__(1024) void k_tw_scan(TwArgs A) {
-    __shared__ int64_t part[1024];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int32_t b0 = 0; b0 < A.n_tl; b0 += 1024) {
-        const int32_t b = b0 + threadIdx.x;
+// Exclusive prefix sums of the window events' sizes into woff (one wave).
+__device__ void tw_offsets(const TwArgs &A) {
+    int64_t carry = 0;
+    for (int32_t b0 = 0; b0 < A.n_tl; b0 += 64) {
+        const int32_t b = b0 + lane();
         const int64_t v = b < A.n_tl ? A.wcnt[b] : 0;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const int64_t add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
+        int64_t incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t u = __shfl_up(incl, o, 64);
+            if (lane() >= o) incl += u;
         }
-        if (b < A.n_tl) A.woff[b] = carry + part[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
-        __syncthreads();
+        if (b < A.n_tl) A.woff[b] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
     }
-    if (threadIdx.x == 0) A.woff[A.n_tl] = carry;
+    if (lane() == 0) A.woff[A.n_tl] = carry;
 }
 
 // The window's unused hits, in hit order, as window event b.
@@ -300,6 +293,7 @@ __global__ __launch_bounds__(64) void k_tw_scatter(TwArgs A) {
     const int b = blockIdx.x;
     const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
     const float lo = window_lo(A, A.w), hi = lo + A.window_ns;
+    // (the offsets of this step's events are complete: k_tw_step ended)
     int64_t wa, we;
     window_range(A, base, n, lo, hi, &wa, &we);
     int64_t out = A.woff[b];
@@ -317,48 +311,33 @@ __global__ __launch_bounds__(64) void k_tw_scatter(TwArgs A) {
     }
 }
 
-// Seeds and extends a track from each Hough candidate of window event b, in
-// emission order.
-__global__ __launch_bounds__(64) void k_tw_seed(TwArgs A) {
+// Seeds and extends a track from each Hough candidate of window event b
+// (window w), in emission order.
+__device__ void tw_seed(const TwArgs &A, int b, int w) {
     __shared__ int32_t first[kTwVaneMax];
-    const int b = blockIdx.x;
-    const long long fst = A.wcounts[HOUGH_COUNT_STATUS];
+    const long long fst = A.ferr[0];
     if (fst != 0) {
         if (threadIdx.x == 0) atomicMin(&A.err[0], fst);
         return;
     }
     if (A.err[0] != 0) return;
     const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, A.w), hi = lo + A.window_ns, next_lo = window_lo(A, A.w + 1);
+    const float lo = window_lo(A, w), hi = lo + A.window_ns, next_lo = window_lo(A, w + 1);
     int64_t wa, we;
     window_range(A, base, n, lo, hi, &wa, &we);
-    // this event's candidates: a contiguous run of the dense output
-    const int64_t nc = A.wcounts[HOUGH_COUNT_CANDIDATES];
-    int64_t c0 = 0, c1 = nc;
-    {
-        int64_t l = 0, h = nc;
-        while (l < h) {
-            const int64_t m = l + (h - l) / 2;
-            if (A.wcand[m].event >= b) h = m; else l = m + 1;
-        }
-        c0 = l;
-        h = nc;
-        while (l < h) {
-            const int64_t m = l + (h - l) / 2;
-            if (A.wcand[m].event >= b + 1) h = m; else l = m + 1;
-        }
-        c1 = l;
-    }
-    if (lane() == 0) A.tl_cand[b] += c1 - c0;
+    // this event's candidates, in the finder's workspace
     const int64_t wbase = A.woff[b];
+    const hough_candidate *cb = A.fcand + wbase / (int64_t)A.min_votes;
+    const int64_t nc = A.fncand[b];
+    if (lane() == 0) A.tl_cand[b] += nc;
     const int64_t s0 = slot0(A, b, base);
     const int nv = A.n_vanes;
-    for (int64_t ci = c0; ci < c1; ++ci) {
-        const hough_candidate cd = A.wcand[ci];
+    for (int64_t ci = 0; ci < nc; ++ci) {
+        const hough_candidate cd = cb[ci];
         for (int v = lane(); v < nv; v += 64) first[v] = INT_MAX;
         __syncthreads();
         for (uint32_t q = lane(); q < cd.n_hits; q += 64) {
-            const int32_t h = A.widx[wbase + A.whits[cd.hit_offset + q]];
+            const int32_t h = A.widx[wbase + A.fhits[wbase + cd.hit_offset + q]];
             if (A.used[h] < 0) atomicMin(&first[A.vane[h]], (int32_t)(h - base));
         }
         __syncthreads();
@@ -394,8 +373,8 @@ __global__ __launch_bounds__(64) void k_tw_seed(TwArgs A) {
             A.end_down[k] = ha;
             A.end_up[k] = hc;
             A.nh[k] = 3;
-            A.win[k] = A.w;
-            A.last_win[k] = A.w;
+            A.win[k] = w;
+            A.last_win[k] = w;
             A.carried[k] = 0;
             A.tb[k] = cd.theta_bin;
             A.rb[k] = cd.rho_bin;
@@ -410,6 +389,30 @@ __global__ __launch_bounds__(64) void k_tw_seed(TwArgs A) {
         tw_extend(A, base, wa, we, k, kid, -1);
         if (lane() == 0) A.flag[k] = A.tmax[k] >= next_lo ? 1 : 0;
         __syncthreads();
+    }
+}
+
+// One step of the window loop for timeline b (one wave): the seeds of
+// window A.w - 1 (from the finder's output of the previous step), then, for
+// A.w < n_windows, the continuation into window A.w and its unused hits.
+// Every workgroup takes a ticket once it is done (after a device-scope
+// fence); the last one, which therefore sees every count and follows every
+// read of the previous offsets, writes the offsets of window A.w's events.
+__global__ __launch_bounds__(64) void k_tw_step(TwArgs A) {
+    const int b = blockIdx.x;
+    if (A.w > 0) tw_seed(A, b, A.w - 1);
+    if (A.w >= A.n_windows) return;
+    tw_carry(A, b, A.w);
+    const int32_t cnt = tw_count(A, b, A.w);
+    if (lane() == 0) A.wcnt[b] = cnt;
+    __shared__ int s_last;
+    __threadfence();
+    if (threadIdx.x == 0) s_last = atomicAdd(A.ticket, 1) == (int)gridDim.x - 1 ? 1 : 0;
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        tw_offsets(A);
+        if (lane() == 0) *A.ticket = 0;
     }
 }
 
@@ -469,6 +472,9 @@ __global__ __launch_bounds__(1024) void k_tw_out_scan(TwArgs A) {
         A.counts[HOUGH_TW_COUNT_CANDIDATES] = ccand;
         A.counts[HOUGH_TW_COUNT_CONTINUED] = ccarry;
         for (int i = HOUGH_TW_COUNT_CONTINUED + 1; i < HOUGH_COUNTS; ++i) A.counts[i] = 0;
+        // leave the finder's error words cleared for the next call
+        A.ferr[0] = 0;
+        A.ferr[1] = LLONG_MAX;
     }
 }
 
@@ -562,17 +568,15 @@ hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *
 
     const int64_t N = n_hits_total, B = n_timelines;
     const int64_t nslots = N / 3 + B + 1;
-    const int64_t ncand = N / (int64_t)c->cfg.min_votes + B + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     const size_t o_used = take(4 * N), o_up = take(4 * N), o_down = take(4 * N), o_widx = take(4 * N);
-    const size_t o_wz = take(4 * N), o_wv = take(2 * N), o_whits = take(4 * N);
+    const size_t o_wz = take(4 * N), o_wv = take(2 * N);
     const size_t o_ntr = take(4 * B), o_clo = take(4 * B), o_wcnt = take(4 * B), o_woff = take(8 * (B + 1));
     const size_t o_tlc = take(8 * B), o_tlk = take(8 * B), o_tlh = take(8 * B), o_tlt = take(8 * B),
                  o_tlhb = take(8 * B);
     const size_t o_slots = take(40 * (size_t)nslots);
-    const size_t o_wcand = take(sizeof(hough_candidate) * (size_t)ncand), o_wcnts = take(8 * HOUGH_COUNTS),
-                 o_err = take(8 * 4);
+    const size_t o_err = take(8 * 4), o_ticket = take(4);
     if (off > c->tw_bytes) {
         if (c->tw_base) {
             if (hipStreamSynchronize(s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipStreamSynchronize failed");
@@ -611,8 +615,6 @@ hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *
     A.widx = reinterpret_cast<int32_t *>(base + o_widx);
     A.wz = reinterpret_cast<float *>(base + o_wz);
     A.wv = reinterpret_cast<int16_t *>(base + o_wv);
-    int32_t *whits = reinterpret_cast<int32_t *>(base + o_whits);
-    A.whits = whits;
     A.ntr = reinterpret_cast<int32_t *>(base + o_ntr);
     A.carry_lo = reinterpret_cast<int32_t *>(base + o_clo);
     A.wcnt = reinterpret_cast<int32_t *>(base + o_wcnt);
@@ -633,11 +635,13 @@ hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *
     A.tb = sl + 7 * nslots;
     A.rb = sl + 8 * nslots;
     A.tmax = reinterpret_cast<float *>(sl + 9 * nslots);
-    hough_candidate *wcand = reinterpret_cast<hough_candidate *>(base + o_wcand);
-    A.wcand = wcand;
-    int64_t *wcounts = reinterpret_cast<int64_t *>(base + o_wcnts);
-    A.wcounts = wcounts;
     A.err = reinterpret_cast<long long *>(base + o_err);
+    A.ticket = reinterpret_cast<int32_t *>(base + o_ticket);
+    A.fcand = c->ws.cand_ws;
+    A.fhits = c->ws.hits_ws;
+    A.fncand = c->ws.ev_ncand;
+    A.ferr = c->ws.err;
+    A.min_votes = c->cfg.min_votes;
     A.tracks = tracks;
     A.hit_index = hit_index;
     A.counts = counts;
@@ -657,21 +661,17 @@ hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *
     if (B > 0) {
         hipLaunchKernelGGL(k_tw_validate, dim3((unsigned)B), dim3(256), 0, s, A);
         if ((st = launched("k_tw_validate"))) return st;
-        for (int32_t w = 0; w < n_windows; ++w) {
+        for (int32_t w = 0; w <= n_windows; ++w) {
+            // seeds of window w - 1; continuation into window w and its events
             A.w = w;
-            hipLaunchKernelGGL(k_tw_carry, dim3((unsigned)B), dim3(64), 0, s, A);
-            if ((st = launched("k_tw_carry"))) return st;
-            hipLaunchKernelGGL(k_tw_count, dim3((unsigned)B), dim3(256), 0, s, A);
-            if ((st = launched("k_tw_count"))) return st;
-            hipLaunchKernelGGL(k_tw_scan, dim3(1), dim3(1024), 0, s, A);
-            if ((st = launched("k_tw_scan"))) return st;
+            hipLaunchKernelGGL(k_tw_step, dim3((unsigned)B), dim3(64), 0, s, A);
+            if ((st = launched("k_tw_step"))) return st;
+            if (w == n_windows) break;
             hipLaunchKernelGGL(k_tw_scatter, dim3((unsigned)B), dim3(64), 0, s, A);
             if ((st = launched("k_tw_scatter"))) return st;
-            st = enqueue_find(*c, c->ws, s, (int32_t)B, N, A.woff, A.wz, A.wv, c->cfg.max_iters, wcand, whits,
-                              wcounts, false, true, true);
+            st = enqueue_find(*c, c->ws, s, (int32_t)B, N, A.woff, A.wz, A.wv, c->cfg.max_iters, nullptr, nullptr,
+                              nullptr, false, true, true, true);
             if (st) return st;
-            hipLaunchKernelGGL(k_tw_seed, dim3((unsigned)B), dim3(64), 0, s, A);
-            if ((st = launched("k_tw_seed"))) return st;
         }
         hipLaunchKernelGGL(k_tw_tl_hits, dim3((unsigned)B), dim3(64), 0, s, A);
         if ((st = launched("k_tw_tl_hits"))) return st;
