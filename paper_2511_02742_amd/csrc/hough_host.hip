@@ -74,6 +74,7 @@ constexpr int kOrderMin = 64;           // calls of more events than this (and t
 constexpr int kSingleSweepGroups = 32;
 constexpr int kSingleSweepThreads = 256;
 constexpr int kSmallCall = 8;
+constexpr int64_t kRegisterHits = 512;    // alive hits the finder holds in registers
 }  // namespace
 thread_local std::string g_last_global_error;
 
@@ -284,6 +285,15 @@ hough_status choose_shape(Ctx &c, std::string &why) {
         if (sl + kStaticLds <= lds_max && hough::set_sweep_lds_limit(kSingleSweepThreads, sl) == hipSuccess)
             c.single_split = 1;
     }
+    // a few events' large-event first sweeps over one workgroup per finder
+    // wave (k_band holds every hit the finder's large path takes in LDS)
+    c.band_split = 0;
+    if (c.single_split && c.big_ok && g.peak_mode == 1 && g.nms_radius == 1) {
+        const int max_hits = 512 + std::min(c.hs_cap & ~63, 56 * 64);
+        c.band_lds = hough::band_lds_bytes(c.pitch, max_hits);
+        if (c.band_lds + kStaticLds <= lds_max && hough::set_band_lds_limit(c.band_lds) == hipSuccess)
+            c.band_split = 1;
+    }
     int drows = std::min(g.n_theta, std::max(1, (lds_max - kStaticLds) / row_bytes));
     c.dump_rows = std::min(drows, 64);
     c.dump_lds = c.dump_rows * row_bytes;
@@ -337,7 +347,8 @@ size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, ch
     // device at once, hold one at a time
     const int32_t slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ne, std::max(c.max_resident, 1)));
     const int64_t slot_bytes = (int64_t)align256(8 * 2 * (size_t)big_pk);
-    const size_t o_pflags = take(4 * (size_t)slots);
+    const size_t o_pflags = take(4 * ((size_t)slots + 2 * kSmallCall));
+    const size_t o_bcnt = take(4 * (size_t)kSmallCall * 16);
     const size_t o_pool = take((size_t)slots * (size_t)slot_bytes);
     if (base != nullptr) {
         w->base = base;
@@ -362,6 +373,10 @@ size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, ch
         w->order = reinterpret_cast<int32_t *>(base + o_order);
         w->g_hs = ghs_events > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
         w->pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
+        w->b_ok = w->pool_flags + slots;
+        w->b_slot = w->b_ok + kSmallCall;
+        w->b_cnt = reinterpret_cast<int32_t *>(base + o_bcnt);
+        w->pool_words = slots + 2 * kSmallCall;
         w->pool = reinterpret_cast<unsigned char *>(base + o_pool);
         w->pool_slots = slots;
         w->slot_bytes = slot_bytes;
@@ -391,7 +406,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
     layout_workspace(c, nh, ne, c.big_pk, static_cast<char *>(p), &w);
     // error and split-sweep words start cleared; every call
     // leaves them so
-    if (hough::launch_clear_workspace(w.err, w.g_cnt, w.g_flag, ne, w.pool_flags, w.pool_slots, s) != hipSuccess)
+    if (hough::launch_clear_workspace(w.err, w.g_cnt, w.g_flag, ne, w.pool_flags, w.pool_words, s) != hipSuccess)
         return HOUGH_ERR_DEVICE;
     return HOUGH_OK;
 }
@@ -479,9 +494,25 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     }
     if (n_events > 0 && n_events <= kSmallCall && c.single_split && a.g_hs == nullptr) {
         // a few events: each one's first sweep spread over several workgroups
-        a.g_hs = w.g_hs;
-        hipError_t ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
-        if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
+        // (the sweep kernel takes events of up to 512 hits, the register
+        // batch; a lone larger event skips it)
+        hipError_t ss = hipSuccess;
+        if (!(n_events == 1 && n_total > kRegisterHits && !total_is_bound)) {
+            a.g_hs = w.g_hs;
+            ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
+            if (ss != hipSuccess)
+                return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
+        }
+        if (c.band_split && w.pool_slots > n_events && n_total > kRegisterHits) {
+            // and a large one's first banded sweep over one workgroup per
+            // finder wave (slot e of the pool reserved for event e)
+            a.b_ok = w.b_ok;
+            a.b_slot = w.b_slot;
+            a.b_cnt = w.b_cnt;
+            a.b_events = n_events;
+            ss = hough::launch_band(a, c.wg_threads / 64, c.band_lds, s);
+            if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("band launch failed: ") + hipGetErrorString(ss));
+        }
     } else if (a.g_hs != nullptr && n_events > 0) {
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
@@ -715,7 +746,7 @@ hough_status hough_find_noalloc(hough_ctx *ctx, void *stream, int32_t n_events, 
     layout_workspace(*c, nh, ne, kNoAllocBigPk, base, &w);
     // the scratch holds whatever the last call left there: clear the words
     // the finder expects at zero
-    if (hough::launch_clear_workspace(w.err, w.g_cnt, w.g_flag, ne, w.pool_flags, w.pool_slots, s) != hipSuccess)
+    if (hough::launch_clear_workspace(w.err, w.g_cnt, w.g_flag, ne, w.pool_flags, w.pool_words, s) != hipSuccess)
         return fail(c, HOUGH_ERR_DEVICE, "workspace clearing launch failed");
     st = enqueue_find(*c, w, s, n_events, n_hits_total, event_offsets, z, vane, c->cfg.max_iters, cand, hit_index,
                       counts, false, true);

@@ -102,6 +102,12 @@ struct FindArgs {
     // clock when the event's finder workgroup started, ev_clock[2 e + 1] when
     // it had written its last output; NULL = not recorded
     unsigned long long *ev_clock;
+    // first banded sweep of a small call's large events done ahead by
+    // k_band (NULL = not run): b_ok[e] workgroups finished event e's band,
+    // b_slot[e] = 1 + the pool slot k_band reserved for it (0 = none),
+    // b_cnt[e * NW + w] the peaks of the finder wave w's rows
+    int32_t *b_ok, *b_slot, *b_cnt;
+    int32_t b_events;
 };
 
 // Records the event's start and retire clock stamps when the call asked for
@@ -146,6 +152,12 @@ struct CompactArgs {
 // Kernel launchers (hough_kernels.hip). Each returns the launch status.
 hipError_t launch_find(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t s);
+// k_band over a small call's events: nwf workgroups of kBandThreads per
+// event (nwf = the finder's waves), band_lds bytes of LDS
+constexpr int kBandThreads = 256;
+hipError_t launch_band(const FindArgs &a, int nwf, int band_lds, hipStream_t s);
+hipError_t set_band_lds_limit(int lds_bytes);
+int band_lds_bytes(int pitch, int max_hits);
 hipError_t set_sweep_lds_limit(int threads, int lds_bytes);
 int sweep_lds_bytes(int threads, int pitch);
 // Clears the error words, the split-sweep counters and flags of n_events

@@ -355,6 +355,8 @@ struct Shared {
     int rcnt[2];     // open peaks of the current and the next claim round
     int big_ovf;     // a large-event sweep lost a bin >= T (row list full)
     int slot;        // device-memory slot of a large event, or -1
+    int pre;         // k_band workgroups that finished the event's first banded sweep
+    int rslot;       // the slot k_band reserved for the event, or -1
     int nruns;       // runs of equal counts in a large event's peak list
     int rollc[16 * kMaxLists];  // fill of each wave's row lists (banded sweep)
     int rlive;       // live bins the last recount tested
@@ -1105,12 +1107,15 @@ __device__ __forceinline__ int ring_off(const FindArgs &A, int nx) {
 // Whether band_ring can run: a 3 x 3 window, 16-bit counts, room for the
 // third ring row of every wave and row lists of at least 32 bins, and for
 // order_segments' count tables below the LDS-resident hits.
-template <int NT>
-__device__ __forceinline__ bool band_ring_ok(const FindArgs &A, int n_alive, int nx) {
-    constexpr int NW = NT / kWave;
+__device__ __forceinline__ bool band_ring_ok_nw(const FindArgs &A, int n_alive, int nx, int NW) {
     const int room = A.roll_off + A.roll_bytes - ring_off(A, nx);
     return A.nms_radius == 1 && n_alive < 65536 && room - NW * (A.pitch / 2) * 4 >= 12 * NW * 32 &&
            4 * (2 * (n_alive + 1) + NW * kSegCounts) <= A.hs_off;
+}
+
+template <int NT>
+__device__ __forceinline__ bool band_ring_ok(const FindArgs &A, int n_alive, int nx) {
+    return band_ring_ok_nw(A, n_alive, nx, NT / kWave);
 }
 
 // Votes of U hit chunks (LDS-resident hits xh, chunks x0 .. x0 + U - 1) into
@@ -2101,9 +2106,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         sh.nhit = 0;
         sh.n_trunc = 0;
         sh.n_hotscan = 0;
+        // the event's first banded sweep, done ahead by k_band, and the slot
+        // it reserved (taken over here, released at the end)
+        sh.pre = 0;
+        sh.rslot = -1;
+        if (A.b_ok != nullptr && e < A.b_events) {
+            sh.pre = A.b_ok[e];
+            sh.rslot = A.b_slot[e] - 1;
+            A.b_ok[e] = 0;
+            A.b_slot[e] = 0;
+            // each finder wave's segment count, as band_ring leaves it
+            if (sh.pre == NW)
+                for (int w = 0; w < NW; ++w) {
+                    sh.rollc[w * kMaxLists + 3] = A.b_cnt[e * NW + w];
+                    sh.rollc[w * kMaxLists + 4] = 0;
+                }
+        }
     }
     __syncthreads();
     if (sh.bad) {
+        release_slot(A, sh.rslot);
         if (threadIdx.x == 0) {
             if (A.g_cnt != nullptr) {
                 A.g_cnt[e] = 0;
@@ -2138,6 +2160,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         A.state[b + i] = -1;
     }
     if (__syncthreads_or(badhit)) {
+        release_slot(A, sh.rslot);
         if (threadIdx.x == 0) {
             if (A.g_cnt != nullptr) {
                 A.g_cnt[e] = 0;
@@ -2308,7 +2331,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 }
             }
             if (safe && big && !done && A.big_ok && 2 * A.nms_radius + 1 <= kMaxLists) {
-                if (slot < 0) slot = acquire_slot(A, sh);
+                if (slot < 0) slot = sh.rslot >= 0 ? sh.rslot : acquire_slot(A, sh);
                 if (slot >= 0) {
                     // a fresh banded sweep every iteration: with thousands
                     // of bins >= T, recounting them costs more than a sweep
@@ -2324,10 +2347,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     __syncthreads();
                     HOUGH_PHASE_MARK(kPhRest);
                     const bool ring = band_ring_ok<NT>(A, n_alive, nx);
-                    if (ring)
+                    if (ring && iter == 0 && sh.pre == NW) {
+                        // k_band swept this band into the slot (the segment
+                        // counts were taken over at the start)
+                    } else if (ring) {
                         band_ring<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
-                    else
+                    } else {
                         band_big<NT>(A, cs, L, h, xh, nx, n_alive, S.pk, sh);
+                    }
                     sync_global();
                     HOUGH_PHASE_MARK(kPhBigSweep);
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
@@ -2407,7 +2434,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         ++iter;
         if (sh.ncand == ncand0) break;
     }
-    release_slot(A, slot);
+    release_slot(A, slot >= 0 ? slot : sh.rslot);
     if (A.g_cnt != nullptr && threadIdx.x == 0) {
         // leave the split-sweep words cleared for the next call
         A.g_cnt[e] = 0;
@@ -2496,6 +2523,156 @@ __global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restri
     if (n < (int)A.min_votes) return;
     stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(NW * A.pitch) + threadIdx.x, h, n,
                     g * NW + wave, groups * NW, A.g_hs + (size_t)e * A.hs_cap, A.g_cnt + e, A.hs_cap);
+}
+
+// First banded sweep of the large events of a small call, spread over nwf
+// workgroups per event: workgroup g sweeps the rows the finder's wave g
+// would (band_ring's partition), with every hit of the event in LDS, in
+// band_ring's 16-bit three-row rings with the direct window test (its waves
+// split the band again; each wave keeps its own rings, lists and peaks).
+// The band's peaks, in flat order, go to segment g of the event's slot (slot
+// e of the pool, reserved here; the finder's workgroup of event e takes it
+// over), their number to b_cnt[e * nwf + g], and each workgroup that
+// succeeds adds 1 to b_ok[e]. An event that the finder will not sweep with
+// band_ring (not large, too large, an invalid or unsafe hit), or a list or
+// segment that overflows, leaves b_ok[e] below nwf: the finder then sweeps
+// the band itself.
+template <int NTB>
+__global__ __launch_bounds__(NTB) void k_band(FindArgs A, const float2 *__restrict__ cs, int nwf) {
+    constexpr int NWB = NTB / kWave;
+    constexpr int kSegW = 512;   // peaks per wave
+    constexpr int kCapB = 128;   // bins >= T per row list
+    const int e = blockIdx.x / nwf;
+    const int g = blockIdx.x - e * nwf;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    const int64_t b = uniform64(A.offsets[e]);
+    const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
+    const int xmax = kChunks * kWave + min(A.hs_cap & ~(kWave - 1), 56 * kWave);
+    if (A.peak_mode != 1 || !A.stream_ok || !A.big_ok || b < 0 || n64 <= kChunks * kWave || n64 > xmax ||
+        b + n64 > A.n_total)
+        return;
+    const int n = (int)n64;
+    if (!band_ring_ok_nw(A, n, (n - kChunks * kWave + kWave - 1) / kWave, nwf)) return;
+    // LDS: the hits | per wave: three 16-bit rows, three row lists, peaks |
+    // a dummy word per lane
+    const int hw = A.pitch / 2;
+    float2 *xy = reinterpret_cast<float2 *>(g_lds);
+    const uint32_t rings = (uint32_t)(((n * 8 + 15) & ~15) / 4);
+    const uint32_t ring0 = rings + (uint32_t)(wave * 3 * hw);
+    uint32_t *lists = g_lds + rings + NWB * 3 * hw + wave * 3 * kCapB;
+    unsigned long long *pk = reinterpret_cast<unsigned long long *>(g_lds + rings + NWB * 3 * hw + NWB * 3 * kCapB) +
+                             wave * kSegW;
+    const uint32_t dummy_w = rings + NWB * 3 * hw + NWB * 3 * kCapB + 2 * NWB * kSegW + threadIdx.x;
+    __shared__ int s_rc[NWB][3];
+    __shared__ int s_n[NWB];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    // the hits (every hit is alive in the first iteration)
+    bool bad = false;
+    for (int i = threadIdx.x; i < n; i += NTB) {
+        const int v = A.vane[b + i];
+        const float zz = A.z[b + i];
+        float ph = 0.0f;
+        if (v < 0 || v >= A.n_vanes || !(fabsf(zz) <= HOUGH_Z_LIMIT))
+            bad = true;
+        else
+            ph = A.phi_v[v];
+        bad = bad || (double)ph * ph + (double)zz * zz > A.safe_r2;
+        xy[i] = make_float2(ph, zz);
+    }
+    if (__syncthreads_or(bad)) return;
+    if (g == 0 && threadIdx.x == 0) {
+        // the slot the finder will take over for this event
+        A.pool_flags[e] = 1;
+        A.b_slot[e] = e + 1;
+    }
+    const int nx = (n + kWave - 1) / kWave;
+    // the finder wave g's rows, split over this workgroup's waves
+    const int bwf = (A.n_theta + nwf - 1) / nwf;
+    const int g0 = g * bwf, g1 = min(A.n_theta, g0 + bwf);
+    const int sb = (max(g1 - g0, 0) + NWB - 1) / NWB;
+    const int r0 = g0 + wave * sb, r1 = min(g1, r0 + sb);
+    const uint32_t tm1 = A.min_votes - 1u;
+    (void)tm1;
+    int *rc = s_rc[wave];
+    int nseg = 0;
+    bool ovf = false;
+    {
+        uint2 *q = reinterpret_cast<uint2 *>(g_lds + ring0);
+        for (int x = lane; x < 3 * hw / 2; x += kWave) q[x] = make_uint2(0u, 0u);
+        if (lane < 3) rc[lane] = 0;
+    }
+    if (r0 < r1) {
+        const int jlo = max(r0 - 1, 0);
+        const int jhi = min(r1 + 1, A.n_theta);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        for (int jb = jlo; jb < jhi; jb += kWave) {
+            const int nr = min(kWave, jhi - jb);
+            const float2 mine = lane < nr ? cs[jb + lane] : make_float2(0.0f, 0.0f);
+            for (int i = 0; i < nr; ++i) {
+                const int j = jb + i;
+                const int cur = j % 3;
+                const uint32_t R = ring0 + (uint32_t)(cur * hw);
+                uint32_t *lst = lists + cur * kCapB;
+                int *lc = &rc[cur];
+                const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.x), i));
+                const float sn = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, mine.y), i));
+                // (ring_votes_x numbers the LDS chunks after 512 register hits)
+                for (int x0 = 0; x0 < nx; x0 += 4) {
+                    switch (min(4, nx - x0)) {
+                    case 1: ring_votes_x<1>(A, xy, x0, nx, n + kChunks * kWave, c, sn, R, dummy_w, lst, lc, kCapB); break;
+                    case 2: ring_votes_x<2>(A, xy, x0, nx, n + kChunks * kWave, c, sn, R, dummy_w, lst, lc, kCapB); break;
+                    case 3: ring_votes_x<3>(A, xy, x0, nx, n + kChunks * kWave, c, sn, R, dummy_w, lst, lc, kCapB); break;
+                    default: ring_votes_x<4>(A, xy, x0, nx, n + kChunks * kWave, c, sn, R, dummy_w, lst, lc, kCapB); break;
+                    }
+                }
+                ovf = ovf || *lc > kCapB;
+                const int jt = j - 1;
+                if (jt >= r0 && jt < r1) {
+                    const int pc = jt % 3, pp = (jt + 2) % 3;
+                    ring_test(A, lists + pc * kCapB, min(rc[pc], kCapB), ring0 + (uint32_t)(pp * hw),
+                              ring0 + (uint32_t)(pc * hw), R, jt, pk, kSegW, nseg, lists + pp * kCapB);
+                }
+                if (j + 1 < jhi) {
+                    const int nx3 = (j + 1) % 3;
+                    uint2 *q = reinterpret_cast<uint2 *>(g_lds + ring0 + (uint32_t)(nx3 * hw));
+                    for (int x = lane; x < hw / 2; x += kWave) q[x] = make_uint2(0u, 0u);
+                    if (lane == 0) rc[nx3] = 0;
+                }
+            }
+        }
+        const int jt = jhi - 1;
+        if (jt >= r0 && jt < r1) {
+            const int pc = jt % 3, pp = (jt + 2) % 3;
+            ring_test(A, lists + pc * kCapB, min(rc[pc], kCapB), ring0 + (uint32_t)(pp * hw),
+                      ring0 + (uint32_t)(pc * hw), ring0 + (uint32_t)(pc * hw), jt, pk, kSegW, nseg,
+                      lists + pp * kCapB);
+        }
+    }
+    if (lane == 0) {
+        s_n[wave] = nseg;
+        if (ovf || nseg > kSegW) s_bad = 1;
+    }
+    __syncthreads();
+    int total = 0, before = 0;
+    for (int w = 0; w < NWB; ++w) {
+        before += w < wave ? s_n[w] : 0;
+        total += s_n[w];
+    }
+    const int segcap = A.big_pk / nwf;
+    if (s_bad || total > segcap) return;
+    // this band's segment of the event's slot: the waves' peaks in order
+    unsigned long long *seg = slot_ptrs(A, e).pk + (size_t)g * segcap;
+    for (int i = lane; i < nseg; i += kWave) seg[before + i] = pk[i];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A.b_cnt[e * nwf + g] = total;
+        __threadfence();
+        atomicAdd(&A.b_ok[e], 1);
+    }
 }
 
 __global__ void k_set_offsets(int64_t *offsets, int64_t n) {
@@ -2702,6 +2879,24 @@ hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t 
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+int band_lds_bytes(int pitch, int max_hits) {
+    constexpr int NWB = kBandThreads / kWave;
+    return ((max_hits * 8 + 15) & ~15) + 4 * (NWB * 3 * (pitch / 2)) + 4 * (NWB * 3 * 128) + 8 * (NWB * 512) +
+           4 * kBandThreads;
+}
+
+hipError_t set_band_lds_limit(int lds_bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_band<kBandThreads>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+
+hipError_t launch_band(const FindArgs &a, int nwf, int band_lds, hipStream_t s) {
+    if (a.n_events <= 0 || nwf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band<kBandThreads>, dim3((unsigned)a.n_events * (unsigned)nwf), dim3(kBandThreads),
+                       band_lds, s, a, a.cs, nwf);
     return hipGetLastError();
 }
 

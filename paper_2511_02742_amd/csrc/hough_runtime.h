@@ -37,6 +37,11 @@ struct Workspace {
     unsigned char *pool = nullptr;
     int32_t *pool_flags = nullptr;
     int32_t pool_slots = 0;
+    // first banded sweeps of a small call's large events (k_band): b_ok and
+    // b_slot follow the pool flags (cleared with them: pool_words words in
+    // all), b_cnt holds kSmallCall x 16 segment counts
+    int32_t *b_ok = nullptr, *b_slot = nullptr, *b_cnt = nullptr;
+    int32_t pool_words = 0;
     int64_t slot_bytes = 0;
     int32_t big_pk = 0;        // peak entries per slot list
 };
@@ -60,6 +65,7 @@ struct Ctx {
     int tile_rows = 0, wg_threads = 0, pitch = 0, tile_bytes = 0, lds_bytes = 0;
     int sweep_groups = 0, sweep_threads = 256, hs_cap = 0;
     int single_split = 0;                     // calls of a few events split their first sweeps
+    int band_split = 0, band_lds = 0;         // and their large events' first banded sweeps (k_band)
     int stream_ok = 0, hs_off = 0, sorted_off = 0;
     int big_pk = 0;                           // peak entries per large-event slot
     int big_sort = 0;                         // longest equal-count run sorted in LDS

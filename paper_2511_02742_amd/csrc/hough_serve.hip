@@ -194,7 +194,7 @@ struct Server {
         // the block held another launch's data: clear the words the finder
         // expects at zero
         if (hough::launch_clear_workspace(L.ws.err, L.ws.g_cnt, L.ws.g_flag, L.ws.events, L.ws.pool_flags,
-                                          L.ws.pool_slots, L.stream) != hipSuccess)
+                                          L.ws.pool_words, L.stream) != hipSuccess)
             return HOUGH_ERR_DEVICE;
         // no longest-first ordering here: the lanes' launches overlap on the
         // device, and ordered overlapping launches of thousands of mixed
