@@ -289,6 +289,29 @@ def test_large_events(gpu_available, pileup, n_events):
         assert got1[2]["tiled"] == 0, got1[2]
 
 
+@pytest.mark.parametrize("kw", [{}, {"wg_threads": 512, "tile_rows": 14}, {"wg_threads": 256, "tile_rows": 6}])
+def test_small_call_large_events_mixed(gpu_available, kw):
+    # a call of a few events takes its large events' first banded sweep
+    # ahead of the finder, one workgroup per finder wave, each large event in
+    # its own reserved slot; small events, large events of different sizes
+    # and the last event large, in one call
+    evs = [eventgen.pileup_event(7600, n_tracks=100), eventgen.pileup_event(7601, n_tracks=10),
+           eventgen.pileup_event(7602, n_tracks=150), eventgen.pileup_event(7603, n_tracks=50),
+           eventgen.pileup_event(7604, n_tracks=120)]
+    b = eventgen.make_batch(evs)
+    assert sum(int(n) > 512 for n in np.diff(b.offsets)) == 3
+    got, want = check_batch(b, "small mixed call " + str(kw), **kw)
+    assert got[2]["large"] > 0, got[2]
+    if not kw:
+        assert got[2]["tiled"] == 0, got[2]
+    # the same call twice on one finder: the reserved slots are released
+    f = finder(**kw)
+    first = run_batch(f, b)
+    again = run_batch(f, b)
+    assert_same(again, want, "small mixed call again " + str(kw))
+    assert_same(first, want, "small mixed call first " + str(kw))
+
+
 @pytest.mark.parametrize("kw", [{"sweep_groups": 4}, {"wg_threads": 512}, {"peak_mode": 0, "max_iters": 12},
                                 {"nms_radius": 2}, {"assoc_window": 1}, {"wg_threads": 512, "tile_rows": 14},
                                 {"wg_threads": 256, "tile_rows": 6}])
