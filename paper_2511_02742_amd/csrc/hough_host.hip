@@ -74,6 +74,7 @@ constexpr int kOrderMin = 64;           // calls of more events than this (and t
 constexpr int kSingleSweepGroups = 32;
 constexpr int kSingleSweepThreads = 256;
 constexpr int kSmallCall = 8;
+constexpr int kBandCall = 64;             // calls of up to this many events may run k_band
 constexpr int64_t kRegisterHits = 512;    // alive hits the finder holds in registers
 }  // namespace
 thread_local std::string g_last_global_error;
@@ -347,8 +348,8 @@ size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, ch
     // device at once, hold one at a time
     const int32_t slots = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ne, std::max(c.max_resident, 1)));
     const int64_t slot_bytes = (int64_t)align256(8 * 2 * (size_t)big_pk);
-    const size_t o_pflags = take(4 * ((size_t)slots + 2 * kSmallCall));
-    const size_t o_bcnt = take(4 * (size_t)kSmallCall * 16);
+    const size_t o_pflags = take(4 * ((size_t)slots + 2 * kBandCall));
+    const size_t o_bcnt = take(4 * (size_t)kBandCall * 16);
     const size_t o_pool = take((size_t)slots * (size_t)slot_bytes);
     if (base != nullptr) {
         w->base = base;
@@ -374,9 +375,9 @@ size_t layout_workspace(const Ctx &c, int64_t nh, int64_t ne, int32_t big_pk, ch
         w->g_hs = ghs_events > 0 ? reinterpret_cast<unsigned long long *>(base + o_ghs) : nullptr;
         w->pool_flags = reinterpret_cast<int32_t *>(base + o_pflags);
         w->b_ok = w->pool_flags + slots;
-        w->b_slot = w->b_ok + kSmallCall;
+        w->b_slot = w->b_ok + kBandCall;
         w->b_cnt = reinterpret_cast<int32_t *>(base + o_bcnt);
-        w->pool_words = slots + 2 * kSmallCall;
+        w->pool_words = slots + 2 * kBandCall;
         w->pool = reinterpret_cast<unsigned char *>(base + o_pool);
         w->pool_slots = slots;
         w->slot_bytes = slot_bytes;
@@ -496,26 +497,27 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         // a few events: each one's first sweep spread over several workgroups
         // (the sweep kernel takes events of up to 512 hits, the register
         // batch; a lone larger event skips it)
-        hipError_t ss = hipSuccess;
         if (!(n_events == 1 && n_total > kRegisterHits && !total_is_bound)) {
             a.g_hs = w.g_hs;
-            ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
+            hipError_t ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
             if (ss != hipSuccess)
                 return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
-        }
-        if (c.band_split && w.pool_slots > n_events && n_total > kRegisterHits) {
-            // and a large one's first banded sweep over one workgroup per
-            // finder wave (slot e of the pool reserved for event e)
-            a.b_ok = w.b_ok;
-            a.b_slot = w.b_slot;
-            a.b_cnt = w.b_cnt;
-            a.b_events = n_events;
-            ss = hough::launch_band(a, c.wg_threads / 64, c.band_lds, s);
-            if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("band launch failed: ") + hipGetErrorString(ss));
         }
     } else if (a.g_hs != nullptr && n_events > 0) {
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
+    }
+    if (n_events > 0 && n_events <= kBandCall && c.band_split && c.sweep_groups == 0 && !total_is_bound &&
+        w.pool_slots > 2 * n_events && n_total > kRegisterHits) {
+        // a call of a few tens of events: its large events' first banded
+        // sweeps over one workgroup per finder wave each (slot e of the pool
+        // reserved for large event e)
+        a.b_ok = w.b_ok;
+        a.b_slot = w.b_slot;
+        a.b_cnt = w.b_cnt;
+        a.b_events = n_events;
+        hipError_t sb = hough::launch_band(a, c.wg_threads / 64, c.band_lds, s);
+        if (sb != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("band launch failed: ") + hipGetErrorString(sb));
     }
     if (longest_first && n_events > std::max(c.max_resident, kOrderMin)) {
         // the longest events start first and the short ones fill the CUs at

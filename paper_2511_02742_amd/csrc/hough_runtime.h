@@ -39,7 +39,7 @@ struct Workspace {
     int32_t pool_slots = 0;
     // first banded sweeps of a small call's large events (k_band): b_ok and
     // b_slot follow the pool flags (cleared with them: pool_words words in
-    // all), b_cnt holds kSmallCall x 16 segment counts
+    // all), b_cnt holds 64 x 16 segment counts
     int32_t *b_ok = nullptr, *b_slot = nullptr, *b_cnt = nullptr;
     int32_t pool_words = 0;
     int64_t slot_bytes = 0;
