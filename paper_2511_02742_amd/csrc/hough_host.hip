@@ -508,10 +508,11 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
     if (n_events > 0 && n_events <= kBandCall && c.band_split && c.sweep_groups == 0 && !total_is_bound &&
-        w.pool_slots > 2 * n_events && n_total > kRegisterHits) {
+        w.pool_slots >= n_events && n_total > kRegisterHits) {
         // a call of a few tens of events: its large events' first banded
         // sweeps over one workgroup per finder wave each (slot e of the pool
-        // reserved for large event e)
+        // reserved for large event e; an event k_band does not take finds
+        // at least its own slot free)
         a.b_ok = w.b_ok;
         a.b_slot = w.b_slot;
         a.b_cnt = w.b_cnt;
