@@ -66,6 +66,7 @@ struct TwArgs {
     int16_t *wv;
     int32_t *widx;                   // global hit index of each window-event hit
     int32_t *ticket;                 // workgroups of k_tw_step done with window w
+    int64_t *wr;                     // [2 n_tl] hit range [wa, we) of each timeline's latest window
     // the finder's workspace: event e's candidates at fcand[woff[e] / T],
     // ev_ncand[e] of them, hit lists (event-local indices) at fhits[woff[e]],
     // and its status words
@@ -180,6 +181,35 @@ __device__ void window_range(const TwArgs &A, int64_t base, int64_t n, float lo,
 
 __device__ __forceinline__ float window_lo(const TwArgs &A, int w) { return (float)w * A.step_ns; }
 
+// First index in [from, end) whose time is >= x (times sorted), scanning
+// forward 64 hits at a time: the windows advance by one step, so the next
+// window's bounds lie a few hits past the last ones (one wave).
+__device__ int64_t advance_lb(const float *t, int64_t from, int64_t end, float x) {
+    int64_t p = from;
+    for (;;) {
+        const int64_t i = p + lane();
+        const int c = __popcll(__ballot(i < end && t[i] < x));
+        p += c;
+        if (c < 64) return p;
+    }
+}
+
+// The hit range of window w of timeline b: binary searches for the first
+// window, then advanced from the previous window's range (stored in A.wr).
+__device__ void window_next(const TwArgs &A, int b, int w, int64_t base, int64_t n, int64_t *wa, int64_t *we) {
+    const float lo = window_lo(A, w), hi = lo + A.window_ns;
+    if (w == 0) {
+        window_range(A, base, n, lo, hi, wa, we);
+    } else {
+        *wa = advance_lb(A.t, A.wr[2 * b], base + n, lo);
+        *we = advance_lb(A.t, max(A.wr[2 * b + 1], *wa), base + n, hi);
+    }
+    if (lane() == 0) {
+        A.wr[2 * b] = *wa;
+        A.wr[2 * b + 1] = *we;
+    }
+}
+
 __global__ void k_tw_init(TwArgs A) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A.n_total; i += stride) {
@@ -224,12 +254,10 @@ __global__ __launch_bounds__(256) void k_tw_validate(TwArgs A) {
 
 // Continues the tracks flagged in window w - 1 into window w (one wave per
 // timeline).
-__device__ void tw_carry(const TwArgs &A, int b, int w) {
+__device__ void tw_carry(const TwArgs &A, int b, int w, int64_t wa, int64_t we) {
     if (A.err[0] != 0) return;
-    const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, w), hi = lo + A.window_ns, next_lo = window_lo(A, w + 1);
-    int64_t wa, we;
-    window_range(A, base, n, lo, hi, &wa, &we);
+    const int64_t base = A.offsets[b];
+    const float next_lo = window_lo(A, w + 1);
     const int64_t s0 = slot0(A, b, base);
     const int32_t ntr = A.ntr[b];
     int32_t first_flagged = -1;
@@ -259,12 +287,8 @@ __device__ void tw_carry(const TwArgs &A, int b, int w) {
 }
 
 // The unused hits of window w of timeline b (one wave).
-__device__ int32_t tw_count(const TwArgs &A, int b, int w) {
+__device__ int32_t tw_count(const TwArgs &A, int64_t wa, int64_t we) {
     if (A.err[0] != 0) return 0;
-    const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, w), hi = lo + A.window_ns;
-    int64_t wa, we;
-    window_range(A, base, n, lo, hi, &wa, &we);
     int64_t c = 0;
     for (int64_t h = wa + lane(); h < we; h += 64) c += A.used[h] < 0 ? 1 : 0;
     return (int32_t)wave_sum_i64(c);
@@ -291,11 +315,8 @@ __device__ void tw_offsets(const TwArgs &A) {
 __global__ __launch_bounds__(64) void k_tw_scatter(TwArgs A) {
     if (A.err[0] != 0) return;
     const int b = blockIdx.x;
-    const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, A.w), hi = lo + A.window_ns;
-    // (the offsets of this step's events are complete: k_tw_step ended)
-    int64_t wa, we;
-    window_range(A, base, n, lo, hi, &wa, &we);
+    // this step's window range and event offsets (k_tw_step ended)
+    const int64_t wa = A.wr[2 * b], we = A.wr[2 * b + 1];
     int64_t out = A.woff[b];
     for (int64_t h0 = wa; h0 < we; h0 += 64) {
         const int64_t h = h0 + lane();
@@ -313,7 +334,7 @@ __global__ __launch_bounds__(64) void k_tw_scatter(TwArgs A) {
 
 // Seeds and extends a track from each Hough candidate of window event b
 // (window w), in emission order.
-__device__ void tw_seed(const TwArgs &A, int b, int w) {
+__device__ void tw_seed(const TwArgs &A, int b, int w, int64_t wa, int64_t we) {
     __shared__ int32_t first[kTwVaneMax];
     const long long fst = A.ferr[0];
     if (fst != 0) {
@@ -321,10 +342,8 @@ __device__ void tw_seed(const TwArgs &A, int b, int w) {
         return;
     }
     if (A.err[0] != 0) return;
-    const int64_t base = A.offsets[b], n = A.offsets[b + 1] - base;
-    const float lo = window_lo(A, w), hi = lo + A.window_ns, next_lo = window_lo(A, w + 1);
-    int64_t wa, we;
-    window_range(A, base, n, lo, hi, &wa, &we);
+    const int64_t base = A.offsets[b];
+    const float next_lo = window_lo(A, w + 1);
     // this event's candidates, in the finder's workspace
     const int64_t wbase = A.woff[b];
     const hough_candidate *cb = A.fcand + wbase / (int64_t)A.min_votes;
@@ -400,10 +419,15 @@ __device__ void tw_seed(const TwArgs &A, int b, int w) {
 // read of the previous offsets, writes the offsets of window A.w's events.
 __global__ __launch_bounds__(64) void k_tw_step(TwArgs A) {
     const int b = blockIdx.x;
-    if (A.w > 0) tw_seed(A, b, A.w - 1);
+    if (A.w > 0) tw_seed(A, b, A.w - 1, A.wr[2 * b], A.wr[2 * b + 1]);
     if (A.w >= A.n_windows) return;
-    tw_carry(A, b, A.w);
-    const int32_t cnt = tw_count(A, b, A.w);
+    int64_t wa = 0, we = 0;
+    if (__builtin_amdgcn_readfirstlane(A.err[0] == 0 ? 1 : 0)) {
+        const int64_t base = A.offsets[b];
+        window_next(A, b, A.w, base, A.offsets[b + 1] - base, &wa, &we);
+    }
+    tw_carry(A, b, A.w, wa, we);
+    const int32_t cnt = tw_count(A, wa, we);
     if (lane() == 0) A.wcnt[b] = cnt;
     __shared__ int s_last;
     __threadfence();
@@ -576,7 +600,7 @@ hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *
     const size_t o_tlc = take(8 * B), o_tlk = take(8 * B), o_tlh = take(8 * B), o_tlt = take(8 * B),
                  o_tlhb = take(8 * B);
     const size_t o_slots = take(40 * (size_t)nslots);
-    const size_t o_err = take(8 * 4), o_ticket = take(4);
+    const size_t o_err = take(8 * 4), o_ticket = take(4), o_wr = take(16 * (size_t)B);
     if (off > c->tw_bytes) {
         if (c->tw_base) {
             if (hipStreamSynchronize(s) != hipSuccess) return fail(c, HOUGH_ERR_DEVICE, "hipStreamSynchronize failed");
@@ -637,6 +661,7 @@ hough_status hough_tw_find(hough_ctx *ctx, void *stream, const hough_tw_config *
     A.tmax = reinterpret_cast<float *>(sl + 9 * nslots);
     A.err = reinterpret_cast<long long *>(base + o_err);
     A.ticket = reinterpret_cast<int32_t *>(base + o_ticket);
+    A.wr = reinterpret_cast<int64_t *>(base + o_wr);
     A.fcand = c->ws.cand_ws;
     A.fhits = c->ws.hits_ws;
     A.fncand = c->ws.ev_ncand;
