@@ -477,6 +477,36 @@ def test_graph_replays_ordered_call(gpu_available, kw):
     g.close()
 
 
+def test_graph_replays_small_call_large_events(gpu_available):
+    # a captured call of a few events, three of them large: the large events'
+    # first banded sweep (k_band, with its reserved slots) is in the graph;
+    # every replay against the oracle, with the hits rewritten between replays
+    # and eager calls of large events on the same context in between
+    import torch
+    f = finder()
+    evs = [eventgen.pileup_event(7700 + i, n_tracks=nt) for i, nt in enumerate((100, 25, 150, 50, 110))]
+    b = eventgen.make_batch(evs)
+    dev = torch.device("cuda", 0)
+    z = torch.from_numpy(b.z).to(dev)
+    v = torch.from_numpy(b.vane).to(dev)
+    o = torch.from_numpy(b.offsets).to(dev)
+    g = f.capture(z, v, o)
+    other = eventgen.make_batch([eventgen.pileup_event(7750, n_tracks=100), eventgen.pileup_event(7751)])
+    ocfg = _ocfg(f.config)
+    for rep in range(4):
+        zz, vv = (b.z, b.vane) if rep == 0 else _permute_within_events(b, rep)
+        z.copy_(torch.from_numpy(zz))
+        v.copy_(torch.from_numpy(vv))
+        out = g.launch()
+        torch.cuda.synchronize(dev)
+        got = out.to_host()
+        want = oracle_find_batch(ocfg, b.offsets, zz, vv)
+        assert_same(got, want, "small-call replay %d" % rep)
+        assert got[2]["large"] > 0, got[2]
+        check_batch(other, "eager large events between replays")
+    g.close()
+
+
 def test_event_clock_stamps(gpu_available):
     # per-event device clock stamps: set for calls up to 128 events, every
     # event stamped with start <= retire inside the call's span; outputs
