@@ -117,19 +117,26 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 // [wa, we); all 64 lanes of the (one-wave) workgroup call it. Returns the
 // hits added.
 __device__ int tw_extend(const TwArgs &A, int64_t base, int64_t wa, int64_t we, int64_t k, int32_t kid, int d) {
+    // the end's three hits and their coordinates stay in registers across
+    // the steps (this wave is the only writer of the track)
+    int32_t n_k = A.nh[k];
+    if (n_k >= A.max_track_hits) return 0;
+    int32_t e3 = d > 0 ? A.end_up[k] : A.end_down[k];
+    const int32_t e2i = d > 0 ? A.down[e3] : A.up[e3];
+    if (e2i < 0) return 0;   // a track always holds three linked hits; never taken
+    const int32_t e1i = d > 0 ? A.down[e2i] : A.up[e2i];
+    if (e1i < 0) return 0;
+    float r1 = A.r[e1i], r2 = A.r[e2i], r3 = A.r[e3];
+    float z1 = A.z[e1i], z2 = A.z[e2i], z3 = A.z[e3];
+    float t3 = A.t[e3];
+    int v3 = A.vane[e3];
+    float tmax = A.tmax[k];
     int added = 0;
     for (;;) {
-        const int32_t n_k = A.nh[k];
-        if (n_k >= A.max_track_hits) break;
-        const int32_t e3 = d > 0 ? A.end_up[k] : A.end_down[k];
-        const int32_t e2 = d > 0 ? A.down[e3] : A.up[e3];
-        if (e2 < 0) break;   // a track always holds three linked hits; never taken
-        const int32_t e1 = d > 0 ? A.down[e2] : A.up[e2];
-        if (e1 < 0) break;
-        const int target = (A.vane[e3] + d + A.n_vanes) % A.n_vanes;
-        const float r_hat = (A.r[e1] - 3.0f * A.r[e2]) + 3.0f * A.r[e3];
-        const float z_hat = (A.z[e1] - 3.0f * A.z[e2]) + 3.0f * A.z[e3];
-        const float te = A.t[e3];
+        const int target = (v3 + d + A.n_vanes) % A.n_vanes;
+        const float r_hat = (r1 - 3.0f * r2) + 3.0f * r3;
+        const float z_hat = (z1 - 3.0f * z2) + 3.0f * z3;
+        const float te = t3;
         unsigned long long best = ~0ull;
         for (int64_t h0 = wa; h0 < we; h0 += 64) {
             const int64_t h = h0 + lane();
@@ -147,6 +154,9 @@ __device__ int tw_extend(const TwArgs &A, int64_t base, int64_t wa, int64_t we, 
         best = wave_min_u64(best);
         if (best == ~0ull) break;
         const int32_t hb = (int32_t)(base + (int64_t)(best & 0xffffffffull));
+        const float rb = A.r[hb], zb = A.z[hb], tb = A.t[hb];
+        const int vb = A.vane[hb];
+        tmax = tb > tmax ? tb : tmax;
         if (lane() == 0) {
             if (d > 0) {
                 A.up[e3] = hb;
@@ -159,10 +169,21 @@ __device__ int tw_extend(const TwArgs &A, int64_t base, int64_t wa, int64_t we, 
             }
             A.used[hb] = kid;
             A.nh[k] = n_k + 1;
-            if (A.t[hb] > A.tmax[k]) A.tmax[k] = A.t[hb];
+            A.tmax[k] = tmax;
         }
         __syncthreads();
         ++added;
+        ++n_k;
+        if (n_k >= A.max_track_hits) break;
+        r1 = r2;
+        r2 = r3;
+        r3 = rb;
+        z1 = z2;
+        z2 = z3;
+        z3 = zb;
+        t3 = tb;
+        v3 = vb;
+        e3 = hb;
     }
     return added;
 }
