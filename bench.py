@@ -272,8 +272,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(events shard across GPUs with no communication; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(events shard across GPUs with no communication between them).", file=sys.stderr)
         sys.exit(2)
     if args.only_batched:
         args.no_cpu_baseline = True
