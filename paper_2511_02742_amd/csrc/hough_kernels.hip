@@ -2594,8 +2594,6 @@ __global__ __launch_bounds__(NTB) void k_band(FindArgs A, const float2 *__restri
     const int g0 = g * bwf, g1 = min(A.n_theta, g0 + bwf);
     const int sb = (max(g1 - g0, 0) + NWB - 1) / NWB;
     const int r0 = g0 + wave * sb, r1 = min(g1, r0 + sb);
-    const uint32_t tm1 = A.min_votes - 1u;
-    (void)tm1;
     int *rc = s_rc[wave];
     int nseg = 0;
     bool ovf = false;
