@@ -40,6 +40,13 @@ namespace hough {
 namespace {
 
 constexpr int kWave = 64;
+// tid_x(), opaque to the optimiser (addresses derived from it are
+// computed where used, not kept live across the kernel)
+__device__ __forceinline__ int tid_x() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
 // Dynamic LDS of every kernel here (the allocation starts at this symbol);
 // indexing it keeps LDS addresses 32-bit.
@@ -54,10 +61,10 @@ constexpr int kClaimBlockW = 8;  // alive-hit words up to which claims are resol
 constexpr int kSegCounts = 128;  // vote counts T .. T + 127 ordered by order_segments
 
 __device__ __forceinline__ int wave_id() {
-    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    return __builtin_amdgcn_readfirstlane(tid_x() >> 6);
 }
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int lane_id() { return tid_x() & 63; }
 
 // Number of set bits of m in lanes below this one.
 // A wave-uniform 64-bit value moved to scalar registers.
@@ -289,7 +296,7 @@ template <int NT>
 __device__ void sort_desc(unsigned long long *buf, int n) {
     for (int size = 2; size <= n; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < (n >> 1); i += NT) {
+            for (int i = tid_x(); i < (n >> 1); i += NT) {
                 int lo = 2 * i - (i & (stride - 1));
                 int hi = lo + stride;
                 bool desc = (lo & size) == 0;
@@ -367,7 +374,7 @@ struct Shared {
 #ifdef HOUGH_PHASE_CLOCKS
 #define HOUGH_PHASE_MARK(k)                                                                                    \
     do {                                                                                                       \
-        if (threadIdx.x == 0) {                                                                                \
+        if (tid_x() == 0) {                                                                                \
             const unsigned long long t_ = clock64();                                                          \
             sh.ph[(k)] += t_ - sh.t_ph;                                                                        \
             sh.t_ph = t_;                                                                                      \
@@ -482,10 +489,10 @@ __device__ __forceinline__ void maybe_truncate(const FindArgs &A, const Lds &L, 
     const int cnt = sh.pcnt;
     if (cnt <= A.pkeep) return;
     const int cap = A.pkeep + A.hcap;
-    for (int i = cnt + threadIdx.x; i < cap; i += NT) L.pbuf[i] = 0ull;
+    for (int i = cnt + tid_x(); i < cap; i += NT) L.pbuf[i] = 0ull;
     __syncthreads();
     sort_desc<NT>(L.pbuf, cap);
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
         unsigned long long d = L.pbuf[A.pkeep];
         if (d > sh.maxdrop) sh.maxdrop = d;
         sh.pcnt = A.pkeep;
@@ -506,7 +513,7 @@ __device__ __forceinline__ void vote_rows(const FindArgs &A, const float2 *__res
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const uint32_t tm1 = A.min_votes - 1u;
-    uint32_t *const my_dummy = L.dummy + threadIdx.x;
+    uint32_t *const my_dummy = L.dummy + tid_x();
     bool valid[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) valid[c] = (qbase + c * kWave) < n_alive;
@@ -646,7 +653,7 @@ __device__ __forceinline__ void stream_sweep(const FindArgs &A, const float2 *__
                              int n_alive, Shared &sh) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
-    stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(L.dummy - L.tile) + threadIdx.x, h, n_alive, wave,
+    stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(L.dummy - L.tile) + tid_x(), h, n_alive, wave,
                     NW, L.hs, &sh.hs_cnt, A.hs_cap);
 }
 
@@ -720,7 +727,7 @@ __device__ __forceinline__ bool window_peak(const FindArgs &A, const unsigned lo
 template <int NT>
 __device__ __forceinline__ void hash_insert(const unsigned long long *hs, int n_hs, unsigned long long *ht, int log2n) {
     const uint32_t mask = (1u << log2n) - 1u;
-    for (int e = threadIdx.x; e < n_hs; e += NT) {
+    for (int e = tid_x(); e < n_hs; e += NT) {
         const unsigned long long key = hs[e];
         if (key == 0ull) continue;
         const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
@@ -737,18 +744,18 @@ __device__ __forceinline__ void hash_insert(const unsigned long long *hs, int n_
 template <int NT>
 __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int n_hs, Shared &sh) {
     if (A.peak_mode == 0) {
-        if (threadIdx.x == 0) sh.best = 0ull;
+        if (tid_x() == 0) sh.best = 0ull;
         __syncthreads();
         // the largest key: per thread, per wave (DPP), then one LDS atomic
         // per wave
         unsigned long long m = 0ull;
-        for (int e = threadIdx.x; e < n_hs; e += NT) m = L.hs[e] > m ? L.hs[e] : m;
+        for (int e = tid_x(); e < n_hs; e += NT) m = L.hs[e] > m ? L.hs[e] : m;
         m = wave_max64(m);
         if (lane_id() == 0 && m) atomicMax(&sh.best, m);
         __syncthreads();
         const unsigned long long best = sh.best;
         const int npk = best != 0ull ? 1 : 0;
-        if (threadIdx.x == 0) L.sorted[0] = best;
+        if (tid_x() == 0) L.sorted[0] = best;
         __syncthreads();
         return npk;
     }
@@ -760,8 +767,8 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     while ((1 << log2n) < 8 * n_hs && (8 << (log2n + 1)) <= A.hs_off) ++log2n;
     const int ht = 1 << log2n;
     unsigned long long *htab = reinterpret_cast<unsigned long long *>(L.tile);
-    for (int i = threadIdx.x; i < ht; i += NT) htab[i] = 0ull;
-    if (threadIdx.x == 0) sh.pcnt = 0;
+    for (int i = tid_x(); i < ht; i += NT) htab[i] = 0ull;
+    if (tid_x() == 0) sh.pcnt = 0;
     __syncthreads();
     hash_insert<NT>(L.hs, n_hs, htab, log2n);
     __syncthreads();
@@ -770,7 +777,7 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     // matches (a superset of its voters) were left unclaimed at its turn.
     // So the peaks leave the hot set here, and the next iteration's recount
     // skips them (the window test reads the hash table, not the hot set).
-    for (int e = threadIdx.x; e < n_hs; e += NT) {
+    for (int e = tid_x(); e < n_hs; e += NT) {
         const unsigned long long key = L.hs[e];
         if (key == 0ull) continue;
         if (window_peak(A, htab, log2n, key)) {
@@ -786,11 +793,11 @@ __device__ __forceinline__ int hotset_peaks(const FindArgs &A, const Lds &L, int
     // adjacent lanes share a key and split its comparisons.
     int G = 1;
     while (G < kWave && 2 * G * npk <= NT) G *= 2;
-    const int g = threadIdx.x & (G - 1);
+    const int g = tid_x() & (G - 1);
     // two keys per 16-byte load (the peak list starts 16-byte aligned)
     const ulonglong2 *pb2 = reinterpret_cast<const ulonglong2 *>(L.pbuf);
     const int npair = npk >> 1;
-    for (int p = threadIdx.x / G; p < npk; p += NT / G) {
+    for (int p = tid_x() / G; p < npk; p += NT / G) {
         const unsigned long long key = L.pbuf[p];
         int r = 0;
         int q = g;
@@ -898,7 +905,7 @@ __device__ __forceinline__ Slot slot_ptrs(const FindArgs &A, int s) {
 // slots as finder workgroups can be resident at once (or as events), so a
 // running workgroup finds one; the scan is bounded either way.
 __device__ __forceinline__ int acquire_slot(const FindArgs &A, Shared &sh) {
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
         int got = -1;
         const int n = A.pool_slots;
         for (int i = 0; i < 2 * n && got < 0; ++i) {
@@ -915,7 +922,7 @@ __device__ __forceinline__ void release_slot(const FindArgs &A, int s) {
     if (s < 0) return;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) atomicExch(&A.pool_flags[s], 0);
+    if (tid_x() == 0) atomicExch(&A.pool_flags[s], 0);
 }
 
 // Loads the first 512 alive hits into registers and the rest into LDS at xh;
@@ -924,7 +931,7 @@ template <int NT>
 __device__ __forceinline__ bool load_big(const FindArgs &A, int64_t b, int n_alive, HitRegs &h, float2 *xh) {
     load_batch(A, b, n_alive, 0, h);
     int ok = 1;
-    for (int q = kChunks * kWave + threadIdx.x; q < n_alive; q += NT) {
+    for (int q = kChunks * kWave + tid_x(); q < n_alive; q += NT) {
         const float p = A.aphi[b + q], z = A.az[b + q];
         xh[q - kChunks * kWave] = make_float2(p, z);
         ok &= ((double)p * p + (double)z * z <= A.safe_r2) ? 1 : 0;
@@ -997,7 +1004,7 @@ __device__ __forceinline__ void band_big(const FindArgs &A, const float2 *__rest
                      wave * nl * cap;
     int *rc = &sh.rollc[wave * kMaxLists];
     const uint32_t row_w = (uint32_t)(wave * A.pitch);
-    const uint32_t dummy_w = (uint32_t)(L.dummy - L.tile) + threadIdx.x;
+    const uint32_t dummy_w = (uint32_t)(L.dummy - L.tile) + tid_x();
     bool valid[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) valid[c] = c < h.nch && c * kWave + lane < n_alive;
@@ -1236,7 +1243,7 @@ __device__ __forceinline__ void band_ring(const FindArgs &A, const float2 *__res
     uint32_t *lists = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.tile) + roff +
                                                    NW * hw * 4) + wave * 3 * cap;
     int *rc = &sh.rollc[wave * kMaxLists];
-    const uint32_t dummy_w = (uint32_t)(L.dummy - L.tile) + threadIdx.x;
+    const uint32_t dummy_w = (uint32_t)(L.dummy - L.tile) + tid_x();
     bool valid[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) valid[c] = c < h.nch && c * kWave + lane < n_alive;
@@ -1359,7 +1366,7 @@ __device__ __forceinline__ int order_peaks(const FindArgs &A, const Lds &L, cons
     const int wave = wave_id();
     const int lane = lane_id();
     if (npk <= 1) {
-        if (npk == 1 && threadIdx.x == 0) S.srt[0] = S.pk[0];
+        if (npk == 1 && tid_x() == 0) S.srt[0] = S.pk[0];
         sync_global();
         return npk;
     }
@@ -1368,9 +1375,9 @@ __device__ __forceinline__ int order_peaks(const FindArgs &A, const Lds &L, cons
     int *cur = hist + (cmax + 1);                  // [cmax + 1] scatter cursors
     uint32_t *runs = reinterpret_cast<uint32_t *>(L.pbuf);  // (start, length) of runs longer than 1
     const int max_runs = A.pkeep + A.hcap;
-    for (int i = threadIdx.x; i <= cmax; i += NT) hist[i] = 0;
+    for (int i = tid_x(); i <= cmax; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < npk; i += NT) atomicAdd(&hist[(uint32_t)(S.pk[i] >> 32)], 1);
+    for (int i = tid_x(); i < npk; i += NT) atomicAdd(&hist[(uint32_t)(S.pk[i] >> 32)], 1);
     __syncthreads();
     if (wave == 0) {
         // run starts in descending count order
@@ -1397,7 +1404,7 @@ __device__ __forceinline__ int order_peaks(const FindArgs &A, const Lds &L, cons
     __syncthreads();
     const int nruns = sh.nruns;
     if (nruns > max_runs) return -1;
-    for (int i = threadIdx.x; i < npk; i += NT) {
+    for (int i = tid_x(); i < npk; i += NT) {
         const unsigned long long key = S.pk[i];
         S.srt[atomicAdd(&cur[(uint32_t)(key >> 32)], 1)] = key;
     }
@@ -1408,10 +1415,10 @@ __device__ __forceinline__ int order_peaks(const FindArgs &A, const Lds &L, cons
         const int len = (int)runs[2 * r + 1];
         if (len > A.big_sort) return -1;
         const int c2 = next_pow2(len);
-        for (int i = threadIdx.x; i < c2; i += NT) buf[i] = i < len ? S.srt[st + i] : 0ull;
+        for (int i = tid_x(); i < c2; i += NT) buf[i] = i < len ? S.srt[st + i] : 0ull;
         __syncthreads();
         sort_desc<NT>(buf, c2);
-        for (int i = threadIdx.x; i < len; i += NT) S.srt[st + i] = buf[i];
+        for (int i = tid_x(); i < len; i += NT) S.srt[st + i] = buf[i];
         __syncthreads();
     }
     sync_global();
@@ -1435,9 +1442,9 @@ __device__ __forceinline__ int order_segments(const FindArgs &A, const Lds &L, c
     int *hist = reinterpret_cast<int *>(L.tile);   // [cmax + 1]
     int *cur = hist + (cmax + 1);                  // [cmax + 1] run starts
     int *wh = cur + (cmax + 1);                    // [NW][kSegCounts] counts T .. per wave
-    for (int i = threadIdx.x; i <= cmax; i += NT) hist[i] = 0;
-    for (int i = threadIdx.x; i < NW * kSegCounts; i += NT) wh[i] = 0;
-    if (threadIdx.x == 0) sh.best = 0ull;
+    for (int i = tid_x(); i <= cmax; i += NT) hist[i] = 0;
+    for (int i = tid_x(); i < NW * kSegCounts; i += NT) wh[i] = 0;
+    if (tid_x() == 0) sh.best = 0ull;
     __syncthreads();
     // (a full segment's peaks beyond segcap were not stored: the result is
     // then dropped, and only stored keys are read)
@@ -1479,7 +1486,7 @@ __device__ __forceinline__ int order_segments(const FindArgs &A, const Lds &L, c
     __syncthreads();
     // wave w's cursor for count T + r: the run start plus the earlier waves'
     // peaks of that count
-    for (int r = threadIdx.x; r < kSegCounts && !wide; r += NT) {
+    for (int r = tid_x(); r < kSegCounts && !wide; r += NT) {
         int off = (uint32_t)(T + r) <= (uint32_t)cmax ? cur[T + r] : 0;
         for (int w = 0; w < NW; ++w) {
             const int v = wh[w * kSegCounts + r];
@@ -1556,9 +1563,9 @@ __device__ __forceinline__ void sweep(const FindArgs &A, const float2 *__restric
         __syncthreads();
 
         const int nhot = *hotc;
-        if (threadIdx.x == 0) sh.hotc[(slab + 1) & 1] = 0;
+        if (tid_x() == 0) sh.hotc[(slab + 1) & 1] = 0;
         if (nhot <= A.hcap) {
-            for (int e = threadIdx.x; e < nhot; e += NT) {
+            for (int e = tid_x(); e < nhot; e += NT) {
                 const uint32_t v = L.hot[e];
                 test_bin(A, L, (int)(v >> 16), (int)(v & 0xffffu), lo, ceil_key, sh);
             }
@@ -1566,11 +1573,11 @@ __device__ __forceinline__ void sweep(const FindArgs &A, const float2 *__restric
             if (A.peak_mode == 1) maybe_truncate<NT>(A, L, sh);
         } else {
             // hot list overflowed: scan the own rows in chunks of hcap bins
-            if (threadIdx.x == 0) sh.n_hotscan += 1;
+            if (tid_x() == 0) sh.n_hotscan += 1;
             const int nb = own * A.n_rho;
             for (int base = 0; base < nb; base += A.hcap) {
                 const int lim = min(A.hcap, nb - base);
-                for (int q = threadIdx.x; q < lim; q += NT) {
+                for (int q = tid_x(); q < lim; q += NT) {
                     const int bin = base + q;
                     const int tr = own_lo + bin / A.n_rho;
                     const int k = bin % A.n_rho;
@@ -1609,16 +1616,16 @@ __device__ __forceinline__ void claim_rounds(const FindArgs &A, unsigned long lo
                              int *owner, int W, int nb, Shared &sh) {
     constexpr int kFresh = 1 << 24;
     const int T = (int)A.min_votes;
-    for (int p = threadIdx.x; p < nb; p += NT) pst[p] = 0;
-    for (int q = threadIdx.x; q < W * kWave; q += NT) owner[q] = 0x7fffffff;
-    if (threadIdx.x == 0) {
+    for (int p = tid_x(); p < nb; p += NT) pst[p] = 0;
+    for (int q = tid_x(); q < W * kWave; q += NT) owner[q] = 0x7fffffff;
+    if (tid_x() == 0) {
         sh.rcnt[0] = 0;
         sh.rcnt[1] = 0;
     }
     __syncthreads();
     for (int round = 0;; ++round) {
         int *open = &sh.rcnt[round & 1];
-        for (int p = threadIdx.x; p < nb; p += NT) {
+        for (int p = tid_x(); p < nb; p += NT) {
             if (pst[p] != 0) continue;
             const unsigned long long *mp = M + (size_t)p * W;
             int c = 0;
@@ -1638,7 +1645,7 @@ __device__ __forceinline__ void claim_rounds(const FindArgs &A, unsigned long lo
         }
         __syncthreads();
         if (*open == 0) break;
-        for (int p = threadIdx.x; p < nb; p += NT) {
+        for (int p = tid_x(); p < nb; p += NT) {
             if (pst[p] != 0) continue;
             unsigned long long *mp = M + (size_t)p * W;
             bool first = true;
@@ -1657,7 +1664,7 @@ __device__ __forceinline__ void claim_rounds(const FindArgs &A, unsigned long lo
             }
         }
         __syncthreads();
-        for (int p = threadIdx.x; p < nb; p += NT) {
+        for (int p = tid_x(); p < nb; p += NT) {
             if (pst[p] > 0 && (pst[p] & kFresh)) {
                 const unsigned long long *mp = M + (size_t)p * W;
                 for (int w = 0; w < W; ++w)
@@ -1665,8 +1672,8 @@ __device__ __forceinline__ void claim_rounds(const FindArgs &A, unsigned long lo
                 pst[p] &= ~kFresh;
             }
         }
-        for (int q = threadIdx.x; q < W * kWave; q += NT) owner[q] = 0x7fffffff;
-        if (threadIdx.x == 0) sh.rcnt[(round + 1) & 1] = 0;
+        for (int q = tid_x(); q < W * kWave; q += NT) owner[q] = 0x7fffffff;
+        if (tid_x() == 0) sh.rcnt[(round + 1) & 1] = 0;
         __syncthreads();
     }
 }
@@ -1853,8 +1860,8 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     const int nb0 = min(pb, npk);
     int2 d0 = make_int2(0, 0);
     float2 t0 = make_float2(0.0f, 0.0f);
-    if (nb0 <= NT && threadIdx.x < nb0) {
-        const uint32_t flat = 0xffffffffu - (uint32_t)(keys[threadIdx.x] & 0xffffffffull);
+    if (nb0 <= NT && tid_x() < nb0) {
+        const uint32_t flat = 0xffffffffu - (uint32_t)(keys[tid_x()] & 0xffffffffull);
         const int j = (int)(flat / (uint32_t)A.n_rho);
         d0 = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
         t0 = cs[j];
@@ -1873,12 +1880,12 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         const int nb = min(pb, npk - p0);
         // coordinates and (cos, sin) of this pass's peaks
         if (p0 == 0 && nb0 <= NT) {
-            if (threadIdx.x < nb0) {
-                dec[threadIdx.x] = d0;
-                pcs[threadIdx.x] = t0;
+            if (tid_x() < nb0) {
+                dec[tid_x()] = d0;
+                pcs[tid_x()] = t0;
             }
         } else {
-            for (int p = threadIdx.x; p < nb; p += NT) {
+            for (int p = tid_x(); p < nb; p += NT) {
                 const uint32_t flat = 0xffffffffu - (uint32_t)(keys[p0 + p] & 0xffffffffull);
                 const int j = (int)(flat / (uint32_t)A.n_rho);
                 dec[p] = make_int2(j, (int)(flat % (uint32_t)A.n_rho));
@@ -1974,7 +1981,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         const int nemit = sh.nemit;
         const int cid0 = sh.ncand - nemit;
         // candidate records and word prefixes of the claimed sets
-        for (int ei = threadIdx.x; ei < nemit; ei += NT) {
+        for (int ei = tid_x(); ei < nemit; ei += NT) {
             const int p = elist[ei];
             const int2 jk = dec[p];
             hough_candidate cd;
@@ -2082,7 +2089,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int64_t b = uniform64(A.offsets[e]);
     const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
 
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
         if (A.ev_clock != nullptr) sh.t_start = wall_clock64();
 #ifdef HOUGH_PHASE_CLOCKS
         sh.t_ph = clock64();
@@ -2126,7 +2133,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __syncthreads();
     if (sh.bad) {
         release_slot(A, sh.rslot);
-        if (threadIdx.x == 0) {
+        if (tid_x() == 0) {
             if (A.g_cnt != nullptr) {
                 A.g_cnt[e] = 0;
                 A.g_flag[e] = 0;
@@ -2146,7 +2153,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // validate, put every hit in the pool and write the first iteration's
     // alive list (every hit, in order)
     int badhit = 0;
-    for (int i = threadIdx.x; i < n; i += NT) {
+    for (int i = tid_x(); i < n; i += NT) {
         const int v = A.vane[b + i];
         const float zz = A.z[b + i];
         if (v < 0 || v >= A.n_vanes || !(fabsf(zz) <= HOUGH_Z_LIMIT)) {
@@ -2161,7 +2168,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
     if (__syncthreads_or(badhit)) {
         release_slot(A, sh.rslot);
-        if (threadIdx.x == 0) {
+        if (tid_x() == 0) {
             if (A.g_cnt != nullptr) {
                 A.g_cnt[e] = 0;
                 A.g_flag[e] = 0;
@@ -2177,7 +2184,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (A.counts != nullptr) {
             // first invalid hit of the event (the only event of the call)
             __syncthreads();
-            if (threadIdx.x == 0) {
+            if (tid_x() == 0) {
                 const long long first = A.err[1];
                 A.err[0] = 0;
                 A.err[1] = 0x7fffffffffffffffll;
@@ -2204,12 +2211,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (;;) {
         HOUGH_PHASE_MARK(kPhRest);
         if (A.max_iters > 0 && iter >= A.max_iters) break;
-        if (threadIdx.x == 0) sh.rlive = 0;  // live bins of a recount in this iteration
+        if (tid_x() == 0) sh.rlive = 0;  // live bins of a recount in this iteration
         // alive list, in ascending hit order (written with the validation
         // for the first iteration)
         int carry = iter == 0 ? n : 0;
         for (int base = 0; base < n && iter > 0; base += NT) {
-            const int i = base + threadIdx.x;
+            const int i = base + tid_x();
             // the hit's state, vane and z are read together, and its phi
             // before the barrier
             const bool in = i < n;
@@ -2239,7 +2246,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (carry < (int)A.min_votes) break;
         const int n_alive = carry;
         const int nbatch = (n_alive + kChunks * kWave - 1) / (kChunks * kWave);
-        if (threadIdx.x == 0) sh.nalive = n_alive;
+        if (tid_x() == 0) sh.nalive = n_alive;
         const int ncand0 = sh.ncand;
         if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
         HOUGH_PHASE_MARK(kPhAlive);
@@ -2268,7 +2275,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     // the first histogram was swept by the split sweep kernel
                     n_hs = A.g_cnt[e];
                     const unsigned long long *src = A.g_hs + (size_t)e * A.hs_cap;
-                    for (int i = threadIdx.x; i < n_hs; i += NT) L.hs[i] = src[i];
+                    for (int i = tid_x(); i < n_hs; i += NT) L.hs[i] = src[i];
                     hs_valid = true;
                     ++passes;
                     evals += (unsigned long long)n_alive * (unsigned long long)A.n_theta;
@@ -2300,7 +2307,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     // row-stream sweep; a hot set larger than LDS holds
                     // sends the event to the large-event path below
                     ++passes;
-                    if (threadIdx.x == 0) sh.hs_cnt = 0;
+                    if (tid_x() == 0) sh.hs_cnt = 0;
                     __syncthreads();
                     stream_sweep<NT>(A, cs, L, h, n_alive, sh);
                     __syncthreads();
@@ -2339,7 +2346,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     ++bigs;
                     ++passes;
                     hs_valid = false;
-                    if (threadIdx.x == 0) {
+                    if (tid_x() == 0) {
                         sh.pcnt = 0;
                         sh.big_ovf = 0;
                         sh.best = 0ull;
@@ -2363,7 +2370,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     if (sh.big_ovf == 0) {
                         if (A.peak_mode == 0) {
                             const unsigned long long best = sh.best;
-                            if (threadIdx.x == 0) S.srt[0] = best;
+                            if (tid_x() == 0) S.srt[0] = best;
                             sync_global();
                             npk = best != 0ull ? 1 : 0;
                         } else if (ring) {
@@ -2399,7 +2406,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (; !done;) {
             ++passes;
             ++tiled;
-            if (threadIdx.x == 0) {
+            if (tid_x() == 0) {
                 sh.pcnt = 0;
                 sh.maxdrop = 0ull;
                 sh.best = 0ull;
@@ -2412,11 +2419,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const unsigned long long best = sh.best;
                 npk = (uint32_t)(best >> 32) >= A.min_votes ? 1 : 0;
                 __syncthreads();
-                if (threadIdx.x == 0) L.pbuf[0] = best;
+                if (tid_x() == 0) L.pbuf[0] = best;
             } else {
                 npk = sh.pcnt;
                 const int cap = next_pow2(npk);
-                for (int i = npk + threadIdx.x; i < cap; i += NT) L.pbuf[i] = 0ull;
+                for (int i = npk + tid_x(); i < cap; i += NT) L.pbuf[i] = 0ull;
                 __syncthreads();
                 if (npk > 1) sort_desc<NT>(L.pbuf, cap);
             }
@@ -2435,7 +2442,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (sh.ncand == ncand0) break;
     }
     release_slot(A, slot >= 0 ? slot : sh.rslot);
-    if (A.g_cnt != nullptr && threadIdx.x == 0) {
+    if (A.g_cnt != nullptr && tid_x() == 0) {
         // leave the split-sweep words cleared for the next call
         A.g_cnt[e] = 0;
         A.g_flag[e] = 0;
@@ -2444,7 +2451,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (A.counts != nullptr) {
         // single-event call: the slots are the caller's arrays; write the
         // counts directly (no other block touches them)
-        if (threadIdx.x == 0) {
+        if (tid_x() == 0) {
             A.counts[HOUGH_COUNT_CANDIDATES] = sh.ncand;
             A.counts[HOUGH_COUNT_HITS] = sh.nhit;
             A.counts[HOUGH_COUNT_STATUS] = 0;
@@ -2465,7 +2472,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         return;
     }
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
         A.ev_ncand[e] = sh.ncand;
         A.ev_nhits[e] = sh.nhit;
         put_ev_stats(A, e, evals, iter, passes, tiled, sh.n_trunc, sh.n_hotscan, hs_full, recounts, bigs, votes);
@@ -2488,7 +2495,7 @@ __global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restri
     const int64_t b = A.offsets[e];
     const int64_t n64 = A.offsets[e + 1] - b;
     if (b < 0 || n64 < 0 || b + n64 > A.n_total || n64 > kChunks * kWave) {
-        if (threadIdx.x == 0) A.g_flag[e] = 1;
+        if (tid_x() == 0) A.g_flag[e] = 1;
         return;
     }
     const int n = (int)n64;
@@ -2517,11 +2524,11 @@ __global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restri
     }
     h.safe = __ballot(!ok) == 0ull;
     if (__syncthreads_or(bad || !h.safe)) {
-        if (threadIdx.x == 0) A.g_flag[e] = 1;
+        if (tid_x() == 0) A.g_flag[e] = 1;
         return;
     }
     if (n < (int)A.min_votes) return;
-    stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(NW * A.pitch) + threadIdx.x, h, n,
+    stream_dispatch(A, cs, (uint32_t)(wave * A.pitch), (uint32_t)(NW * A.pitch) + tid_x(), h, n,
                     g * NW + wave, groups * NW, A.g_hs + (size_t)e * A.hs_cap, A.g_cnt + e, A.hs_cap);
 }
 
@@ -2563,15 +2570,15 @@ __global__ __launch_bounds__(NTB) void k_band(FindArgs A, const float2 *__restri
     uint32_t *lists = g_lds + rings + NWB * 3 * hw + wave * 3 * kCapB;
     unsigned long long *pk = reinterpret_cast<unsigned long long *>(g_lds + rings + NWB * 3 * hw + NWB * 3 * kCapB) +
                              wave * kSegW;
-    const uint32_t dummy_w = rings + NWB * 3 * hw + NWB * 3 * kCapB + 2 * NWB * kSegW + threadIdx.x;
+    const uint32_t dummy_w = rings + NWB * 3 * hw + NWB * 3 * kCapB + 2 * NWB * kSegW + tid_x();
     __shared__ int s_rc[NWB][3];
     __shared__ int s_n[NWB];
     __shared__ int s_bad;
-    if (threadIdx.x == 0) s_bad = 0;
+    if (tid_x() == 0) s_bad = 0;
     __syncthreads();
     // the hits (every hit is alive in the first iteration)
     bool bad = false;
-    for (int i = threadIdx.x; i < n; i += NTB) {
+    for (int i = tid_x(); i < n; i += NTB) {
         const int v = A.vane[b + i];
         const float zz = A.z[b + i];
         float ph = 0.0f;
@@ -2583,7 +2590,7 @@ __global__ __launch_bounds__(NTB) void k_band(FindArgs A, const float2 *__restri
         xy[i] = make_float2(ph, zz);
     }
     if (__syncthreads_or(bad)) return;
-    if (g == 0 && threadIdx.x == 0) {
+    if (g == 0 && tid_x() == 0) {
         // the slot the finder will take over for this event
         A.pool_flags[e] = 1;
         A.b_slot[e] = e + 1;
@@ -2666,7 +2673,7 @@ __global__ __launch_bounds__(NTB) void k_band(FindArgs A, const float2 *__restri
     for (int i = lane; i < nseg; i += kWave) seg[before + i] = pk[i];
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
         A.b_cnt[e * nwf + g] = total;
         __threadfence();
         atomicAdd(&A.b_ok[e], 1);
@@ -2684,11 +2691,11 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
     constexpr int NW = NT / kWave;
     __shared__ long long wc[NW], wh[NW];
     __shared__ unsigned long long ws[NW][kEvStats + 1];
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
+    const int wave = tid_x() >> 6;
+    const int lane = tid_x() & 63;
     long long carry_c = 0, carry_h = 0;
     for (int base = 0; base < A.n_events; base += NT) {
-        const int e = base + threadIdx.x;
+        const int e = base + tid_x();
         const long long c = e < A.n_events ? A.ev_ncand[e] : 0;
         const long long h = e < A.n_events ? A.ev_nhits[e] : 0;
         long long ic = c, ih = h;
@@ -2726,7 +2733,7 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
     unsigned long long acc[kEvStats + 1];
 #pragma unroll
     for (int k = 0; k <= kEvStats; ++k) acc[k] = 0ull;
-    for (int e = threadIdx.x; e < A.n_events; e += NT) {
+    for (int e = tid_x(); e < A.n_events; e += NT) {
 #pragma unroll
         for (int k = 0; k < kEvStats; ++k) acc[k] += A.ev_stats[(size_t)k * A.n_events + e];
         const unsigned long long it = A.ev_stats[(size_t)kEvIters * A.n_events + e];
@@ -2744,14 +2751,14 @@ __global__ __launch_bounds__(1024) void k_scan(CompactArgs A) {
     }
     __syncthreads();
     // thread k combines word k over the waves
-    if (threadIdx.x <= kEvStats) {
-        const int k = threadIdx.x;
+    if (tid_x() <= kEvStats) {
+        const int k = tid_x();
         unsigned long long t = 0ull;
         for (int u = 0; u < NW; ++u) t = k < kEvStats ? t + ws[u][k] : (ws[u][k] > t ? ws[u][k] : t);
         ws[0][k] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid_x() == 0) {
         const unsigned long long *tot = ws[0];
         const long long st = A.err[0];
         A.counts[HOUGH_COUNT_CANDIDATES] = st ? 0 : carry_c;
@@ -2786,12 +2793,12 @@ __global__ __launch_bounds__(256) void k_copy(CompactArgs A) {
         const int nh = A.ev_nhits[e];
         const long long co = A.ev_cout[e];
         const long long ho = A.ev_hout[e];
-        for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        for (int i = tid_x(); i < nc; i += blockDim.x) {
             hough_candidate cd = A.cand_ws[cbase + i];
             cd.hit_offset += ho;
             A.cand[co + i] = cd;
         }
-        for (int i = threadIdx.x; i < nh; i += blockDim.x) A.hit_index[ho + i] = A.hits_ws[b + i];
+        for (int i = tid_x(); i < nh; i += blockDim.x) A.hit_index[ho + i] = A.hits_ws[b + i];
     }
 }
 
@@ -2806,7 +2813,7 @@ __global__ __launch_bounds__(1024) void k_dump(DumpArgs A, const float2 *__restr
     const int wave = wave_id();
     const int lane = lane_id();
     uint4 *t4 = reinterpret_cast<uint4 *>(tile);
-    for (int q = threadIdx.x; q < rows * A.pitch / 4; q += NT) t4[q] = make_uint4(0u, 0u, 0u, 0u);
+    for (int q = tid_x(); q < rows * A.pitch / 4; q += NT) t4[q] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const int64_t chunks = (A.n + kWave - 1) / kWave;
     for (int64_t ch = wave; ch < chunks; ch += NW) {
@@ -2827,7 +2834,7 @@ __global__ __launch_bounds__(1024) void k_dump(DumpArgs A, const float2 *__restr
         }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < rows * A.n_rho; q += NT) {
+    for (int q = tid_x(); q < rows * A.n_rho; q += NT) {
         const int tr = q / A.n_rho;
         const int k = q - tr * A.n_rho;
         A.acc[(int64_t)(j0 + tr) * A.n_rho + k] = tile[tr * A.pitch + k];
@@ -2908,7 +2915,7 @@ constexpr int kOrderBins = 1024;
 __global__ __launch_bounds__(kOrderBins) void k_order(const int64_t *offsets, int32_t n_events, int32_t *order) {
     __shared__ int cur[kOrderBins];
     __shared__ int wsum[kOrderBins / kWave];
-    const int t = threadIdx.x;
+    const int t = tid_x();
     cur[t] = 0;
     __syncthreads();
     for (int e = t; e < n_events; e += kOrderBins) {
@@ -2939,12 +2946,12 @@ __global__ __launch_bounds__(kOrderBins) void k_order(const int64_t *offsets, in
 __global__ void k_clear_ws(long long *err, int32_t *g_cnt, int32_t *g_flag, int64_t n_events, int32_t *pool_flags,
                            int32_t slots) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_events; i += stride) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid_x(); i < n_events; i += stride) {
         g_cnt[i] = 0;
         g_flag[i] = 0;
     }
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < slots; i += stride) pool_flags[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + tid_x(); i < slots; i += stride) pool_flags[i] = 0;
+    if (blockIdx.x == 0 && tid_x() == 0) {
         err[0] = 0;
         err[1] = 0x7fffffffffffffffll;
     }
