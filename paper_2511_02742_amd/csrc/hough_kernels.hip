@@ -40,8 +40,9 @@ namespace hough {
 namespace {
 
 constexpr int kWave = 64;
-// tid_x(), opaque to the optimiser (addresses derived from it are
-// computed where used, not kept live across the kernel)
+// The thread index, opaque to the optimiser: addresses derived from it are
+// computed where they are used instead of being hoisted to the kernel's
+// start and held (spilled to scratch at the finder's 128-VGPR budget)
 __device__ __forceinline__ int tid_x() {
     int t = (int)threadIdx.x;
     asm volatile("" : "+v"(t));
