@@ -189,7 +189,7 @@ __device__ int tw_extend(const TwArgs &A, int64_t base, int64_t wa, int64_t we, 
 }
 
 // The window [lo, lo + width) of timeline b as a hit range.
-__device__ void window_range(const TwArgs &A, int64_t base, int64_t n, float lo, float hi, int64_t *wa, int64_t *we) {
+__device__ __forceinline__ void window_range(const TwArgs &A, int64_t base, int64_t n, float lo, float hi, int64_t *wa, int64_t *we) {
     __shared__ int64_t s_r[2];
     if (threadIdx.x == 0) {
         s_r[0] = lower_bound_t(A.t, base, base + n, lo);
@@ -217,7 +217,7 @@ __device__ int64_t advance_lb(const float *t, int64_t from, int64_t end, float x
 
 // The hit range of window w of timeline b: binary searches for the first
 // window, then advanced from the previous window's range (stored in A.wr).
-__device__ void window_next(const TwArgs &A, int b, int w, int64_t base, int64_t n, int64_t *wa, int64_t *we) {
+__device__ __forceinline__ void window_next(const TwArgs &A, int b, int w, int64_t base, int64_t n, int64_t *wa, int64_t *we) {
     const float lo = window_lo(A, w), hi = lo + A.window_ns;
     if (w == 0) {
         window_range(A, base, n, lo, hi, wa, we);
