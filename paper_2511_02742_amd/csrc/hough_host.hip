@@ -66,7 +66,6 @@ char *scratch_of(int device, hipError_t *err) {
 constexpr int kHotCap = 512;
 constexpr int kPeakKeep = 512;          // kHotCap + kPeakKeep is a power of two
 static_assert(kHotCap % 4 == 0, "the finder reads its peak list, placed after the hot list, 16 bytes at a time");
-constexpr int kStaticLds = 1024;        // headroom for the kernel's static LDS
 constexpr int kOrderMin = 64;           // calls of more events than this (and than resident workgroups) run the longest events first
 // calls of at most kSmallCall events split each event's first sweep over
 // this many 256-thread workgroups when the configuration leaves the split to

@@ -149,6 +149,10 @@ struct CompactArgs {
     int32_t ordered;  // the finder ran the events longest first (counts[HOUGH_COUNT_ORDERED])
 };
 
+// LDS bytes the host leaves beside a kernel's dynamic LDS for its static
+// shared variables (the finder's per-workgroup state is the largest)
+constexpr int kStaticLds = 2048;
+
 // Kernel launchers (hough_kernels.hip). Each returns the launch status.
 hipError_t launch_find(const FindArgs &a, int wg_threads, int lds_bytes, hipStream_t s);
 hipError_t launch_sweep(const FindArgs &a, int threads, int groups, hipStream_t s);

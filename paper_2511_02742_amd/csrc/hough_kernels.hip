@@ -368,7 +368,11 @@ struct Shared {
     int nruns;       // runs of equal counts in a large event's peak list
     int rollc[16 * kMaxLists];  // fill of each wave's row lists (banded sweep)
     int rlive;       // live bins the last recount tested
+    // alive list (event-local hit indices, ascending) of an event of at most
+    // 512 hits; larger events keep theirs in device memory
+    uint16_t aidx_s[kChunks * kWave];
 };
+static_assert(sizeof(Shared) <= kStaticLds, "the host leaves kStaticLds bytes of LDS for the finder's static state");
 
 // Charges the cycles since the last mark to phase k (thread 0; the marks sit
 // after a workgroup barrier, so thread 0's counter stands for the group).
@@ -433,6 +437,27 @@ __device__ __forceinline__ void load_batch(const FindArgs &A, int64_t b, int n_a
         // |rho(theta)| <= sqrt(phi^2 + z^2) (1 + 2^-24)^3 for every sampled
         // theta, which safe_r2 keeps below the rho range by a margin that
         // also covers the rounding of the subtraction and of inv_w
+        const double r2 = (double)h.phi[c] * h.phi[c] + (double)h.z[c] * h.z[c];
+        ok = ok && (!v || r2 <= A.safe_r2);
+    }
+    h.safe = __ballot(!ok) == 0ull;
+}
+
+// load_batch for an event of at most 512 hits, whose alive list sits in LDS:
+// each alive hit's phi and z are read from the call's inputs
+__device__ __forceinline__ void load_small(const FindArgs &A, int64_t b, int n_alive, const uint16_t *aidx_s,
+                                           HitRegs &h) {
+    const int lane = lane_id();
+    h.nch = (n_alive + kWave - 1) / kWave;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const int q = c * kWave + lane;
+        const bool v = c < h.nch && q < n_alive;
+        const int il = v ? (int)aidx_s[q] : 0;
+        const float z = v ? A.z[b + il] : 0.0f;
+        h.phi[c] = v ? A.phi_v[A.vane[b + il]] : 0.0f;
+        h.z[c] = z;
         const double r2 = (double)h.phi[c] * h.phi[c] + (double)h.z[c] * h.z[c];
         ok = ok && (!v || r2 <= A.safe_r2);
     }
@@ -1830,7 +1855,7 @@ __device__ __forceinline__ void match_masks(const FindArgs &A, const HitRegs &h,
 template <int NT>
 __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__restrict__ cs, int e, int64_t b, int iter,
                           const Lds &L, const unsigned long long *keys, int uni_bytes, HitRegs &h, int nbatch,
-                          int npk, Shared &sh, const float2 *xh) {
+                          int npk, Shared &sh, const float2 *xh, bool small) {
     constexpr int NW = NT / kWave;
     const int wave = wave_id();
     const int lane = lane_id();
@@ -1870,7 +1895,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     // the hits claimed by an earlier pass of this iteration
     for (int ch = wave; ch < W; ch += NW) {
         const int q = ch * kWave + lane;
-        const bool taken = q < n_alive && A.state[b + A.aidx[b + q]] != -1;
+        const bool taken = q < n_alive && A.state[b + (small ? (int)sh.aidx_s[q] : A.aidx[b + q])] != -1;
         const unsigned long long m = __ballot(taken);
         if (lane == 0) icl[ch] = m;
     }
@@ -2012,7 +2037,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             const unsigned long long m = M[(size_t)p * W + ch];
             if ((m >> lane) & 1ull) {
                 const int q = ch * kWave + lane;
-                const int il = A.aidx[b + q];
+                const int il = small ? (int)sh.aidx_s[q] : A.aidx[b + q];
                 const int pos = pbase[p] + (int)rp[(size_t)p * W + ch] + mbcnt64(m);
                 A.hits_ws[b + pos] = il;
                 A.state[b + il] = cid0 + ei;
@@ -2152,7 +2177,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int n = (int)n64;
 
     // validate, put every hit in the pool and write the first iteration's
-    // alive list (every hit, in order)
+    // alive list (every hit, in order): in LDS for an event of at most 512
+    // hits, whose alive hits are read from the inputs, else in device memory
+    // with each hit's phi and z
+    const bool small = n64 <= kChunks * kWave;
     int badhit = 0;
     for (int i = tid_x(); i < n; i += NT) {
         const int v = A.vane[b + i];
@@ -2160,6 +2188,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (v < 0 || v >= A.n_vanes || !(fabsf(zz) <= HOUGH_Z_LIMIT)) {
             badhit = 1;
             atomicMin(&A.err[1], (long long)(b + i));
+        } else if (small) {
+            sh.aidx_s[i] = (uint16_t)i;
         } else {
             A.aidx[b + i] = i;
             A.aphi[b + i] = A.phi_v[v];
@@ -2221,11 +2251,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // the hit's state, vane and z are read together, and its phi
             // before the barrier
             const bool in = i < n;
+            const bool rd = in && !small;
             const int st = in ? A.state[b + i] : 0;
-            const int vn = in ? (int)A.vane[b + i] : 0;
-            const float zz = in ? A.z[b + i] : 0.0f;
+            const int vn = rd ? (int)A.vane[b + i] : 0;
+            const float zz = rd ? A.z[b + i] : 0.0f;
             const bool alive = in && st == -1;
-            const float ph = alive ? A.phi_v[vn] : 0.0f;
+            const float ph = alive && rd ? A.phi_v[vn] : 0.0f;
             const unsigned long long m = __ballot(alive);
             if (lane == 0) sh.wtot[wave] = __popcll(m);
             __syncthreads();
@@ -2237,9 +2268,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
             if (alive) {
                 const int q = carry + woff + mbcnt64(m);
-                A.aidx[b + q] = i;
-                A.aphi[b + q] = ph;
-                A.az[b + q] = zz;
+                if (small) {
+                    sh.aidx_s[q] = (uint16_t)i;
+                } else {
+                    A.aidx[b + q] = i;
+                    A.aphi[b + q] = ph;
+                    A.az[b + q] = zz;
+                }
             }
             carry += tot;
             __syncthreads();
@@ -2249,7 +2284,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int nbatch = (n_alive + kChunks * kWave - 1) / (kChunks * kWave);
         if (tid_x() == 0) sh.nalive = n_alive;
         const int ncand0 = sh.ncand;
-        if (nbatch == 1) load_batch(A, b, n_alive, 0, h);
+        if (small)
+            load_small(A, b, n_alive, sh.aidx_s, h);
+        else if (nbatch == 1)
+            load_batch(A, b, n_alive, 0, h);
         HOUGH_PHASE_MARK(kPhAlive);
 
         bool any = false;
@@ -2326,7 +2364,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         done = true;
                         if (npk > 0) {
                             any = true;
-                            associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh, nullptr);
+                            associate<NT>(A, cs, e, b, iter, L, L.sorted, A.hs_off, h, nbatch, npk, sh, nullptr, small);
                             HOUGH_PHASE_MARK(kPhAssoc);
                         }
                     }
@@ -2387,8 +2425,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             any = true;
                             // batch 0 back in registers (the peak ordering
                             // borrowed them), the rest still in LDS
-                            load_batch(A, b, n_alive, 0, h);
-                            associate<NT>(A, cs, e, b, iter, L, S.srt, A.hs_off, h, nbatch, npk, sh, xh);
+                            if (small)
+                                load_small(A, b, n_alive, sh.aidx_s, h);
+                            else
+                                load_batch(A, b, n_alive, 0, h);
+                            associate<NT>(A, cs, e, b, iter, L, S.srt, A.hs_off, h, nbatch, npk, sh, xh, small);
                             HOUGH_PHASE_MARK(kPhBigAssoc);
                         }
                     } else {
@@ -2432,7 +2473,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             if (npk == 0) break;
             any = true;
             const unsigned long long drop = sh.maxdrop;
-            associate<NT>(A, cs, e, b, iter, L, L.pbuf, A.tile_bytes, h, nbatch, npk, sh, nullptr);
+            associate<NT>(A, cs, e, b, iter, L, L.pbuf, A.tile_bytes, h, nbatch, npk, sh, nullptr, small);
             HOUGH_PHASE_MARK(kPhTiled);
             if (drop == 0ull) break;
             ceil_key = drop;
