@@ -897,6 +897,76 @@ __device__ __forceinline__ void recount(const FindArgs &A, const float2 *__restr
     }
 }
 
+// The same recount with one lane per bin, for when the hot set has enough
+// bins to keep every wave busy: the alive hits (one register batch) are
+// staged in LDS as (phi, z) pairs, and each lane tests all of them against
+// its own bin, two hits per broadcast LDS read, where the wave-per-bin
+// recount spends a ballot per 64-hit chunk and bin. The test takes the bin
+// as floor(u) (Eq. (4) in the same float steps), which for the finite u of a
+// valid hit equals the range test u in [k, k + 1): same counts.
+// stage: LDS room for n_alive (phi, z) pairs, 16-byte aligned.
+template <int NT>
+__device__ __forceinline__ void recount_lanes(const FindArgs &A, const float2 *__restrict__ cs,
+                                              unsigned long long *hs, const HitRegs &h, float4 *stage, int n_alive,
+                                              int n_hs, int *live_cnt) {
+    constexpr int NW = NT / kWave;
+    const int wave = wave_id();
+    const int lane = lane_id();
+    float2 *const st2 = reinterpret_cast<float2 *>(stage);
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const int q = c * kWave + lane;
+        if (c % NW == wave && c < h.nch && q < n_alive) st2[q] = make_float2(h.phi[c], h.z[c]);
+    }
+    __syncthreads();
+    const int npair = n_alive >> 1;
+    for (int e0 = wave * kWave; e0 < n_hs; e0 += NT) {
+        const int e = e0 + lane;
+        const unsigned long long key = e < n_hs ? hs[e] : 0ull;
+        const unsigned long long live = __ballot(key != 0ull);
+        if (live == 0ull) continue;
+        if (lane == 0) atomicAdd(live_cnt, __popcll(live));
+        const uint32_t flat = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
+        const int j = key != 0ull ? (int)(flat / (uint32_t)A.n_rho) : 0;
+        const int k = (int)(flat - (uint32_t)j * (uint32_t)A.n_rho);
+        const float2 t = cs[j];
+        int cnt = 0;
+        int p = 0;
+        // four reads in flight per step
+        for (; p + 4 <= npair; p += 4) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = stage[p + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cnt += rho_bin(v[u].x, v[u].y, t.x, t.y, A.rho_min, A.inv_w) == k ? 1 : 0;
+                cnt += rho_bin(v[u].z, v[u].w, t.x, t.y, A.rho_min, A.inv_w) == k ? 1 : 0;
+            }
+        }
+        for (; p < npair; ++p) {
+            const float4 v = stage[p];
+            cnt += rho_bin(v.x, v.y, t.x, t.y, A.rho_min, A.inv_w) == k ? 1 : 0;
+            cnt += rho_bin(v.z, v.w, t.x, t.y, A.rho_min, A.inv_w) == k ? 1 : 0;
+        }
+        if (n_alive & 1) {
+            const float2 v = st2[n_alive - 1];
+            cnt += rho_bin(v.x, v.y, t.x, t.y, A.rho_min, A.inv_w) == k ? 1 : 0;
+        }
+        if (key != 0ull) hs[e] = (uint32_t)cnt >= A.min_votes ? bin_key((uint32_t)cnt, flat) : 0ull;
+    }
+}
+
+// Whether the lane-per-bin recount issues fewer instructions than the
+// wave-per-bin one for this hot set and batch (per wave, about 8 per hit
+// and group of 64 bins against about 11 per chunk and 10 per bin).
+template <int NT>
+__device__ __forceinline__ bool recount_by_lanes(int n_hs, int n_alive, int nch) {
+    constexpr int NW = NT / kWave;
+    const int groups = ((n_hs + kWave - 1) / kWave + NW - 1) / NW;
+    const int per_wave = (n_hs + NW - 1) / NW;
+    return groups * n_alive * 8 < per_wave * (11 * nch + 10);
+}
+
 // ---------------------------------------------------------------------------
 // Large events: more alive hits than the registers hold, or more bins at or
 // above T (or more peaks) than the LDS lists hold. The workgroup takes a slot
@@ -2326,22 +2396,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     case N:                                                                                                    \
         recount<NT, N>(A, cs, L.hs, h, nullptr, 0, n_alive, n_hs, &sh.rlive);                                  \
         break;
-                    switch (h.nch) {
-                        HOUGH_RECOUNT_CASE(1)
-                        HOUGH_RECOUNT_CASE(2)
-                        HOUGH_RECOUNT_CASE(3)
-                        HOUGH_RECOUNT_CASE(4)
-                        HOUGH_RECOUNT_CASE(5)
-                        HOUGH_RECOUNT_CASE(6)
-                        HOUGH_RECOUNT_CASE(7)
-                        HOUGH_RECOUNT_CASE(8)
-                    default: break;
+                    // (the lane-per-bin form stages the hits in the row
+                    // buffers, free until the window test)
+                    const bool by_lanes = recount_by_lanes<NT>(n_hs, n_alive, h.nch);
+                    if (by_lanes) {
+                        recount_lanes<NT>(A, cs, L.hs, h, reinterpret_cast<float4 *>(L.tile), n_alive, n_hs,
+                                          &sh.rlive);
+                    } else {
+                        switch (h.nch) {
+                            HOUGH_RECOUNT_CASE(1)
+                            HOUGH_RECOUNT_CASE(2)
+                            HOUGH_RECOUNT_CASE(3)
+                            HOUGH_RECOUNT_CASE(4)
+                            HOUGH_RECOUNT_CASE(5)
+                            HOUGH_RECOUNT_CASE(6)
+                            HOUGH_RECOUNT_CASE(7)
+                            HOUGH_RECOUNT_CASE(8)
+                        default: break;
+                        }
                     }
 #undef HOUGH_RECOUNT_CASE
                     ++recounts;
                     __syncthreads();
                     HOUGH_PHASE_MARK(kPhRecount);
-                    evals += (unsigned long long)sh.rlive * (unsigned long long)(h.nch * kWave);
+                    evals += (unsigned long long)sh.rlive * (unsigned long long)(by_lanes ? n_alive : h.nch * kWave);
                 } else {
                     // row-stream sweep; a hot set larger than LDS holds
                     // sends the event to the large-event path below
