@@ -1950,6 +1950,13 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     int *pbase = reinterpret_cast<int *>(rp + (size_t)pb * W);
     int *pst = pbase + pb;
     int *elist = pst + pb;
+    // large-event path: the LDS after the LDS-resident hits (free during the
+    // association) takes the unclaimed hits of a pass, compacted: (phi, z)
+    // and the alive position of each
+    const int coff = A.hs_off + (((W > kChunks ? W - kChunks : 0) * kWave * 8 + 15) & ~15);
+    const int cap_c = xh != nullptr ? max(0, (A.tile_bytes - coff) / 12) : 0;
+    float2 *const cp = reinterpret_cast<float2 *>(reinterpret_cast<unsigned char *>(L.tile) + coff);
+    int *const cq = reinterpret_cast<int *>(cp + cap_c);
 
     // coordinates and (cos, sin) of the first pass's peaks, read ahead so
     // that this device-memory read overlaps the one of the claimed hits
@@ -1988,9 +1995,74 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
                 pcs[p] = cs[j];
             }
         }
+        // Once a quarter of the alive hits are claimed (a large event's
+        // later passes: its first peaks claim most hits), the masks are taken
+        // over the unclaimed hits alone, compacted, and scattered to their
+        // alive positions. Every claim reads M & ~icl, so the bits of claimed
+        // hits may stay 0: same claims.
+        int n_c = 0;
+        if (cap_c > 0) {
+            int u = 0;
+            for (int w = lane; w < W; w += kWave) {
+                const unsigned long long vm = w < W - 1 || (n_alive & (kWave - 1)) == 0
+                                                  ? ~0ull
+                                                  : (1ull << (n_alive & (kWave - 1))) - 1ull;
+                u += __popcll(~icl[w] & vm);
+            }
+            n_c = __builtin_amdgcn_readlane(wave_incl_scan(u), kWave - 1);
+        }
+        const bool use_c = cap_c > 0 && n_c <= cap_c && 4 * n_c <= 3 * n_alive;
+        if (use_c) {
+            for (int ch = wave; ch < W; ch += NW) {
+                const unsigned long long vm = ch < W - 1 || (n_alive & (kWave - 1)) == 0
+                                                  ? ~0ull
+                                                  : (1ull << (n_alive & (kWave - 1))) - 1ull;
+                const unsigned long long un = ~icl[ch] & vm;
+                // unclaimed hits of the earlier (whole) chunks
+                int before = 0;
+                for (int w = lane; w < ch; w += kWave) before += __popcll(~icl[w]);
+                before = __builtin_amdgcn_readlane(wave_incl_scan(before), kWave - 1);
+                if ((un >> lane) & 1ull) {
+                    float ph = 0.0f, zz = 0.0f;
+                    if (ch < kChunks) {
+#pragma unroll
+                        for (int c = 0; c < kChunks; ++c) {
+                            ph = c == ch ? h.phi[c] : ph;
+                            zz = c == ch ? h.z[c] : zz;
+                        }
+                    } else {
+                        const float2 v = xh[(ch - kChunks) * kWave + lane];
+                        ph = v.x;
+                        zz = v.y;
+                    }
+                    const int r = before + mbcnt64(un);
+                    cp[r] = make_float2(ph, zz);
+                    cq[r] = ch * kWave + lane;
+                }
+            }
+            for (int i = tid_x(); i < nb * W; i += NT) M[i] = 0ull;
+        }
         __syncthreads();
         // A: match masks
-        if (xh != nullptr && nbatch > 1) {
+        if (use_c) {
+            const int Wc = (n_c + kWave - 1) / kWave;
+            for (int p = wave; p < nb; p += NW) {
+                const int kp = dec[p].y;
+                const float2 t = pcs[p];
+                const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
+                unsigned long long *const mp = M + (size_t)p * W;
+                for (int c = 0; c < Wc; ++c) {
+                    const int r = c * kWave + lane;
+                    const bool v = r < n_c;
+                    const float2 pz = v ? cp[r] : make_float2(0.0f, 0.0f);
+                    const bool in = v && rho_in(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w, lo, hi);
+                    if (__ballot(in) != 0ull && in) {
+                        const int q = cq[r];
+                        atomicOr(&mp[q >> 6], 1ull << (q & (kWave - 1)));
+                    }
+                }
+            }
+        } else if (xh != nullptr && nbatch > 1) {
             // the first 512 alive hits in registers, the rest in LDS at xh
             for (int p = wave; p < nb; p += NW) {
                 const int kp = dec[p].y;

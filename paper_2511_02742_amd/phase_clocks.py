@@ -6,7 +6,7 @@ phase clocks on, and prints the mean cycles per event of each phase (thread
 0's cycle counter between workgroup barriers) with the share of the event's
 total. Workloads: the 4096-event pileup-50 batch on the default launch shape
 and on a 512-thread, 14-row-tile shape (two events per CU), and one-event
-calls at pileup 50 and 100. ``--out NAME`` also writes profiles/NAME.md.
+calls at pileup 50, 100 and 150. ``--out NAME`` also writes profiles/NAME.md.
 
 python -m paper_2511_02742_amd.phase_clocks [--out k_find_phases]
 """
@@ -59,7 +59,7 @@ def main():
     run("4096 pileup-50 events, 1024 threads, 30-row tile", HoughFinder(0), b50)
     run("4096 pileup-50 events, 512 threads, 14-row tile", HoughFinder(0, wg_threads=512, tile_rows=14), b50)
     f = HoughFinder(0)
-    for pile in (50, 100):
+    for pile in (50, 100, 150):
         acc = []
         for s in range(16):
             one = eventgen.make_batch([eventgen.pileup_event(60000 + s, n_tracks=pile)])
