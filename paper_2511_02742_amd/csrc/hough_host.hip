@@ -75,6 +75,11 @@ constexpr int kSingleSweepThreads = 256;
 constexpr int kSmallCall = 8;
 constexpr int kBandCall = 64;             // calls of up to this many events may run k_band
 constexpr int64_t kRegisterHits = 512;    // alive hits the finder holds in registers
+// k_band also takes events of fewer hits than the register batch, from this
+// many on: about where a pileup event's window-test peaks outgrow the
+// finder's LDS peak list (1024 entries), which sends it to the large-event
+// path after a wasted row-stream sweep
+constexpr int64_t kBandMinHits = 448;
 }  // namespace
 thread_local std::string g_last_global_error;
 
@@ -414,6 +419,7 @@ hough_status ensure_workspace(const Ctx &c, Workspace &w, int64_t n_hits, int64_
 hough::FindArgs find_args(const Ctx &c, const Workspace &w) {
     hough::FindArgs a{};
     const hough_config &g = c.cfg;
+    a.band_min = (int32_t)kRegisterHits;
     a.n_theta = g.n_theta;
     a.n_rho = g.n_rho;
     a.n_vanes = g.n_vanes;
@@ -487,6 +493,11 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     a.vane = vane;
     a.max_iters = max_iters;
     const bool single = n_events == 1 && !ws_only;
+    // k_band: a call of a few tens of events sweeps its large events' first
+    // band ahead of the finder, over one workgroup per finder wave each
+    const bool band = n_events > 0 && n_events <= kBandCall && c.band_split && c.sweep_groups == 0 &&
+                      !total_is_bound && w.pool_slots >= n_events && n_total > kBandMinHits;
+    a.band_min = band ? (int32_t)kBandMinHits : (int32_t)kRegisterHits;
     if (single) {
         a.counts = counts;
         a.cand_ws = cand;
@@ -494,9 +505,9 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
     }
     if (n_events > 0 && n_events <= kSmallCall && c.single_split && a.g_hs == nullptr) {
         // a few events: each one's first sweep spread over several workgroups
-        // (the sweep kernel takes events of up to 512 hits, the register
-        // batch; a lone larger event skips it)
-        if (!(n_events == 1 && n_total > kRegisterHits && !total_is_bound)) {
+        // (the sweep kernel takes events of up to band_min hits; a lone
+        // larger event skips it)
+        if (!(n_events == 1 && n_total > a.band_min && !total_is_bound)) {
             a.g_hs = w.g_hs;
             hipError_t ss = hough::launch_sweep(a, kSingleSweepThreads, kSingleSweepGroups, s);
             if (ss != hipSuccess)
@@ -506,12 +517,9 @@ hough_status enqueue_find(Ctx &c, Workspace &w, hipStream_t s, int32_t n_events,
         hipError_t ss = hough::launch_sweep(a, c.sweep_threads, c.sweep_groups, s);
         if (ss != hipSuccess) return fail(&c, HOUGH_ERR_DEVICE, std::string("sweep launch failed: ") + hipGetErrorString(ss));
     }
-    if (n_events > 0 && n_events <= kBandCall && c.band_split && c.sweep_groups == 0 && !total_is_bound &&
-        w.pool_slots >= n_events && n_total > kRegisterHits) {
-        // a call of a few tens of events: its large events' first banded
-        // sweeps over one workgroup per finder wave each (slot e of the pool
-        // reserved for large event e; an event k_band does not take finds
-        // at least its own slot free)
+    if (band) {
+        // slot e of the pool reserved for large event e; an event k_band
+        // does not take finds at least its own slot free
         a.b_ok = w.b_ok;
         a.b_slot = w.b_slot;
         a.b_cnt = w.b_cnt;

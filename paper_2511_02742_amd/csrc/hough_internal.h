@@ -108,6 +108,9 @@ struct FindArgs {
     // b_cnt[e * NW + w] the peaks of the finder wave w's rows
     int32_t *b_ok, *b_slot, *b_cnt;
     int32_t b_events;
+    // events of more hits than this are k_band's (and not the split sweep
+    // kernel's); at least 512 (the register batch) when k_band does not run
+    int32_t band_min;
 };
 
 // Records the event's start and retire clock stamps when the call asked for

@@ -2438,7 +2438,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // the large-event path; once fewer hits are left the next one sweeps
         // row by row again (a fresh histogram either way), unless the hot set
         // or the peak list outgrew LDS in an earlier iteration
-        big = big_lds || nbatch > 1;
+        // (and the first iteration of an event whose first band k_band swept)
+        big = big_lds || nbatch > 1 || (iter == 0 && sh.pre == NW);
         // (the LDS-resident hits are read in whole 64-hit chunks, at most
         // 56 of them: the banded sweep flags hot votes in 64 bits)
         if (A.stream_ok && n_alive <= kChunks * kWave + min(A.hs_cap & ~(kWave - 1), 56 * kWave)) {
@@ -2686,7 +2687,7 @@ __global__ __launch_bounds__(NT) void k_sweep(FindArgs A, const float2 *__restri
     const int lane = lane_id();
     const int64_t b = A.offsets[e];
     const int64_t n64 = A.offsets[e + 1] - b;
-    if (b < 0 || n64 < 0 || b + n64 > A.n_total || n64 > kChunks * kWave) {
+    if (b < 0 || n64 < 0 || b + n64 > A.n_total || n64 > min(A.band_min, kChunks * kWave)) {
         if (tid_x() == 0) A.g_flag[e] = 1;
         return;
     }
@@ -2748,11 +2749,11 @@ __global__ __launch_bounds__(NTB) void k_band(FindArgs A, const float2 *__restri
     const int64_t b = uniform64(A.offsets[e]);
     const int64_t n64 = uniform64(A.offsets[e + 1]) - b;
     const int xmax = kChunks * kWave + min(A.hs_cap & ~(kWave - 1), 56 * kWave);
-    if (A.peak_mode != 1 || !A.stream_ok || !A.big_ok || b < 0 || n64 <= kChunks * kWave || n64 > xmax ||
+    if (A.peak_mode != 1 || !A.stream_ok || !A.big_ok || b < 0 || n64 <= A.band_min || n64 > xmax ||
         b + n64 > A.n_total)
         return;
     const int n = (int)n64;
-    if (!band_ring_ok_nw(A, n, (n - kChunks * kWave + kWave - 1) / kWave, nwf)) return;
+    if (!band_ring_ok_nw(A, n, max(0, (n - kChunks * kWave + kWave - 1) / kWave), nwf)) return;
     // LDS: the hits | per wave: three 16-bit rows, three row lists, peaks |
     // a dummy word per lane
     const int hw = A.pitch / 2;

@@ -250,17 +250,19 @@ def test_overflowing_hot_and_peak_lists(gpu_available):
 def test_hot_set_overflow_takes_the_large_path(gpu_available):
     # few enough hits for the row-stream sweep, but far more bins reach T than
     # the LDS hot set holds: the iteration is redone with the hot set, the
-    # window test and the peak list in a device-memory slot
+    # window test and the peak list in a device-memory slot. A lone event of
+    # more than 448 hits has its first band swept ahead by k_band instead, so
+    # its first iteration takes the large-event path at once
     rng = np.random.default_rng(10)
-    n = 480
-    e = eventgen.pileup_event(2)
-    e.z = rng.uniform(-200, 200, n).astype(np.float32)
-    e.vane = rng.integers(0, 40, n).astype(np.int16)
-    e.r = np.zeros(n, np.float32)
-    e.track = np.zeros(n, np.int32)
-    b = eventgen.make_batch([e])
-    got, want = check_batch(b, "hot set overflow", n_theta=64, n_rho=256, min_votes=2)
-    assert got[2]["hotset_full"] > 0 and got[2]["large"] > 0 and got[2]["tiled"] == 0, got[2]
+    for n, overflow in ((440, True), (480, False)):
+        e = eventgen.pileup_event(2)
+        e.z = rng.uniform(-200, 200, n).astype(np.float32)
+        e.vane = rng.integers(0, 40, n).astype(np.int16)
+        e.r = np.zeros(n, np.float32)
+        e.track = np.zeros(n, np.int32)
+        b = eventgen.make_batch([e])
+        got, want = check_batch(b, "hot set overflow %d" % n, n_theta=64, n_rho=256, min_votes=2)
+        assert (got[2]["hotset_full"] > 0) == overflow and got[2]["large"] > 0 and got[2]["tiled"] == 0, got[2]
 
 
 def test_unsafe_hits_take_the_tiled_path(gpu_available):
@@ -310,6 +312,25 @@ def test_small_call_large_events_mixed(gpu_available, kw):
     again = run_batch(f, b)
     assert_same(again, want, "small mixed call again " + str(kw))
     assert_same(first, want, "small mixed call first " + str(kw))
+
+
+@pytest.mark.parametrize("kw", [{}, {"wg_threads": 512, "tile_rows": 14}])
+def test_small_call_band_below_register_batch(gpu_available, kw):
+    # events of 449..512 hits (within the register batch, but with more
+    # window-test peaks than the finder's LDS list holds): in a call of a few
+    # events their first banded sweep is also done ahead by k_band and the
+    # finder's first iteration takes the large-event path directly
+    evs = [eventgen.pileup_event(7711, n_tracks=90), eventgen.pileup_event(7738, n_tracks=90),
+           eventgen.pileup_event(7708, n_tracks=90), eventgen.pileup_event(7601, n_tracks=10),
+           eventgen.pileup_event(7604, n_tracks=120)]
+    sizes = [int(n) for n in np.diff(eventgen.make_batch(evs).offsets)]
+    assert all(448 < n <= 512 for n in sizes[:3]) and sizes[3] < 448 and sizes[4] > 512, sizes
+    for e in range(3):
+        one = eventgen.make_batch([evs[e]])
+        got1, _ = check_batch(one, "band below 512 alone %d %s" % (e, kw), **kw)
+        assert got1[2]["large"] > 0 and got1[2]["tiled"] == 0, got1[2]
+    got, want = check_batch(eventgen.make_batch(evs), "band below 512 mixed " + str(kw), **kw)
+    assert got[2]["large"] >= 4 and got[2]["tiled"] == 0, got[2]
 
 
 @pytest.mark.parametrize("kw", [{"sweep_groups": 4}, {"wg_threads": 512}, {"peak_mode": 0, "max_iters": 12},
