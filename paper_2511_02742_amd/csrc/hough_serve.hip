@@ -504,55 +504,70 @@ hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t
     for (int32_t r = 0; r < n; ++r)
         if (offsets[r + 1] < offsets[r] || offsets[r] < 0) return HOUGH_ERR_INVALID_ARG;
     if (n > 0 && offsets[n] > offsets[0] && (!z || !vane)) return HOUGH_ERR_INVALID_ARG;
-    std::vector<Result> refused;
-    int32_t r = 0;
-    {
-        std::unique_lock<std::mutex> g(s->mq);
-        const double t = s->now();
-        for (; r < n; ++r) {
-            const int64_t b = offsets[r];
-            const int64_t cnt = offsets[r + 1] - b;
-            const uint64_t tag = tags ? tags[r] : (uint64_t)r;
-            const double ta = t_arrival ? t_arrival[r] : t;
-            hough_status bad = HOUGH_OK;
-            if (cnt > s->sc.max_batch_hits || cnt > HOUGH_MAX_EVENT_HITS ||
-                s->block_bytes(1, cnt) > s->arena.size)
-                bad = HOUGH_ERR_CAPACITY;
-            else if (!valid_hits(*s, z, vane, b, cnt))
-                bad = HOUGH_ERR_DATA;
-            if (bad) {
-                Result R;
-                R.rec.tag = tag;
-                R.rec.status = bad;
-                R.rec.n_hits = (int32_t)std::min<int64_t>(cnt, 0x7fffffff);
-                R.rec.lane = -1;
-                R.rec.t_arrival = ta;
-                R.rec.t_admit = t;
-                R.rec.t_done = t;
-                refused.push_back(std::move(R));
-                s->st.refused += 1;
-                s->st.completed += 1;
-                continue;
-            }
-            if ((int64_t)s->queue.size() + 1 > s->sc.queue_events || s->q_hits + cnt > s->sc.queue_hits) break;
-            Request q;
-            q.tag = tag;
-            q.t_arrival = ta;
-            q.n = (int32_t)cnt;
+    // the requests are validated and copied outside the queue lock, then
+    // moved in a few hundred at a time: a large submission never holds the
+    // dispatcher's admission for long
+    const double t = s->now();
+    std::vector<Request> built((size_t)n);
+    std::vector<hough_status> bad_of((size_t)n, HOUGH_OK);
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t b = offsets[i];
+        const int64_t cnt = offsets[i + 1] - b;
+        Request &q = built[(size_t)i];
+        q.tag = tags ? tags[i] : (uint64_t)i;
+        q.t_arrival = t_arrival ? t_arrival[i] : t;
+        q.n = (int32_t)std::min<int64_t>(cnt, 0x7fffffff);
+        if (cnt > s->sc.max_batch_hits || cnt > HOUGH_MAX_EVENT_HITS || s->block_bytes(1, cnt) > s->arena.size)
+            bad_of[(size_t)i] = HOUGH_ERR_CAPACITY;
+        else if (!valid_hits(*s, z, vane, b, cnt))
+            bad_of[(size_t)i] = HOUGH_ERR_DATA;
+        if (bad_of[(size_t)i] == HOUGH_OK) {
             q.z.assign(z + b, z + b + cnt);
             q.vane.assign(vane + b, vane + b + cnt);
-            s->queue.push_back(std::move(q));
-            s->q_hits += cnt;
-            s->st.submitted += 1;
-            s->st.pending_events += 1;
-            s->st.max_pending_events = std::max(s->st.max_pending_events, s->st.pending_events);
         }
+    }
+    constexpr int32_t kPushChunk = 256;
+    std::vector<Result> refused;
+    int32_t r = 0;
+    bool full = false;
+    while (r < n && !full) {
+        {
+            std::unique_lock<std::mutex> g(s->mq);
+            const int32_t end = std::min(n, r + kPushChunk);
+            for (; r < end; ++r) {
+                Request &q = built[(size_t)r];
+                if (bad_of[(size_t)r] != HOUGH_OK) {
+                    Result R;
+                    R.rec.tag = q.tag;
+                    R.rec.status = bad_of[(size_t)r];
+                    R.rec.n_hits = q.n;
+                    R.rec.lane = -1;
+                    R.rec.t_arrival = q.t_arrival;
+                    R.rec.t_admit = t;
+                    R.rec.t_done = t;
+                    refused.push_back(std::move(R));
+                    s->st.refused += 1;
+                    s->st.completed += 1;
+                    continue;
+                }
+                if ((int64_t)s->queue.size() + 1 > s->sc.queue_events || s->q_hits + q.n > s->sc.queue_hits) {
+                    full = true;
+                    break;
+                }
+                const int64_t cnt = q.n;
+                s->queue.push_back(std::move(q));
+                s->q_hits += cnt;
+                s->st.submitted += 1;
+                s->st.pending_events += 1;
+                s->st.max_pending_events = std::max(s->st.max_pending_events, s->st.pending_events);
+            }
+        }
+        s->cv.notify_all();
     }
     if (!refused.empty()) {
         std::lock_guard<std::mutex> g(s->mr);
         for (Result &R : refused) s->results.push_back(std::move(R));
     }
-    s->cv.notify_all();
     *n_accepted = r;
     return HOUGH_OK;
 }
@@ -564,13 +579,31 @@ hough_status hough_server_poll(hough_server *server, int32_t max_results, hough_
     if (!s || max_results < 0 || !n_results || (max_results > 0 && !results) || cand_capacity < 0 ||
         hit_capacity < 0 || (cand_capacity > 0 && !cand) || (hit_capacity > 0 && !hit_index))
         return HOUGH_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> g(s->mr);
-    int32_t k = 0;
+    // the results are taken off the list under its lock (moves) and copied
+    // out after it: the dispatcher's finished launches never wait for a copy
+    std::vector<Result> got;
+    {
+        std::lock_guard<std::mutex> g(s->mr);
+        int64_t nc_all = 0, nh_all = 0;
+        while ((int32_t)got.size() < max_results && !s->results.empty()) {
+            Result &R = s->results.front();
+            const int64_t nc = (int64_t)R.cand.size(), nh = (int64_t)R.hits.size();
+            if (nc_all + nc > cand_capacity || nh_all + nh > hit_capacity) break;
+            nc_all += nc;
+            nh_all += nh;
+            got.push_back(std::move(R));
+            s->results.pop_front();
+        }
+        // the oldest result alone is larger than the caller's arrays
+        if (got.empty() && max_results > 0 && !s->results.empty()) {
+            *n_results = 0;
+            return HOUGH_ERR_CAPACITY;
+        }
+    }
     int64_t co = 0, ho = 0;
-    while (k < max_results && !s->results.empty()) {
-        Result &R = s->results.front();
+    int32_t k = 0;
+    for (Result &R : got) {
         const int64_t nc = (int64_t)R.cand.size(), nh = (int64_t)R.hits.size();
-        if (co + nc > cand_capacity || ho + nh > hit_capacity) break;
         hough_served rec = R.rec;
         rec.cand_offset = co;
         rec.hit_offset = ho;
@@ -579,11 +612,8 @@ hough_status hough_server_poll(hough_server *server, int32_t max_results, hough_
         results[k++] = rec;
         co += nc;
         ho += nh;
-        s->results.pop_front();
     }
     *n_results = k;
-    // the oldest result alone is larger than the caller's arrays
-    if (k == 0 && max_results > 0 && !s->results.empty()) return HOUGH_ERR_CAPACITY;
     return HOUGH_OK;
 }
 
