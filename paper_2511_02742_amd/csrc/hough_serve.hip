@@ -26,6 +26,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -49,8 +50,11 @@ struct Request {
     uint64_t tag = 0;
     double t_arrival = 0.0;
     int32_t n = 0;
-    std::vector<float> z;
-    std::vector<int16_t> vane;
+    // the hits, inside the submit call's one copy of its hit arrays (shared
+    // by that call's requests, freed with the last of them)
+    std::shared_ptr<const std::vector<char>> blk;
+    const float *z = nullptr;
+    const int16_t *vane = nullptr;
 };
 
 struct Result {
@@ -178,8 +182,8 @@ struct Server {
             const Request &r = L.reqs[e];
             offs[e] = o;
             if (r.n > 0) {
-                std::memcpy(zz + o, r.z.data(), 4 * (size_t)r.n);
-                std::memcpy(vv + o, r.vane.data(), 2 * (size_t)r.n);
+                std::memcpy(zz + o, r.z, 4 * (size_t)r.n);
+                std::memcpy(vv + o, r.vane, 2 * (size_t)r.n);
             }
             o += r.n;
         }
@@ -510,6 +514,23 @@ hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t
     const double t = s->now();
     std::vector<Request> built((size_t)n);
     std::vector<hough_status> bad_of((size_t)n, HOUGH_OK);
+    // one copy of the call's hit arrays (z, then vane) for all its requests
+    const int64_t h0 = n > 0 ? offsets[0] : 0;
+    const int64_t nh = n > 0 ? offsets[n] - h0 : 0;
+    std::shared_ptr<std::vector<char>> blk;
+    const float *bz = nullptr;
+    const int16_t *bv = nullptr;
+    if (nh > 0) {
+        try {
+            blk = std::make_shared<std::vector<char>>((size_t)nh * 6);
+        } catch (...) {
+            return HOUGH_ERR_OOM;
+        }
+        std::memcpy(blk->data(), z + h0, 4 * (size_t)nh);
+        std::memcpy(blk->data() + 4 * (size_t)nh, vane + h0, 2 * (size_t)nh);
+        bz = reinterpret_cast<const float *>(blk->data());
+        bv = reinterpret_cast<const int16_t *>(blk->data() + 4 * (size_t)nh);
+    }
     for (int32_t i = 0; i < n; ++i) {
         const int64_t b = offsets[i];
         const int64_t cnt = offsets[i + 1] - b;
@@ -521,9 +542,10 @@ hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t
             bad_of[(size_t)i] = HOUGH_ERR_CAPACITY;
         else if (!valid_hits(*s, z, vane, b, cnt))
             bad_of[(size_t)i] = HOUGH_ERR_DATA;
-        if (bad_of[(size_t)i] == HOUGH_OK) {
-            q.z.assign(z + b, z + b + cnt);
-            q.vane.assign(vane + b, vane + b + cnt);
+        if (bad_of[(size_t)i] == HOUGH_OK && cnt > 0) {
+            q.blk = blk;
+            q.z = bz + (b - h0);
+            q.vane = bv + (b - h0);
         }
     }
     constexpr int32_t kPushChunk = 256;
