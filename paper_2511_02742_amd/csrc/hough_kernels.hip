@@ -1932,24 +1932,15 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     const int n_alive = sh.nalive;
     const int W = (n_alive + kWave - 1) / kWave;
     const int64_t cbase = b / (int64_t)A.min_votes;
-    const bool rounds = W <= kAssocRoundMaxW;
-
     // union area: icl[W] u64 | owner[64 W] (rounds only) | per peak of a
-    // pass: M[pb*W] u64 | pcs[pb] float2 | dec[pb] int2 | rp[pb*W] u32
-    //       | pbase[pb] | pst[pb] | elist[pb]
+    // pass: M[nb*W] u64 | pcs[nb] float2 | dec[nb] int2 | rp[nb*W] u32
+    //       | pbase[nb] | pst[nb] | elist[nb]
+    // A compacted pass (below) lays out the same arrays for its Wc words
+    // after icl and owner.
     unsigned char *uni = reinterpret_cast<unsigned char *>(L.tile);
     unsigned long long *icl = reinterpret_cast<unsigned long long *>(uni);
-    int *owner = reinterpret_cast<int *>(icl + W);
-    unsigned long long *M = reinterpret_cast<unsigned long long *>(uni + assoc_fixed_bytes(W));
     // at least one peak per pass: the host sizes uni_bytes for the largest W
-    int pb = (uni_bytes - assoc_fixed_bytes(W)) / assoc_peak_bytes(W);
-    pb = min(pb, npk);
-    float2 *pcs = reinterpret_cast<float2 *>(M + (size_t)pb * W);
-    int2 *dec = reinterpret_cast<int2 *>(pcs + pb);
-    uint32_t *rp = reinterpret_cast<uint32_t *>(dec + pb);
-    int *pbase = reinterpret_cast<int *>(rp + (size_t)pb * W);
-    int *pst = pbase + pb;
-    int *elist = pst + pb;
+    const int pb_full = min((uni_bytes - assoc_fixed_bytes(W)) / assoc_peak_bytes(W), npk);
     // large-event path: the LDS after the LDS-resident hits (free during the
     // association) takes the unclaimed hits of a pass, compacted: (phi, z)
     // and the alive position of each
@@ -1960,7 +1951,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
 
     // coordinates and (cos, sin) of the first pass's peaks, read ahead so
     // that this device-memory read overlaps the one of the claimed hits
-    const int nb0 = min(pb, npk);
+    const int nb0 = pb_full;
     int2 d0 = make_int2(0, 0);
     float2 t0 = make_float2(0.0f, 0.0f);
     if (nb0 <= NT && tid_x() < nb0) {
@@ -1978,11 +1969,48 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     }
     __syncthreads();
 
-    for (int p0 = 0; p0 < npk; p0 += pb) {
+    for (int p0 = 0; p0 < npk;) {
         HOUGH_PHASE_MARK(kPhAsPrep);
-        const int nb = min(pb, npk - p0);
+        // the alive hits not claimed yet
+        int n_c;
+        {
+            int u = 0;
+            for (int w = lane; w < W; w += kWave) {
+                const unsigned long long vm = w < W - 1 || (n_alive & (kWave - 1)) == 0
+                                                  ? ~0ull
+                                                  : (1ull << (n_alive & (kWave - 1))) - 1ull;
+                u += __popcll(~icl[w] & vm);
+            }
+            n_c = __builtin_amdgcn_readlane(wave_incl_scan(u), kWave - 1);
+        }
+        // fewer than T: every later peak is rejected
+        if (n_c < (int)A.min_votes) break;
+        // Once a quarter of the alive hits are claimed (a large event's
+        // later passes: its first peaks claim most hits, and thousands of
+        // window-test peaks remain), a pass works on the unclaimed hits
+        // alone, compacted in alive order: its masks, claims and hit-list
+        // words cover Wc words instead of W (so a pass holds more peaks),
+        // and the claimed hits go back to icl at their alive positions. A
+        // claimed hit matches no later claim anyway (every claim reads its
+        // matches less the claimed hits): same claims.
+        const int Wc = (n_c + kWave - 1) / kWave;
+        const int cfix = assoc_fixed_bytes(W);
+        const int pb_c = cap_c > 0 ? (uni_bytes - cfix - assoc_fixed_bytes(Wc)) / assoc_peak_bytes(Wc) : 0;
+        const bool use_c = cap_c > 0 && n_c <= cap_c && 4 * n_c <= 3 * n_alive && pb_c >= 1;
+        const int Wp = use_c ? Wc : W;
+        const int nb = use_c ? min(pb_c, npk - p0) : min(pb_full, npk - p0);
+        unsigned char *const base = uni + (use_c ? cfix : 0);
+        unsigned long long *const iclp = reinterpret_cast<unsigned long long *>(base);
+        int *const owner = reinterpret_cast<int *>(iclp + Wp);
+        unsigned long long *const M = reinterpret_cast<unsigned long long *>(base + assoc_fixed_bytes(Wp));
+        float2 *const pcs = reinterpret_cast<float2 *>(M + (size_t)nb * Wp);
+        int2 *const dec = reinterpret_cast<int2 *>(pcs + nb);
+        uint32_t *const rp = reinterpret_cast<uint32_t *>(dec + nb);
+        int *const pbase = reinterpret_cast<int *>(rp + (size_t)nb * Wp);
+        int *const pst = pbase + nb;
+        int *const elist = pst + nb;
         // coordinates and (cos, sin) of this pass's peaks
-        if (p0 == 0 && nb0 <= NT) {
+        if (p0 == 0 && !use_c && nb0 <= NT) {
             if (tid_x() < nb0) {
                 dec[tid_x()] = d0;
                 pcs[tid_x()] = t0;
@@ -1995,23 +2023,6 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
                 pcs[p] = cs[j];
             }
         }
-        // Once a quarter of the alive hits are claimed (a large event's
-        // later passes: its first peaks claim most hits), the masks are taken
-        // over the unclaimed hits alone, compacted, and scattered to their
-        // alive positions. Every claim reads M & ~icl, so the bits of claimed
-        // hits may stay 0: same claims.
-        int n_c = 0;
-        if (cap_c > 0) {
-            int u = 0;
-            for (int w = lane; w < W; w += kWave) {
-                const unsigned long long vm = w < W - 1 || (n_alive & (kWave - 1)) == 0
-                                                  ? ~0ull
-                                                  : (1ull << (n_alive & (kWave - 1))) - 1ull;
-                u += __popcll(~icl[w] & vm);
-            }
-            n_c = __builtin_amdgcn_readlane(wave_incl_scan(u), kWave - 1);
-        }
-        const bool use_c = cap_c > 0 && n_c <= cap_c && 4 * n_c <= 3 * n_alive;
         if (use_c) {
             for (int ch = wave; ch < W; ch += NW) {
                 const unsigned long long vm = ch < W - 1 || (n_alive & (kWave - 1)) == 0
@@ -2040,26 +2051,50 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
                     cq[r] = ch * kWave + lane;
                 }
             }
-            for (int i = tid_x(); i < nb * W; i += NT) M[i] = 0ull;
+            for (int w = tid_x(); w < Wc; w += NT) iclp[w] = 0ull;
         }
         __syncthreads();
         // A: match masks
-        if (use_c) {
-            const int Wc = (n_c + kWave - 1) / kWave;
+        if (use_c && Wc == 1) {
+            // at most 64 unclaimed hits: one lane per peak tests them all
+            // (one broadcast LDS read per hit) and builds the peak's word
+            for (int p = tid_x(); p < nb; p += NT) {
+                const int kp = dec[p].y;
+                const float2 t = pcs[p];
+                const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
+                unsigned long long m = 0ull;
+                int r = 0;
+                // eight hits per step, four 16-byte reads in flight
+                const float4 *const cp4 = reinterpret_cast<const float4 *>(cp);
+                for (; r + 8 <= n_c; r += 8) {
+                    float4 v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = cp4[(r >> 1) + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        m |= rho_in(v[u].x, v[u].y, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << (r + 2 * u) : 0ull;
+                        m |= rho_in(v[u].z, v[u].w, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << (r + 2 * u + 1)
+                                                                                          : 0ull;
+                    }
+                }
+                for (; r < n_c; ++r) {
+                    const float2 pz = cp[r];
+                    m |= rho_in(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << r : 0ull;
+                }
+                M[p] = m;
+            }
+        } else if (use_c) {
             for (int p = wave; p < nb; p += NW) {
                 const int kp = dec[p].y;
                 const float2 t = pcs[p];
                 const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
-                unsigned long long *const mp = M + (size_t)p * W;
                 for (int c = 0; c < Wc; ++c) {
                     const int r = c * kWave + lane;
                     const bool v = r < n_c;
                     const float2 pz = v ? cp[r] : make_float2(0.0f, 0.0f);
                     const bool in = v && rho_in(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w, lo, hi);
-                    if (__ballot(in) != 0ull && in) {
-                        const int q = cq[r];
-                        atomicOr(&mp[q >> 6], 1ull << (q & (kWave - 1)));
-                    }
+                    const unsigned long long m = __ballot(in);
+                    if (lane == 0) M[(size_t)p * Wc + c] = m;
                 }
             }
         } else if (xh != nullptr && nbatch > 1) {
@@ -2091,36 +2126,37 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
                     }
                 }
             }
-        }
-        for (int bt = 0; bt < nbatch && (xh == nullptr || nbatch == 1); ++bt) {
-            if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
+        } else {
+            for (int bt = 0; bt < nbatch; ++bt) {
+                if (nbatch > 1) load_batch(A, b, n_alive, bt, h);
 #define HOUGH_MASK_CASE(N)                                                                                     \
     case N:                                                                                                    \
         match_masks<N, NW>(A, h, dec, pcs, M, W, nb, n_alive, bt);                                             \
         break;
-            switch (h.nch) {
-                HOUGH_MASK_CASE(1)
-                HOUGH_MASK_CASE(2)
-                HOUGH_MASK_CASE(3)
-                HOUGH_MASK_CASE(4)
-                HOUGH_MASK_CASE(5)
-                HOUGH_MASK_CASE(6)
-                HOUGH_MASK_CASE(7)
-                HOUGH_MASK_CASE(8)
-            default: break;
-            }
+                switch (h.nch) {
+                    HOUGH_MASK_CASE(1)
+                    HOUGH_MASK_CASE(2)
+                    HOUGH_MASK_CASE(3)
+                    HOUGH_MASK_CASE(4)
+                    HOUGH_MASK_CASE(5)
+                    HOUGH_MASK_CASE(6)
+                    HOUGH_MASK_CASE(7)
+                    HOUGH_MASK_CASE(8)
+                default: break;
+                }
 #undef HOUGH_MASK_CASE
-            if (nbatch > 1) __syncthreads();
+                if (nbatch > 1) __syncthreads();
+            }
         }
         __syncthreads();
         HOUGH_PHASE_MARK(kPhAsMask);
         // B: which peaks claim which hits
-        if (W <= kClaimBlockW)
-            claim_block(A, icl, M, pst, W, nb);
-        else if (rounds)
-            claim_rounds<NT>(A, icl, M, pst, owner, W, nb, sh);
+        if (Wp <= kClaimBlockW)
+            claim_block(A, iclp, M, pst, Wp, nb);
+        else if (Wp <= kAssocRoundMaxW)
+            claim_rounds<NT>(A, iclp, M, pst, owner, Wp, nb, sh);
         else
-            claim_serial<NT>(A, icl, M, pst, W, nb);
+            claim_serial<NT>(A, iclp, M, pst, Wp, nb);
         __syncthreads();
         HOUGH_PHASE_MARK(kPhAsClaim);
         // emission order = key order of the taken peaks
@@ -2164,29 +2200,34 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
             cd.rho = A.rho_c[jk.y];
             A.cand_ws[cbase + cid0 + ei] = cd;
             uint32_t run = 0;
-            for (int w = 0; w < W; ++w) {
-                rp[(size_t)p * W + w] = run;
-                run += (uint32_t)__popcll(M[(size_t)p * W + w]);
+            for (int w = 0; w < Wp; ++w) {
+                rp[(size_t)p * Wp + w] = run;
+                run += (uint32_t)__popcll(M[(size_t)p * Wp + w]);
             }
         }
         __syncthreads();
         HOUGH_PHASE_MARK(kPhAsEmit);
-        // C: hit lists (ascending alive-list position = ascending hit index)
-        for (int t = wave; t < nemit * W; t += NW) {
-            const int ei = t / W;
-            const int ch = t - ei * W;
+        // C: hit lists (ascending alive-list position = ascending hit index;
+        // a compacted pass keeps alive order); a compacted pass also marks
+        // its claimed hits in icl
+        for (int t = wave; t < nemit * Wp; t += NW) {
+            const int ei = t / Wp;
+            const int ch = t - ei * Wp;
             const int p = elist[ei];
-            const unsigned long long m = M[(size_t)p * W + ch];
+            const unsigned long long m = M[(size_t)p * Wp + ch];
             if ((m >> lane) & 1ull) {
-                const int q = ch * kWave + lane;
+                const int qc = ch * kWave + lane;
+                const int q = use_c ? cq[qc] : qc;
                 const int il = small ? (int)sh.aidx_s[q] : A.aidx[b + q];
-                const int pos = pbase[p] + (int)rp[(size_t)p * W + ch] + mbcnt64(m);
+                const int pos = pbase[p] + (int)rp[(size_t)p * Wp + ch] + mbcnt64(m);
                 A.hits_ws[b + pos] = il;
                 A.state[b + il] = cid0 + ei;
+                if (use_c) atomicOr(&icl[q >> 6], 1ull << (q & (kWave - 1)));
             }
         }
         __syncthreads();
         HOUGH_PHASE_MARK(kPhAsLists);
+        p0 += nb;
     }
 }
 
