@@ -333,6 +333,21 @@ def test_small_call_band_below_register_batch(gpu_available, kw):
     assert got[2]["large"] >= 4 and got[2]["tiled"] == 0, got[2]
 
 
+@pytest.mark.parametrize("kw", [{"min_votes": 10}, {"min_votes": 12}, {"min_votes": 12, "wg_threads": 512, "tile_rows": 14}])
+def test_large_event_compacted_passes(gpu_available, kw):
+    # a large event's first peaks claim most of its hits; its later
+    # association passes run over the compacted unclaimed hits. At T = 6 a
+    # pileup-150 event leaves a few dozen unclaimed (one 64-hit word); higher
+    # thresholds leave a hundred or more (two or three words), which takes
+    # the wave-per-peak masks and the multi-word claims of a compacted pass
+    b = eventgen.pileup_batch(3, n_tracks=150, seed0=7900)
+    got, want = check_batch(b, "compacted passes " + str(kw), **kw)
+    assert got[2]["large"] > 0 and got[2]["tiled"] == 0, got[2]
+    one = eventgen.make_batch([b.events[0]])
+    got1, _ = check_batch(one, "compacted passes alone " + str(kw), **kw)
+    assert got1[2]["large"] > 0, got1[2]
+
+
 @pytest.mark.parametrize("kw", [{"sweep_groups": 4}, {"wg_threads": 512}, {"peak_mode": 0, "max_iters": 12},
                                 {"nms_radius": 2}, {"assoc_window": 1}, {"wg_threads": 512, "tile_rows": 14},
                                 {"wg_threads": 256, "tile_rows": 6}])
