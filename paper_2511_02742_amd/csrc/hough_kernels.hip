@@ -2055,46 +2055,37 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         }
         __syncthreads();
         // A: match masks
-        if (use_c && Wc == 1) {
-            // at most 64 unclaimed hits: one lane per peak tests them all
-            // (one broadcast LDS read per hit) and builds the peak's word
+        if (use_c) {
+            // one lane per peak: it tests the unclaimed hits (broadcast LDS
+            // reads, eight hits per step with four 16-byte reads in flight)
+            // against its peak, 64 at a time, and writes its Wc words
+            const float4 *const cp4 = reinterpret_cast<const float4 *>(cp);
             for (int p = tid_x(); p < nb; p += NT) {
                 const int kp = dec[p].y;
                 const float2 t = pcs[p];
                 const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
-                unsigned long long m = 0ull;
-                int r = 0;
-                // eight hits per step, four 16-byte reads in flight
-                const float4 *const cp4 = reinterpret_cast<const float4 *>(cp);
-                for (; r + 8 <= n_c; r += 8) {
-                    float4 v[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = cp4[(r >> 1) + u];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        m |= rho_in(v[u].x, v[u].y, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << (r + 2 * u) : 0ull;
-                        m |= rho_in(v[u].z, v[u].w, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << (r + 2 * u + 1)
-                                                                                          : 0ull;
-                    }
-                }
-                for (; r < n_c; ++r) {
-                    const float2 pz = cp[r];
-                    m |= rho_in(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << r : 0ull;
-                }
-                M[p] = m;
-            }
-        } else if (use_c) {
-            for (int p = wave; p < nb; p += NW) {
-                const int kp = dec[p].y;
-                const float2 t = pcs[p];
-                const float lo = (float)(kp - A.assoc_window), hi = (float)(kp + A.assoc_window + 1);
                 for (int c = 0; c < Wc; ++c) {
-                    const int r = c * kWave + lane;
-                    const bool v = r < n_c;
-                    const float2 pz = v ? cp[r] : make_float2(0.0f, 0.0f);
-                    const bool in = v && rho_in(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w, lo, hi);
-                    const unsigned long long m = __ballot(in);
-                    if (lane == 0) M[(size_t)p * Wc + c] = m;
+                    const int r0 = c * kWave;
+                    const int r1 = min(n_c, r0 + kWave);
+                    unsigned long long m = 0ull;
+                    int r = r0;
+                    for (; r + 8 <= r1; r += 8) {
+                        float4 v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[u] = cp4[(r >> 1) + u];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int sh0 = r - r0 + 2 * u;
+                            m |= rho_in(v[u].x, v[u].y, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << sh0 : 0ull;
+                            m |= rho_in(v[u].z, v[u].w, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << (sh0 + 1)
+                                                                                              : 0ull;
+                        }
+                    }
+                    for (; r < r1; ++r) {
+                        const float2 pz = cp[r];
+                        m |= rho_in(pz.x, pz.y, t.x, t.y, A.rho_min, A.inv_w, lo, hi) ? 1ull << (r - r0) : 0ull;
+                    }
+                    M[(size_t)p * Wc + c] = m;
                 }
             }
         } else if (xh != nullptr && nbatch > 1) {
