@@ -1875,6 +1875,58 @@ __device__ __forceinline__ void claim_block_w(const FindArgs &A, unsigned long l
 }
 
 // claim_block_w for the event's word count (W <= kClaimBlockW)
+// The same register claims for 9 to WM words (a large event's first pass):
+// the words past W count as claimed and are never written back.
+template <int WM>
+__device__ __forceinline__ void claim_block_wr(const FindArgs &A, unsigned long long *icl, unsigned long long *M,
+                                               int *pst, int W, int nb) {
+    if (wave_id() != 0) return;
+    const int lane = lane_id();
+    const int T = (int)A.min_votes;
+    unsigned long long c[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) c[w] = w < W ? uniform64(icl[w]) : ~0ull;
+    for (int p0 = 0; p0 < nb; p0 += kWave) {
+        const int p = p0 + lane;
+        unsigned long long *mp = M + (size_t)(p < nb ? p : p0) * W;
+        unsigned long long m[WM];
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            m[w] = w < W ? mp[w] : 0ull;
+            cnt += __popcll(m[w] & ~c[w]);
+        }
+        int res = -1;
+        unsigned long long open = __ballot(p < nb && cnt >= T);
+        while (open) {
+            const int q = __ffsll((long long)open) - 1;
+            int drop = 0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                const unsigned long long t = readlane64(m[w], q) & ~c[w];
+                drop += __popcll(m[w] & t);
+                c[w] |= t;
+                if (lane == q) m[w] = t;
+            }
+            if (lane == q) res = cnt;
+            if (lane > q) cnt -= drop;
+            open = __ballot(lane > q && p < nb && cnt >= T);
+        }
+        if (p < nb) {
+            pst[p] = res;
+            if (res >= 0) {
+#pragma unroll
+                for (int w = 0; w < WM; ++w)
+                    if (w < W) mp[w] = m[w];
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < WM; ++w)
+            if (w < W) icl[w] = c[w];
+    }
+}
 __device__ __forceinline__ void claim_block(const FindArgs &A, unsigned long long *icl, unsigned long long *M, int *pst,
                                             int W, int nb) {
     switch (W) {
@@ -2144,6 +2196,8 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         // B: which peaks claim which hits
         if (Wp <= kClaimBlockW)
             claim_block(A, iclp, M, pst, Wp, nb);
+        else if (Wp <= 2 * kClaimBlockW)
+            claim_block_wr<2 * kClaimBlockW>(A, iclp, M, pst, Wp, nb);
         else if (Wp <= kAssocRoundMaxW)
             claim_rounds<NT>(A, iclp, M, pst, owner, Wp, nb, sh);
         else
