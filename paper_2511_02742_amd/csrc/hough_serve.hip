@@ -512,20 +512,22 @@ hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t
     // moved in a few hundred at a time: a large submission never holds the
     // dispatcher's admission for long
     const double t = s->now();
-    std::vector<Request> built((size_t)n);
-    std::vector<hough_status> bad_of((size_t)n, HOUGH_OK);
+    std::vector<Request> built;
+    std::vector<hough_status> bad_of;
     // one copy of the call's hit arrays (z, then vane) for all its requests
     const int64_t h0 = n > 0 ? offsets[0] : 0;
     const int64_t nh = n > 0 ? offsets[n] - h0 : 0;
     std::shared_ptr<std::vector<char>> blk;
     const float *bz = nullptr;
     const int16_t *bv = nullptr;
+    try {
+        built.resize((size_t)n);
+        bad_of.assign((size_t)n, HOUGH_OK);
+        if (nh > 0) blk = std::make_shared<std::vector<char>>((size_t)nh * 6);
+    } catch (...) {
+        return HOUGH_ERR_OOM;
+    }
     if (nh > 0) {
-        try {
-            blk = std::make_shared<std::vector<char>>((size_t)nh * 6);
-        } catch (...) {
-            return HOUGH_ERR_OOM;
-        }
         std::memcpy(blk->data(), z + h0, 4 * (size_t)nh);
         std::memcpy(blk->data() + 4 * (size_t)nh, vane + h0, 2 * (size_t)nh);
         bz = reinterpret_cast<const float *>(blk->data());
