@@ -440,7 +440,10 @@ double hough_server_clock(const hough_server *server);
  * hit, more than max_batch_hits hits, or a launch of their own larger than
  * the device arena become results with an error status at once. *n_accepted receives how many requests, from the first, were
  * taken; it is less than n only when the queue is full (back-pressure: submit
- * the rest later). Returns HOUGH_ERR_INVALID_ARG for bad pointers or offsets.
+ * the rest later). The call holds the queue only to move its requests in, a
+ * few hundred at a time. Returns HOUGH_ERR_INVALID_ARG for bad pointers or
+ * offsets, HOUGH_ERR_OOM (nothing queued) if the host copy of the call's hits
+ * cannot be allocated.
  */
 hough_status hough_server_submit(hough_server *server, int32_t n, const uint64_t *tags, const int64_t *offsets,
                                  const float *z, const int16_t *vane, const double *t_arrival,
