@@ -2001,9 +2001,11 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
     float2 *const cp = reinterpret_cast<float2 *>(reinterpret_cast<unsigned char *>(L.tile) + coff);
     int *const cq = reinterpret_cast<int *>(cp + cap_c);
 
+    // A large event's first pass takes only its 64 strongest peaks: they
+    // claim most of its hits, and the passes after it can run compacted.
+    const int nb0 = xh != nullptr ? min(kWave, pb_full) : pb_full;
     // coordinates and (cos, sin) of the first pass's peaks, read ahead so
     // that this device-memory read overlaps the one of the claimed hits
-    const int nb0 = pb_full;
     int2 d0 = make_int2(0, 0);
     float2 t0 = make_float2(0.0f, 0.0f);
     if (nb0 <= NT && tid_x() < nb0) {
@@ -2050,7 +2052,7 @@ __device__ __forceinline__ void associate(const FindArgs &A, const float2 *__res
         const int pb_c = cap_c > 0 ? (uni_bytes - cfix - assoc_fixed_bytes(Wc)) / assoc_peak_bytes(Wc) : 0;
         const bool use_c = cap_c > 0 && n_c <= cap_c && 4 * n_c <= 3 * n_alive && pb_c >= 1;
         const int Wp = use_c ? Wc : W;
-        const int nb = use_c ? min(pb_c, npk - p0) : min(pb_full, npk - p0);
+        const int nb = use_c ? min(pb_c, npk - p0) : min(p0 == 0 ? nb0 : pb_full, npk - p0);
         unsigned char *const base = uni + (use_c ? cfix : 0);
         unsigned long long *const iclp = reinterpret_cast<unsigned long long *>(base);
         int *const owner = reinterpret_cast<int *>(iclp + Wp);
