@@ -6,7 +6,7 @@
  * returns them as track candidates with their hit lists. Per event it runs
  * the find-and-remove loop: fill the theta x rho vote histogram from the hits
  * still in the pool (Sec. 5: every hit votes in every theta bin), search
- * peaks (Sec. 4 and 5: the most populated bin is the most probable line; with
+ * peaks (Sec. 4 and 5: a line sits where the histogram count is largest; with
  * pileup, every local maximum of a (2w+1)^2 window, or the single maximum),
  * associate the hits that lie on each peak's line (Sec. 5, seed finding),
  * remove them, and repeat until no bin reaches the vote threshold (the

@@ -13,7 +13,7 @@
  *     one vote into the rho bin it lands in, filling a 2-D histogram over
  *     theta in [0, pi) and rho in [rho_min, rho_max) (Sec. 5 uses 180 x 1000
  *     bins over 0..180 degrees and -500..500);
- *   - the most populated bin is the most probable line (Sec. 4, Sec. 5);
+ *   - a line is read off where the histogram count is largest (Sec. 4, Sec. 5);
  *     with several tracks per event the peak search keeps either the single
  *     global maximum (argmax mode) or every local maximum of a (2w+1)^2
  *     window (nms mode);
